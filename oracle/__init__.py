@@ -1,0 +1,289 @@
+"""FP64 CPU oracle for Fastron with the forward-kinematics kernel.
+
+TEST INFRASTRUCTURE ONLY. Only the test suite, ``__graft_entry__.smoke()`` and
+the CPU-baseline leg of ``bench.py`` may import this package. It shares no code
+with the GPU library (``paper_1910_06451_amd``) and never imports it; the GPU
+library never imports this package.
+
+The arithmetic lives in ``fastron_oracle.c`` (plain C, IEEE double) and in
+``mlp_oracle.py`` (NumPy float64). This module only marshals NumPy arrays into
+that C code. Float32 inputs are upcast to float64 exactly, so the oracle and
+the GPU path see identical input values.
+
+Functions and the passages they follow (Das & Yip, "Forward Kinematics Kernel
+for Improved Proxy Collision Checking"):
+
+* ``dh_link``          -- Section II-A, Eq. 1 (D-H link transform)
+* ``frames``           -- Section II-A, chain product of link transforms
+* ``control_points``   -- Section II-A, Eq. 2 (FK_m(x) = pos(wA_{j_m} T_m))
+* ``k_rq``             -- Section II-B, Eq. 3 (second-order rational quadratic)
+* ``k_fk``, ``gram``   -- Section III-A, Eq. 4 (FK kernel) and the kernel matrix
+* ``score``            -- Section III-B, model f(x) = sum_i K(S_i, x) alpha_i
+* ``fastron_update``   -- Section III-B, Eq. 5-9 and Algorithm 1
+* ``loss``             -- Section III-B, Eq. 5
+* ``capsule_box_labels`` -- geometric labeller standing in for the checker used
+  in Section IV (not part of the paper's method)
+* ``metrics``          -- Section IV-A, Eq. 10-12 (accuracy, TPR, TNR)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "fastron_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+
+_lib = None
+
+MAX_JOINTS = 64
+MAX_POINTS = 64
+
+
+def build() -> str:
+    """Compile the C oracle with gcc (plain -O2, OpenMP across queries)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        build()
+    lib = ctypes.CDLL(_LIB_PATH)
+    dp = ctypes.POINTER(ctypes.c_double)
+    ip = ctypes.POINTER(ctypes.c_int)
+    lp = ctypes.POINTER(ctypes.c_int64)
+    i64 = ctypes.c_int64
+    lib.oracle_dh_link.argtypes = [ctypes.c_double] * 4 + [dp]
+    lib.oracle_frames.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+    lib.oracle_control_points_batch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, dp, i64, dp, dp]
+    lib.oracle_k_rq.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double]
+    lib.oracle_k_rq.restype = ctypes.c_double
+    lib.oracle_k_fk.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double]
+    lib.oracle_k_fk.restype = ctypes.c_double
+    lib.oracle_gram.argtypes = [i64, ctypes.c_int, dp, ctypes.c_double, dp]
+    lib.oracle_gram_summand.argtypes = [i64, ctypes.c_int, dp, ctypes.c_double, ctypes.c_int, dp]
+    lib.oracle_score_points.argtypes = [ctypes.c_int, i64, dp, dp, ctypes.c_double, i64, dp, dp]
+    lib.oracle_score.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, dp, i64, dp, dp, ctypes.c_double,
+                                 i64, dp, dp]
+    lib.oracle_loss.argtypes = [i64, ctypes.c_int, dp, ip, ctypes.c_double, ctypes.c_double, dp]
+    lib.oracle_loss.restype = ctypes.c_double
+    lib.oracle_fastron_update.argtypes = [i64, ctypes.c_int, dp, ip, ctypes.c_double, ctypes.c_double, i64, i64,
+                                          dp, dp, lp, lp, lp, i64, ip, lp, dp]
+    lib.oracle_fastron_update.restype = ctypes.c_int
+    lib.oracle_segment_box_dist2.argtypes = [dp, dp, dp, dp]
+    lib.oracle_segment_box_dist2.restype = ctypes.c_double
+    lib.oracle_capsule_box_labels.argtypes = [ctypes.c_int, dp, dp, i64, dp, ctypes.c_double, ctypes.c_int, dp, ip,
+                                              dp]
+    _lib = lib
+    return lib
+
+
+def _d(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+def _ptr(a, ct=ctypes.c_double):
+    if a is None:
+        return None
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+# --------------------------------------------------------------------------- #
+# Chain description shared by all oracle calls
+# --------------------------------------------------------------------------- #
+def dh_table(a, alpha, d, theta=None, joint_type=None) -> np.ndarray:
+    """Pack a D-H chain as rows (a, alpha, d, theta, type); type 0 revolute, 1 prismatic."""
+    a = np.asarray(a, dtype=np.float64)
+    n = a.shape[0]
+    theta = np.zeros(n) if theta is None else np.asarray(theta, dtype=np.float64)
+    joint_type = np.zeros(n) if joint_type is None else np.asarray(joint_type, dtype=np.float64)
+    return np.ascontiguousarray(np.stack([a, np.asarray(alpha, np.float64), np.asarray(d, np.float64),
+                                          theta, joint_type], axis=1))
+
+
+def _check_chain(dh, M=None, frame=None):
+    dh = _d(dh)
+    n = dh.shape[0]
+    if dh.ndim != 2 or dh.shape[1] != 5 or not (1 <= n <= MAX_JOINTS):
+        raise ValueError("dh must be n x 5 with 1 <= n <= 64")
+    if frame is not None:
+        frame = np.ascontiguousarray(np.asarray(frame, dtype=np.int32))
+        if frame.ndim != 1 or not (1 <= frame.shape[0] <= MAX_POINTS):
+            raise ValueError("frame must list 1..64 control points")
+        if frame.min() < 0 or frame.max() > n:
+            raise ValueError("control-point frame index out of range [0, n]")
+    return dh, n, frame
+
+
+def dh_link(theta, alpha, a, d) -> np.ndarray:
+    A = np.zeros(16)
+    _load().oracle_dh_link(float(theta), float(alpha), float(a), float(d), _ptr(A))
+    return A.reshape(4, 4)
+
+
+def frames(dh, q, base=None) -> np.ndarray:
+    dh, n, _ = _check_chain(dh)
+    q = _d(q)
+    T = np.zeros((n + 1) * 16)
+    _load().oracle_frames(n, _ptr(dh), _ptr(_d(base)) if base is not None else None, _ptr(q), _ptr(T))
+    return T.reshape(n + 1, 4, 4)
+
+
+def control_points(dh, frame, q, offset=None, base=None) -> np.ndarray:
+    """FK_m for every configuration: q is (N, n) -> (N, M, 3) float64."""
+    dh, n, frame = _check_chain(dh, frame=frame)
+    q = _d(q)
+    single = q.ndim == 1
+    q = q.reshape(-1, n)
+    N, M = q.shape[0], frame.shape[0]
+    P = np.zeros((N, M, 3))
+    off = _d(offset).reshape(M, 3) if offset is not None else None
+    _load().oracle_control_points_batch(n, _ptr(dh), _ptr(_d(base)) if base is not None else None, M,
+                                        _ptr(frame, ctypes.c_int), _ptr(off), N, _ptr(np.ascontiguousarray(q)),
+                                        _ptr(P))
+    return P[0] if single else P
+
+
+def k_rq(x, xp, gamma) -> float:
+    x, xp = _d(x), _d(xp)
+    return float(_load().oracle_k_rq(_ptr(x), _ptr(xp), x.shape[0], float(gamma)))
+
+
+def k_fk(Px, Pxp, gamma) -> float:
+    Px, Pxp = _d(Px), _d(Pxp)
+    return float(_load().oracle_k_fk(Px.shape[0], _ptr(Px), _ptr(Pxp), float(gamma)))
+
+
+def gram(P, gamma) -> np.ndarray:
+    P = _d(P)
+    N, M = P.shape[0], P.shape[1]
+    K = np.zeros((N, N))
+    _load().oracle_gram(N, M, _ptr(P), float(gamma), _ptr(K))
+    return K
+
+
+def gram_summand(P, gamma, m) -> np.ndarray:
+    P = _d(P)
+    N, M = P.shape[0], P.shape[1]
+    K = np.zeros((N, N))
+    _load().oracle_gram_summand(N, M, _ptr(P), float(gamma), int(m), _ptr(K))
+    return K
+
+
+def score_points(Ps, alpha, gamma, Pq) -> np.ndarray:
+    Ps, Pq, alpha = _d(Ps), _d(Pq), _d(alpha)
+    S, M = Ps.shape[0], Ps.shape[1]
+    N = Pq.shape[0]
+    f = np.zeros(N)
+    _load().oracle_score_points(M, S, _ptr(Ps), _ptr(alpha), float(gamma), N, _ptr(Pq), _ptr(f))
+    return f
+
+
+def score(dh, frame, support_q, alpha, gamma, q, offset=None, base=None) -> np.ndarray:
+    """f(q) = sum_s alpha_s K_FK(S_s, q) from joint configurations (FK included)."""
+    dh, n, frame = _check_chain(dh, frame=frame)
+    sq = _d(support_q).reshape(-1, n)
+    q = _d(q).reshape(-1, n)
+    alpha = _d(alpha)
+    M = frame.shape[0]
+    f = np.zeros(q.shape[0])
+    off = _d(offset).reshape(M, 3) if offset is not None else None
+    _load().oracle_score(n, _ptr(dh), _ptr(_d(base)) if base is not None else None, M, _ptr(frame, ctypes.c_int),
+                         _ptr(off), sq.shape[0], _ptr(sq), _ptr(alpha), float(gamma), q.shape[0], _ptr(q), _ptr(f))
+    return f
+
+
+def predict(f) -> np.ndarray:
+    """Sign of the model: +1 (C_obs) for f > 0, -1 (C_free) for f < 0; f == 0 reads as +1."""
+    f = np.asarray(f)
+    return np.where(f < 0, -1, 1).astype(np.int8)
+
+
+def loss(P, y, gamma, beta, alpha) -> float:
+    P = _d(P)
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    alpha = _d(alpha)
+    return float(_load().oracle_loss(P.shape[0], P.shape[1], _ptr(P), _ptr(y, ctypes.c_int), float(gamma),
+                                     float(beta), _ptr(alpha)))
+
+
+ACT_ADD = 1
+ACT_REMOVE = 2
+
+
+def fastron_update(P, y, gamma, beta=1.0, iter_max=None, s_max=None, alpha=None, F=None, trace=False):
+    """Algorithm 1 on the control points P (N, M, 3) and labels y (+1 / -1).
+
+    Returns a dict with alpha, F (N,), support (ascending indices), converged,
+    updates and, with ``trace=True``, per-update (action, index, dalpha).
+    """
+    P = _d(P)
+    N, M = P.shape[0], P.shape[1]
+    y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
+    if iter_max is None:
+        iter_max = 20 * max(N, 1)
+    if s_max is None:
+        s_max = max(N, 1)
+    alpha = np.zeros(N) if alpha is None else _d(alpha).copy()
+    F = np.zeros(N) if F is None else _d(F).copy()
+    support = np.zeros(max(N, 1), dtype=np.int64)
+    ns = ctypes.c_int64(0)
+    upd = ctypes.c_int64(0)
+    cap = int(iter_max) if trace else 0
+    cap = min(cap, 10_000_000)
+    t_act = np.zeros(max(cap, 1), dtype=np.int32)
+    t_idx = np.zeros(max(cap, 1), dtype=np.int64)
+    t_da = np.zeros(max(cap, 1))
+    rc = _load().oracle_fastron_update(N, M, _ptr(P), _ptr(y, ctypes.c_int), float(gamma), float(beta),
+                                       int(iter_max), int(s_max), _ptr(alpha), _ptr(F),
+                                       ctypes.byref(upd), _ptr(support, ctypes.c_int64), ctypes.byref(ns), cap,
+                                       _ptr(t_act, ctypes.c_int), _ptr(t_idx, ctypes.c_int64), _ptr(t_da))
+    out = dict(alpha=alpha, F=F, support=support[: ns.value].copy(), converged=(rc == 0), updates=upd.value)
+    if trace:
+        k = min(upd.value, cap)
+        out["trace_action"] = t_act[:k].copy()
+        out["trace_index"] = t_idx[:k].copy()
+        out["trace_dalpha"] = t_da[:k].copy()
+    return out
+
+
+def segment_box_dist2(A, B, lo, hi) -> float:
+    A, B, lo, hi = _d(A), _d(B), _d(lo), _d(hi)
+    return float(_load().oracle_segment_box_dist2(_ptr(A), _ptr(B), _ptr(lo), _ptr(hi)))
+
+
+def capsule_box_labels(dh, q, radius, boxes_lo, boxes_hi, base=None):
+    """Geometric labels (+1 collision, -1 free) and clearance (min distance - r)."""
+    dh, n, _ = _check_chain(dh)
+    q = _d(q).reshape(-1, n)
+    lo = _d(boxes_lo).reshape(-1, 3)
+    hi = _d(boxes_hi).reshape(-1, 3)
+    boxes = np.ascontiguousarray(np.concatenate([lo, hi], axis=1))
+    N = q.shape[0]
+    lab = np.zeros(N, dtype=np.int32)
+    clr = np.zeros(N)
+    _load().oracle_capsule_box_labels(n, _ptr(dh), _ptr(_d(base)) if base is not None else None, N, _ptr(q),
+                                      float(radius), boxes.shape[0], _ptr(boxes), _ptr(lab, ctypes.c_int), _ptr(clr))
+    return lab.astype(np.int8), clr
+
+
+def metrics(pred, truth) -> dict:
+    """Section IV-A, Eq. 10-12 with +1 (C_obs) as the positive class."""
+    pred = np.asarray(pred)
+    truth = np.asarray(truth)
+    tp = int(np.sum((pred == 1) & (truth == 1)))
+    tn = int(np.sum((pred == -1) & (truth == -1)))
+    fp = int(np.sum((pred == 1) & (truth == -1)))
+    fn = int(np.sum((pred == -1) & (truth == 1)))
+    tot = tp + tn + fp + fn
+    return dict(accuracy=(tp + tn) / tot if tot else float("nan"),
+                tpr=tp / (tp + fn) if (tp + fn) else float("nan"),
+                tnr=tn / (tn + fp) if (tn + fp) else float("nan"), tp=tp, tn=tn, fp=fp, fn=fn)
