@@ -1,0 +1,209 @@
+"""Benchmark: proxy collision checks/s of Fastron with the FK kernel on one MI355X.
+
+Workload (7-DOF D-H arm, M = 8 control points, S = 4,000 support points with
+alpha ~ N(0, 1), N = 1,000,000 query configurations uniform in [-pi, pi]^7,
+gamma = 10). One step = the whole scoring path for one batch: prepare the
+support set (FK of the supports, scaled operands, alpha / M) and score every
+query (FK of the query fused with K_FK against all supports, weighted sum,
+sign). Inputs are resident in device memory before timing starts.
+
+Also reported on the same line: the fused score kernel's roofline position
+(its own average duration from HIP events on the launch stream), the
+precision and VALU forms, a full Algorithm 1 training run on 50,000 labelled
+samples, and the CPU FP64 oracle timed on a bounded sample of the same
+workload (which also gives the sign agreement with FP64).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# Derived ALU ceiling of the fused score, in control-point kernel evaluations
+# per second: each evaluation needs one reciprocal (transcendental, quarter
+# rate: 32 lanes/clk/CU) and one FMA (full rate: 128 lanes/clk/CU) on the
+# vector ALU once the cross term runs on the matrix cores:
+#   256 CU * 2.4e9 Hz / (1/32 + 1/128) = 15.73e12 evaluations/s.
+ALU_PEAK_CP_PER_S = 256 * 2.4e9 / (1.0 / 32 + 1.0 / 128)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--S", type=int, default=4000)
+    ap.add_argument("--N", type=int, default=1_000_000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_1910_06451_amd import api, workloads as wl
+
+    dev = torch.device("cuda:0")
+    arm = wl.arm_7dof()
+    gamma, S, N = 10.0, args.S, args.N
+    sq_np, al_np = wl.model("bench7", S, arm.n)
+    q_np = wl.configs("bench7/q", N, arm.n)
+    sq, al, q = (torch.from_numpy(x).to(dev) for x in (sq_np, al_np, q_np))
+    f = torch.empty(N, dtype=torch.float32, device=dev)
+    lab = torch.empty(N, dtype=torch.int8, device=dev)
+    Mm = int(np.sum(arm.frames > 0))  # control points that move; base-frame points are folded exactly
+
+    def step():
+        api.fk_score(arm, sq, al, gamma, q, out=(f, lab))
+
+    log(f"[bench] warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1e3 / args.steps
+    checks_per_s = N / (ms * 1e-3)
+
+    # dominant kernel alone: score against a prepared model, timed with events on the launch stream
+    model = api.support_prep(arm, sq, al, gamma)
+    stream = torch.cuda.current_stream()
+
+    def kernel_ms(flags, reps):
+        for _ in range(2):
+            api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    k_ms = kernel_ms(api.SCORE_FP32, args.steps)
+    cp_per_launch = N * S * Mm
+    achieved = cp_per_launch / (k_ms * 1e-3)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_CP_PER_S / 1e12,
+                "unit": "Tcp-eval/s", "frac": achieved / ALU_PEAK_CP_PER_S, "traffic": None,
+                "kernel": f"k_score_mfma<{Mm},double>", "kernel_ms": k_ms, "cp_evals_per_launch": cp_per_launch}
+    f_gpu = f.clone()
+    lab_gpu = lab.cpu().numpy()
+    f_np = f_gpu.cpu().numpy()
+
+    extras = {}
+    if not args.no_extras:
+        forms = {}
+        for name, flags in (("valu", api.SCORE_VALU), ("bf16_plain", api.SCORE_BF16 | api.BF16_PLAIN),
+                            ("bf16_split3", api.SCORE_BF16 | api.BF16_SPLIT3)):
+            log(f"[bench] form {name}")
+            t = kernel_ms(flags, max(3, args.steps // 4))
+            forms[name] = {"kernel_ms": t, "checks_per_s": N / (t * 1e-3), "vs_fp32": k_ms / t,
+                           "labels": lab.cpu().numpy()}
+        extras["forms"] = forms
+        log("[bench] training run on 50,000 labelled samples")
+        extras["train"] = train_run(api, wl, arm, gamma, dev)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] cpu baseline (FP64 oracle)")
+        cpu, agree = cpu_baseline(arm, sq_np, al_np, q_np, gamma, f_np, lab_gpu, args.cpu_seconds, extras)
+    else:
+        agree = {}
+
+    out = {
+        "metric": "proxy collision checks/s (7-DOF, fused FK + FK-kernel score + sign)",
+        "value": checks_per_s,
+        "unit": "checks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded D-H arm, uniform configurations, alpha ~ N(0,1))",
+        "config": {"workload": "7-DOF arm, M=8 control points, S=4000 supports, N=1,000,000 queries, gamma=10",
+                   "S": S, "N": N, "M": int(arm.M), "M_moving": Mm, "gamma": gamma},
+        "kernel_evals_per_s": N * S / (ms * 1e-3),
+        "cp_evals_per_s": N * S * Mm / (ms * 1e-3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    out.update(agree)
+    if extras:
+        for v in extras.get("forms", {}).values():
+            v.pop("labels", None)
+        out["extras"] = extras
+    print(json.dumps(out), flush=True)
+
+
+def train_run(api, wl, arm, gamma, dev):
+    """Label 50,000 configurations with the device labeller (20 cubes), FK them, run Algorithm 1."""
+    import torch
+
+    N = 50_000
+    q = torch.from_numpy(wl.configs("bench7/train", N, arm.n)).to(dev)
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    y, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    P = api.fk_points(arm, q)
+    out = api.train(P, y, gamma)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"N": N, "label_ms": (t1 - t0) * 1e3, "train_ms": (t2 - t1) * 1e3, "updates": out["updates"],
+            "support": int(out["support"].numel()), "converged": bool(out["converged"]),
+            "us_per_update": (t2 - t1) * 1e6 / max(out["updates"], 1),
+            "collision_rate": float((y == 1).float().mean().item())}
+
+
+def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras):
+    """FP64 oracle on a bounded, evenly spaced sample of the queries (all host threads)."""
+    import oracle
+
+    dh = oracle.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
+    sq64, al64 = sq.astype(np.float64), al.astype(np.float64)
+    probe = np.linspace(0, q.shape[0] - 1, 256).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.score(dh, arm.frames, sq64, al64, gamma, q[probe].astype(np.float64))
+    rate = probe.shape[0] / (time.perf_counter() - t0)
+    n = int(min(q.shape[0], max(1024, rate * seconds)))
+    idx = np.linspace(0, q.shape[0] - 1, n).astype(np.int64)
+    t0 = time.perf_counter()
+    ref = oracle.score(dh, arm.frames, sq64, al64, gamma, q[idx].astype(np.float64))
+    dt = time.perf_counter() - t0
+    sign_ref = np.where(ref < 0, -1, 1)
+    agree = {"sign_agreement_vs_fp64": float(np.mean(lab_gpu[idx] == sign_ref)),
+             "max_abs_df_vs_fp64": float(np.max(np.abs(f_gpu[idx] - ref))),
+             "fp64_sample": int(n)}
+    for name, form in extras.get("forms", {}).items():
+        form["sign_agreement_vs_fp64"] = float(np.mean(form["labels"][idx] == sign_ref))
+    cpu = {"value": n / dt, "unit": "checks/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "sample": f"{n} evenly spaced queries of the same workload (S={sq.shape[0]}), {dt:.1f} s"}
+    return cpu, agree
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * fastron_fk.h -- C ABI of the gfx950 (MI355X) Fastron-FK library.
+ *
+ * Fastron with the forward-kinematics (FK) kernel, after Das & Yip,
+ * "Forward Kinematics Kernel for Improved Proxy Collision Checking":
+ *   - forward kinematics of a standard D-H chain into control points
+ *     (Section II-A, Eq. 1 and Eq. 2);
+ *   - the FK kernel K_FK(x, x') = (1/M) sum_m K_RQ(FK_m(x), FK_m(x')) built on
+ *     the second-order rational quadratic kernel
+ *     K_RQ(p, p') = (1 + gamma/2 ||p - p'||^2)^-2 (Section II-B Eq. 3,
+ *     Section III-A Eq. 4);
+ *   - the Fastron model f(x) = sum_i alpha_i K_FK(S_i, x) and its sign
+ *     (Section III-B): f > 0 predicts "in collision" (+1), f < 0 "free" (-1);
+ *     f == 0 is reported as +1;
+ *   - Gram-column updates and the Fastron model update, Algorithm 1
+ *     (Section III-B, Eq. 5-9).
+ *
+ * Conventions shared by every entry point
+ *   - Array arguments are DEVICE pointers (memory of the current HIP device)
+ *     owned by the caller, contiguous, row-major, of the element type named
+ *     in the prototype. Structs and the arrays they point to are HOST memory,
+ *     read only during the call. The library never frees caller memory.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream). All
+ *     work is enqueued on it asynchronously unless an entry point says it
+ *     synchronises.
+ *   - Arguments are validated before any HIP call. Errors come back as a
+ *     negative fastron_status; fastron_last_error() then returns a message
+ *     (thread-local, valid until the next call on the same thread). Nothing
+ *     aborts or throws across the ABI.
+ *   - Limits: 1 <= n <= 16 joints, 1 <= M <= 16 control points.
+ */
+#ifndef FASTRON_FK_H
+#define FASTRON_FK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FASTRON_OK = 0,
+  FASTRON_NOT_CONVERGED = 1,  /* Algorithm 1 hit iter_max; outputs are a valid partial model */
+  FASTRON_EINVAL = -1,        /* invalid argument (nothing was launched) */
+  FASTRON_EUNSUPPORTED = -2,  /* valid but unsupported request (e.g. no gfx950 device) */
+  FASTRON_EHIP = -3,          /* a HIP runtime call failed; see fastron_last_error() */
+  FASTRON_ENOMEM = -4,        /* a device allocation failed */
+  FASTRON_EDEVICE = -5        /* a device-side safety limit fired (e.g. a grid barrier timed out) */
+} fastron_status;
+
+#define FASTRON_MAX_JOINTS 16
+#define FASTRON_MAX_POINTS 16
+
+/* Standard D-H chain (Section II-A, Eq. 1). Joint i (0-based) has link length
+ * a[i] (translation along the new x axis), twist alpha[i], offset d[i]
+ * (translation along the previous z axis) and angle offset theta[i]. A
+ * revolute joint adds its variable to theta, a prismatic joint adds it to d.
+ * wA_0 = base (row-major 4x4, last row 0 0 0 1) or the identity.           */
+typedef struct {
+  int32_t n;
+  const double* a;       /* [n] */
+  const double* alpha;   /* [n] */
+  const double* d;       /* [n] */
+  const double* theta;   /* [n] or NULL = zeros */
+  const int32_t* type;   /* [n] 0 revolute, 1 prismatic; NULL = all revolute */
+  const double* base;    /* [16] or NULL = identity */
+} fastron_chain;
+
+/* Control points (Section II-A, Eq. 2): point m sits at pos(wA_{frame[m]} T_m)
+ * where T_m translates by offset[3m..3m+2] in frame frame[m]; frame 0 is the
+ * base frame, frame n the end of the chain. Section III-A places points at
+ * frame origins (offset NULL).                                              */
+typedef struct {
+  int32_t M;
+  const int32_t* frame;  /* [M], each in [0, n] */
+  const double* offset;  /* [M*3] or NULL = frame origins */
+} fastron_cpoints;
+
+/* ---- a1: batched forward kinematics (Section II-A, Eq. 1-2) --------------
+ * q [N][n] float joint values -> P [N][M][3] float control-point positions.
+ * One thread per configuration; the chain product runs in FP64 when n >= 7,
+ * FP32 otherwise. N == 0 is a no-op.                                        */
+fastron_status fastron_fk_points(const fastron_chain* chain, const fastron_cpoints* cp, const float* q,
+                                 int64_t N, float* P, void* stream);
+
+/* ---- a2: prepared support set --------------------------------------------
+ * The support set of a Fastron model (Section III-B: configurations S_i with
+ * weights alpha_i) converted once into the operand layout the scoring kernels
+ * stream: per-point scaled control points, their squared norms and alpha/M.
+ * `data` is caller-owned device memory of at least fastron_model_bytes(S, M)
+ * bytes, 256-byte aligned; its contents are private to the library.         */
+typedef struct {
+  int64_t S;        /* support-set size (0 allowed: f == 0 everywhere) */
+  int32_t M;        /* control points per configuration */
+  float gamma;      /* kernel width, gamma > 0 (Eq. 3) */
+  void* data;       /* device blob */
+  int64_t bytes;    /* capacity of data in bytes */
+} fastron_model;
+
+int64_t fastron_model_bytes(int64_t S, int32_t M);
+
+fastron_status fastron_support_prep(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,
+                                    const float* alpha, int64_t S, float gamma, fastron_model* model, void* stream);
+
+/* ---- a3/a6: fused FK-kernel score and sign (Section III-B) --------------
+ * f[j] = sum_i alpha_i K_FK(S_i, q_j) with the FK of q_j computed in the same
+ * kernel; label[j] = +1 if f[j] >= 0 else -1. f and/or label may be NULL
+ * (not both). flags select the arithmetic of the cross term:
+ *   FASTRON_SCORE_FP32  FP32 MFMA cross term (default)
+ *   FASTRON_SCORE_BF16  BF16 MFMA cross term, FP32 norms and accumulation
+ *   FASTRON_SCORE_VALU  FP32 cross term on the vector ALU (no MFMA)         */
+#define FASTRON_SCORE_FP32 0u
+#define FASTRON_SCORE_BF16 1u
+#define FASTRON_SCORE_VALU 2u
+/* BF16 precision variants (OR into FASTRON_SCORE_BF16): the cross term uses
+ * 1, 3 or 6 bf16 products per coordinate (hi.hi; + hi.mid + mid.hi;
+ * + hi.lo + lo.hi + mid.mid), splitting each coordinate into bf16 parts.  */
+#define FASTRON_BF16_PLAIN 0x00u
+#define FASTRON_BF16_SPLIT2 0x10u
+#define FASTRON_BF16_SPLIT3 0x20u
+
+fastron_status fastron_fk_score_prepared(const fastron_chain* chain, const fastron_cpoints* cp,
+                                         const fastron_model* model, const float* q, int64_t N, float* f,
+                                         int8_t* label, uint32_t flags, void* stream);
+
+/* Convenience form: prepares the support set (a2) into stream-ordered scratch
+ * memory and scores (a3) in one call.                                       */
+fastron_status fastron_fk_score(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,
+                                const float* alpha, int64_t S, float gamma, const float* q, int64_t N, float* f,
+                                int8_t* label, uint32_t flags, void* stream);
+
+/* ---- a4: Gram column and F update (Section III-B, Eq. 8; Algorithm 1) ----
+ * kcol[j] = K_FK(X_j, X_i) for all j, and F[j] += delta_alpha * kcol[j].
+ * P [N][M][3] are the control points of the training set (fastron_fk_points
+ * output). F (in/out) and kcol (out) may each be NULL (not both).           */
+fastron_status fastron_gram_update(const float* P, int64_t N, int32_t M, float gamma, int64_t i, float delta_alpha,
+                                   float* F, float* kcol, void* stream);
+
+/* ---- a5: Fastron model update, Algorithm 1 (Section III-B) --------------
+ * Runs Algorithm 1 on the device: greedy add/adjust of the most negative
+ * margin y_i F_i (lowest index on ties), removal of redundant support points
+ * (largest y_i (F_i - alpha_i) over alpha_i != 0, lowest index on ties),
+ * caps iter_max and s_max, then removeNonsupportPoints.
+ *   P [N][M][3] float   control points of the training set
+ *   y [N] int8          +1 in collision, -1 free
+ *   alpha, F [N]        in/out; zeros = fresh model, else a previous model
+ *                       (loadPreviousModel: F must equal K alpha)
+ *   support_idx [N]     out: ascending indices with alpha != 0
+ *   n_support, updates  HOST out: |S| and the number of add/remove updates
+ * beta >= 1 is the conditional bias (Eq. 5). The call synchronises `stream`.
+ * Returns FASTRON_OK when the loop ended by break, FASTRON_NOT_CONVERGED when
+ * iter_max updates were made first. fastron_train_f64 keeps alpha and F in
+ * double and evaluates the kernel in FP64 (reference-precision mode).
+ * trace_action / trace_index (device int32 [trace_cap], may be NULL) record
+ * the first trace_cap updates: action 1 = add, 2 = remove.                  */
+fastron_status fastron_train(const float* P, const int8_t* y, int64_t N, int32_t M, float gamma, float beta,
+                             int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
+                             int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
+                             int64_t trace_cap, void* stream);
+fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma, double beta,
+                                 int64_t iter_max, int64_t s_max, double* alpha, double* F, int32_t* support_idx,
+                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
+                                 int64_t trace_cap, void* stream);
+
+/* ---- a9: geometric labels -------------------------------------------------
+ * Stands in for the ground-truth collision checker of Section IV: link i is a
+ * capsule of radius `radius` around the segment between the origins of
+ * frames i-1 and i; obstacles are axis-aligned boxes, a DEVICE array of nbox
+ * rows (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z) in double, 0 <= nbox <= 4096.
+ * label[j] = +1 if some capsule touches some box (exact segment-box distance
+ * <= radius), else -1. clearance[j] (may be NULL) = min distance - radius.
+ * Computed in FP64.                                                         */
+fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float* q, int64_t N, double radius,
+                                         const double* boxes, int32_t nbox, int8_t* label, float* clearance,
+                                         void* stream);
+
+/* ---- tuning ----------------------------------------------------------------
+ * Process-wide launch parameters (host side):
+ *   "train.blocks"  workgroups of the persistent training grid, 0 = automatic
+ *   "train.threads" threads per training workgroup: 256, 512 or 1024
+ * fastron_tune_get returns -1 for an unknown key.                         */
+fastron_status fastron_tune_set(const char* key, int64_t value);
+int64_t fastron_tune_get(const char* key);
+
+/* Last error message of the calling thread ("" after success). */
+const char* fastron_last_error(void);
+
+/* Library version string. */
+const char* fastron_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FASTRON_FK_H */

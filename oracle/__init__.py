@@ -82,8 +82,14 @@ def _load():
     lib.oracle_segment_box_dist2.restype = ctypes.c_double
     lib.oracle_capsule_box_labels.argtypes = [ctypes.c_int, dp, dp, i64, dp, ctypes.c_double, ctypes.c_int, dp, ip,
                                               dp]
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())
 
 
 def _d(a) -> np.ndarray:

@@ -25,6 +25,9 @@
  *                                                of Section IV; not part of the paper)
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -393,4 +396,13 @@ void oracle_capsule_box_labels(int n, const double* dh, const double* base, int6
     label[j] = (best <= 0.0) ? 1 : -1;
     if (clearance) clearance[j] = best;
   }
+}
+
+/* Threads the oracle's OpenMP loops use (1 without OpenMP). */
+int oracle_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
 }

@@ -1,0 +1,196 @@
+"""Torch-facing wrappers with the same names as the C ABI entry points.
+
+Each function checks dtype / device / contiguity, passes raw pointers and the
+current HIP stream to the library, and returns torch tensors. No arithmetic
+of the method happens here.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+import torch
+
+from . import _native as nat
+from ._native import HostChain, check
+
+__all__ = [
+    "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train",
+    "label_capsule_box", "PreparedModel", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
+    "BF16_SPLIT3",
+]
+
+SCORE_FP32, SCORE_BF16, SCORE_VALU = nat.SCORE_FP32, nat.SCORE_BF16, nat.SCORE_VALU
+BF16_PLAIN, BF16_SPLIT2, BF16_SPLIT3 = nat.BF16_PLAIN, nat.BF16_SPLIT2, nat.BF16_SPLIT3
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a device tensor, got {t.device}")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(0 if t is None else t.data_ptr())
+
+
+def _chain(arm):
+    return arm if isinstance(arm, HostChain) else HostChain(arm)
+
+
+def fk_points(arm, q: torch.Tensor) -> torch.Tensor:
+    """Control points FK_m(q) for every configuration: (N, n) float32 -> (N, M, 3) float32."""
+    hc = _chain(arm)
+    _dev(q, torch.float32, "q")
+    if q.dim() != 2 or q.shape[1] != hc.n:
+        raise ValueError(f"q must be (N, {hc.n})")
+    P = torch.empty((q.shape[0], hc.M, 3), dtype=torch.float32, device=q.device)
+    check(nat.lib().fastron_fk_points(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), _ptr(q), q.shape[0],
+                                      _ptr(P), _stream()))
+    return P
+
+
+def model_bytes(S: int, M: int) -> int:
+    return int(nat.lib().fastron_model_bytes(int(S), int(M)))
+
+
+class PreparedModel:
+    """A support set prepared for scoring (device blob + descriptor)."""
+
+    def __init__(self, S, M, gamma, device):
+        self.nbytes = model_bytes(S, M)
+        self.buf = torch.empty(self.nbytes + 256, dtype=torch.uint8, device=device)
+        base = self.buf.data_ptr()
+        aligned = (base + 255) & ~255
+        self.desc = nat.Model(int(S), int(M), float(gamma), ctypes.c_void_p(aligned), self.nbytes)
+        self.S, self.M, self.gamma = int(S), int(M), float(gamma)
+
+
+def support_prep(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float) -> PreparedModel:
+    hc = _chain(arm)
+    _dev(support_q, torch.float32, "support_q")
+    _dev(alpha, torch.float32, "alpha")
+    S = support_q.shape[0]
+    if support_q.dim() != 2 or support_q.shape[1] != hc.n or alpha.shape != (S,):
+        raise ValueError("support_q must be (S, n) and alpha (S,)")
+    model = PreparedModel(S, hc.M, gamma, support_q.device)
+    check(nat.lib().fastron_support_prep(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), _ptr(support_q),
+                                         _ptr(alpha), S, float(gamma), ctypes.byref(model.desc), _stream()))
+    model._keep = (support_q, alpha)
+    return model
+
+
+def _score_outputs(N, device, want_f, want_label):
+    f = torch.empty(N, dtype=torch.float32, device=device) if want_f else None
+    lab = torch.empty(N, dtype=torch.int8, device=device) if want_label else None
+    return f, lab
+
+
+def fk_score_prepared(arm, model: PreparedModel, q: torch.Tensor, flags: int = SCORE_FP32, want_f=True,
+                      want_label=True, out=None):
+    """f(q) and sign labels against a prepared model. Returns (f, label); either may be None."""
+    hc = _chain(arm)
+    _dev(q, torch.float32, "q")
+    if q.dim() != 2 or q.shape[1] != hc.n:
+        raise ValueError(f"q must be (N, {hc.n})")
+    f, lab = out if out is not None else _score_outputs(q.shape[0], q.device, want_f, want_label)
+    check(nat.lib().fastron_fk_score_prepared(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints),
+                                              ctypes.byref(model.desc), _ptr(q), q.shape[0], _ptr(f), _ptr(lab),
+                                              int(flags), _stream()))
+    return f, lab
+
+
+def fk_score(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, q: torch.Tensor,
+             flags: int = SCORE_FP32, want_f=True, want_label=True, out=None):
+    """One call: prepare the support set and score the queries. Returns (f, label)."""
+    hc = _chain(arm)
+    _dev(support_q, torch.float32, "support_q")
+    _dev(alpha, torch.float32, "alpha")
+    _dev(q, torch.float32, "q")
+    S = support_q.shape[0]
+    if support_q.dim() != 2 or support_q.shape[1] != hc.n or alpha.shape != (S,):
+        raise ValueError("support_q must be (S, n) and alpha (S,)")
+    if q.dim() != 2 or q.shape[1] != hc.n:
+        raise ValueError(f"q must be (N, {hc.n})")
+    f, lab = out if out is not None else _score_outputs(q.shape[0], q.device, want_f, want_label)
+    check(nat.lib().fastron_fk_score(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), _ptr(support_q),
+                                     _ptr(alpha), S, float(gamma), _ptr(q), q.shape[0], _ptr(f), _ptr(lab),
+                                     int(flags), _stream()))
+    return f, lab
+
+
+def gram_update(P: torch.Tensor, gamma: float, i: int, delta_alpha: float, F: torch.Tensor | None = None,
+                want_kcol=True):
+    """kcol = K_FK(X_j, X_i) over j; F += delta_alpha * kcol (in place). Returns kcol (or None)."""
+    _dev(P, torch.float32, "P")
+    if P.dim() != 3 or P.shape[2] != 3:
+        raise ValueError("P must be (N, M, 3)")
+    N, M = P.shape[0], P.shape[1]
+    if F is not None:
+        _dev(F, torch.float32, "F")
+        if F.shape != (N,):
+            raise ValueError("F must be (N,)")
+    kcol = torch.empty(N, dtype=torch.float32, device=P.device) if want_kcol else None
+    check(nat.lib().fastron_gram_update(_ptr(P), N, M, float(gamma), int(i), float(delta_alpha), _ptr(F),
+                                        _ptr(kcol), _stream()))
+    return kcol
+
+
+def train(P: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, iter_max: int | None = None,
+          s_max: int | None = None, alpha: torch.Tensor | None = None, F: torch.Tensor | None = None,
+          fp64: bool = False, trace_cap: int = 0):
+    """Algorithm 1 on the device. Returns dict(alpha, F, support, converged, updates[, trace])."""
+    _dev(P, torch.float32, "P")
+    _dev(y, torch.int8, "y")
+    N, M = P.shape[0], P.shape[1]
+    if P.dim() != 3 or P.shape[2] != 3 or y.shape != (N,):
+        raise ValueError("P must be (N, M, 3) and y (N,)")
+    dt = torch.float64 if fp64 else torch.float32
+    alpha = torch.zeros(N, dtype=dt, device=P.device) if alpha is None else alpha.clone()
+    F = torch.zeros(N, dtype=dt, device=P.device) if F is None else F.clone()
+    _dev(alpha, dt, "alpha")
+    _dev(F, dt, "F")
+    iter_max = 20 * max(N, 1) if iter_max is None else int(iter_max)
+    s_max = max(N, 1) if s_max is None else int(s_max)
+    support = torch.empty(max(N, 1), dtype=torch.int32, device=P.device)
+    tr_a = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=P.device) if trace_cap else None
+    tr_i = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=P.device) if trace_cap else None
+    ns = ctypes.c_int64(0)
+    upd = ctypes.c_int64(0)
+    fn = nat.lib().fastron_train_f64 if fp64 else nat.lib().fastron_train
+    st = fn(_ptr(P), _ptr(y), N, M, float(gamma), float(beta), iter_max, s_max, _ptr(alpha), _ptr(F),
+            _ptr(support), ctypes.byref(ns), ctypes.byref(upd), _ptr(tr_a), _ptr(tr_i), int(trace_cap), _stream())
+    check(st, allow=(nat.FASTRON_OK, nat.FASTRON_NOT_CONVERGED))
+    out = dict(alpha=alpha, F=F, support=support[: ns.value], converged=(st == nat.FASTRON_OK), updates=upd.value)
+    if trace_cap:
+        k = min(upd.value, trace_cap)
+        out["trace_action"] = tr_a[:k]
+        out["trace_index"] = tr_i[:k]
+    return out
+
+
+def label_capsule_box(arm, q: torch.Tensor, radius: float, boxes_lo, boxes_hi, want_clearance=True):
+    """Geometric labels (+1 collision / -1 free, int8) and clearance (float32, min distance - radius)."""
+    hc = _chain(arm)
+    _dev(q, torch.float32, "q")
+    if q.dim() != 2 or q.shape[1] != hc.n:
+        raise ValueError(f"q must be (N, {hc.n})")
+    lo = np.asarray(boxes_lo, dtype=np.float64).reshape(-1, 3)
+    hi = np.asarray(boxes_hi, dtype=np.float64).reshape(-1, 3)
+    boxes = torch.from_numpy(np.ascontiguousarray(np.concatenate([lo, hi], axis=1))).to(q.device)
+    N = q.shape[0]
+    lab = torch.empty(N, dtype=torch.int8, device=q.device)
+    clr = torch.empty(N, dtype=torch.float32, device=q.device) if want_clearance else None
+    check(nat.lib().fastron_label_capsule_box(ctypes.byref(hc.chain), _ptr(q), N, float(radius), _ptr(boxes),
+                                              boxes.shape[0], _ptr(lab), _ptr(clr), _stream()))
+    return lab, clr

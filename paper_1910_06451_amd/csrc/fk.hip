@@ -1,0 +1,295 @@
+// Forward kinematics (Section II-A, Eq. 1-2), the prepared support set and the
+// library's shared host utilities (errors, argument packing).
+#include <cmath>
+#include <cstring>
+#include <mutex>
+
+#include "fastron_internal.h"
+#include "model_layout.h"
+
+namespace fastron {
+
+// ---------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------
+static thread_local char g_err[512];
+
+void clear_error() { g_err[0] = '\0'; }
+
+fastron_status fail(fastron_status st, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return st;
+}
+
+// ---------------------------------------------------------------------------
+// Chain packing and validation (host only, no HIP calls)
+// ---------------------------------------------------------------------------
+fastron_status pack_chain(const fastron_chain* chain, const fastron_cpoints* cp, ChainArgs* out, bool need_points) {
+  FASTRON_CHECK(chain != nullptr, "chain is NULL");
+  FASTRON_CHECK(chain->n >= 1 && chain->n <= FASTRON_MAX_JOINTS, "chain->n = %d outside [1, %d]", chain->n,
+                FASTRON_MAX_JOINTS);
+  FASTRON_CHECK(chain->a && chain->alpha && chain->d, "chain->a, alpha and d must be non-NULL");
+  std::memset(out, 0, sizeof(*out));
+  const int n = chain->n;
+  out->n = n;
+  for (int i = 0; i < n; ++i) {
+    double a = chain->a[i], al = chain->alpha[i], d = chain->d[i];
+    double th = chain->theta ? chain->theta[i] : 0.0;
+    FASTRON_CHECK(std::isfinite(a) && std::isfinite(al) && std::isfinite(d) && std::isfinite(th),
+                  "non-finite D-H parameter at joint %d", i);
+    int ty = chain->type ? chain->type[i] : 0;
+    FASTRON_CHECK(ty == 0 || ty == 1, "joint %d type %d is neither 0 (revolute) nor 1 (prismatic)", i, ty);
+    out->a[i] = a;
+    out->d[i] = d;
+    out->th[i] = th;
+    out->ca[i] = std::cos(al);
+    out->sa[i] = std::sin(al);
+    if (ty == 1) out->prismatic |= 1u << i;
+  }
+  if (chain->base) {
+    const double* b = chain->base;
+    for (int k = 0; k < 16; ++k) FASTRON_CHECK(std::isfinite(b[k]), "non-finite base transform entry %d", k);
+    FASTRON_CHECK(b[12] == 0.0 && b[13] == 0.0 && b[14] == 0.0 && b[15] == 1.0,
+                  "base transform last row must be (0, 0, 0, 1)");
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) out->base_r[3 * r + c] = b[4 * r + c];
+      out->base_p[r] = b[4 * r + 3];
+    }
+  } else {
+    out->base_r[0] = out->base_r[4] = out->base_r[8] = 1.0;
+  }
+  if (!need_points) return FASTRON_OK;
+  FASTRON_CHECK(cp != nullptr, "control points are NULL");
+  FASTRON_CHECK(cp->M >= 1 && cp->M <= FASTRON_MAX_POINTS, "cp->M = %d outside [1, %d]", cp->M,
+                FASTRON_MAX_POINTS);
+  FASTRON_CHECK(cp->frame != nullptr, "cp->frame is NULL");
+  out->M = cp->M;
+  int mm = 0;
+  for (int m = 0; m < cp->M; ++m) {
+    int f = cp->frame[m];
+    FASTRON_CHECK(f >= 0 && f <= n, "control point %d: frame %d outside [0, %d]", m, f, n);
+    out->on_frame[f] |= 1u << m;
+    for (int k = 0; k < 3; ++k) {
+      double o = cp->offset ? cp->offset[3 * m + k] : 0.0;
+      FASTRON_CHECK(std::isfinite(o), "non-finite offset of control point %d", m);
+      out->off[m][k] = o;
+    }
+    if (f >= 1) {
+      out->slot[m] = mm;
+      out->moving[mm++] = m;
+    } else {
+      out->slot[m] = -1;
+    }
+  }
+  out->Mm = mm;
+  return FASTRON_OK;
+}
+
+// ---------------------------------------------------------------------------
+// a1: one thread per configuration.
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ void __launch_bounds__(256) k_fk_points(ChainArgs c, const float* __restrict__ q, int64_t N,
+                                                    float* __restrict__ P) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= N) return;
+  float qv[FASTRON_MAX_JOINTS];
+#pragma unroll
+  for (int i = 0; i < FASTRON_MAX_JOINTS; ++i)
+    if (i < c.n) qv[i] = q[j * c.n + i];
+  float* out = P + j * (int64_t)c.M * 3;
+  fk_walk<R>(c, qv, [&](int m, float x, float y, float z) {
+    out[3 * m + 0] = x;
+    out[3 * m + 1] = y;
+    out[3 * m + 2] = z;
+  });
+}
+
+// ---------------------------------------------------------------------------
+// a2: support set -> scoring operands. One thread per (padded) support.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(r >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Splits v into `parts` bf16 terms whose sum approximates v (hi, mid, lo).
+__device__ __forceinline__ void bf16_split(float v, int parts, uint16_t out[3]) {
+  float rem = v;
+  for (int k = 0; k < 3; ++k) {
+    if (k < parts) {
+      out[k] = bf16_rne(rem);
+      rem -= bf16_to_f(out[k]);
+    } else {
+      out[k] = 0;
+    }
+  }
+}
+
+template <typename R>
+__global__ void __launch_bounds__(256) k_support_prep(ChainArgs c, const float* __restrict__ sq,
+                                                       const float* __restrict__ alpha, int64_t S, int64_t ntiles,
+                                                       float gamma, char* __restrict__ blob) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntiles * kTile) return;
+  const int Mp = (c.M + 3) & ~3;
+  const int64_t tile = s / kTile;
+  const int sl = (int)(s % kTile);
+  float* tiles = reinterpret_cast<float*>(blob + kHeaderBytes);
+  float* T = tiles + tile * tile_floats(Mp);
+  float* A = T;                          // [4][16][Mp]
+  float* C = T + tile_c_offset(Mp);      // [4][Mp][4]
+  float* W = T + tile_w_offset(Mp);      // [16]
+  const int64_t S_pad = ntiles * kTile;
+  float* V = reinterpret_cast<float*>(blob + kHeaderBytes + ntiles * tile_floats(Mp) * 4) + s * Mp * 4;
+  uint16_t* B16 = reinterpret_cast<uint16_t*>(blob + kHeaderBytes + ntiles * tile_floats(Mp) * 4 +
+                                              S_pad * Mp * 4 * 4) +
+                  tile * (int64_t)Mp * 512;
+  const int g_of = sl;  // row of this support inside its tile
+  // defaults: padding / unused slots contribute nothing
+  for (int m = 0; m < Mp; ++m) {
+    A[(0 * 16 + sl) * Mp + m] = 0.f;
+    A[(1 * 16 + sl) * Mp + m] = 0.f;
+    A[(2 * 16 + sl) * Mp + m] = 0.f;
+    A[(3 * 16 + sl) * Mp + m] = 1.f;
+    C[((g_of >> 2) * Mp + m) * 4 + (g_of & 3)] = 0.f;
+    V[m * 4 + 0] = 0.f; V[m * 4 + 1] = 0.f; V[m * 4 + 2] = 0.f; V[m * 4 + 3] = 0.f;
+    // bf16 A operand: row sl, k = 0..31, stored as [g][s][8] per m
+    for (int k = 0; k < 32; ++k) B16[(int64_t)m * 512 + ((k >> 3) * 16 + sl) * 8 + (k & 7)] = 0;
+  }
+  W[sl] = 0.f;
+  if (s >= S) return;
+  float qv[FASTRON_MAX_JOINTS];
+#pragma unroll
+  for (int i = 0; i < FASTRON_MAX_JOINTS; ++i)
+    if (i < c.n) qv[i] = sq[s * c.n + i];
+  const float half_g = 0.5f * gamma;
+  fk_walk<R>(c, qv, [&](int m, float x, float y, float z) {
+    const int slot = c.slot[m];
+    if (slot < 0) return;
+    const float ax = -gamma * x, ay = -gamma * y, az = -gamma * z;
+    const float cs = half_g * (x * x + y * y + z * z);
+    A[(0 * 16 + sl) * Mp + slot] = ax;
+    A[(1 * 16 + sl) * Mp + slot] = ay;
+    A[(2 * 16 + sl) * Mp + slot] = az;
+    C[((g_of >> 2) * Mp + slot) * 4 + (g_of & 3)] = cs;
+    V[slot * 4 + 0] = ax; V[slot * 4 + 1] = ay; V[slot * 4 + 2] = az; V[slot * 4 + 3] = cs;
+    // bf16 cross-term operand: -gamma p' split into hi + mid + lo bf16 terms, laid out so that the query
+    // side selects the precision: k0-2 hi, k3-5 hi, k6-8 mid, k9-11 hi, k12-14 lo, k15-17 mid, k18-20 = 1
+    // (the query side puts hi/mid/lo of p against them, and the three bf16 parts of c_q against the ones).
+    uint16_t sx[3], sy[3], sz[3];
+    bf16_split(ax, 3, sx);
+    bf16_split(ay, 3, sy);
+    bf16_split(az, 3, sz);
+    uint16_t* row = B16 + (int64_t)slot * 512;
+    auto put = [&](int k, uint16_t v) { row[((k >> 3) * 16 + sl) * 8 + (k & 7)] = v; };
+    auto put3 = [&](int k0, int part) { put(k0, sx[part]); put(k0 + 1, sy[part]); put(k0 + 2, sz[part]); };
+    put3(0, 0); put3(3, 0); put3(6, 1); put3(9, 0); put3(12, 2); put3(15, 1);
+    const uint16_t one = 0x3f80;
+    put(18, one); put(19, one); put(20, one);
+  });
+  W[sl] = alpha[s] / (float)c.M;
+}
+
+// f_const = (#fixed points / M) * sum_s alpha_s, summed by one block in a fixed order.
+__global__ void __launch_bounds__(1024) k_fixed_term(const float* __restrict__ alpha, int64_t S, float scale,
+                                                      float* __restrict__ header) {
+  __shared__ float part[1024];
+  float acc = 0.f;
+  for (int64_t s = threadIdx.x; s < S; s += 1024) acc += alpha[s];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 512; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) header[0] = part[0] * scale;
+}
+
+__global__ void k_zero_header(float* header) {
+  if (threadIdx.x < 64) header[threadIdx.x] = 0.f;
+}
+
+}  // namespace fastron
+
+using namespace fastron;
+
+extern "C" {
+
+const char* fastron_last_error(void) { return g_err; }
+
+const char* fastron_version(void) { return "fastron-fk gfx950 1.0"; }
+
+int64_t fastron_model_bytes(int64_t S, int32_t M) {
+  if (S < 0 || M < 1 || M > FASTRON_MAX_POINTS) return -1;
+  return model_bytes(S, M);
+}
+
+fastron_status fastron_fk_points(const fastron_chain* chain, const fastron_cpoints* cp, const float* q, int64_t N,
+                                 float* P, void* stream) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(N >= 0, "N = %lld < 0", (long long)N);
+  if (N == 0) return FASTRON_OK;
+  FASTRON_CHECK(q && P, "q and P must be non-NULL");
+  FASTRON_CHECK(aligned(q, 4) && aligned(P, 4), "q and P must be 4-byte aligned");
+  const int64_t blocks = (N + 255) / 256;
+  FASTRON_CHECK(blocks <= INT32_MAX, "N too large");
+  if (c.n >= kFp64Joints)
+    hipLaunchKernelGGL(k_fk_points<double>, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), c, q, N, P);
+  else
+    hipLaunchKernelGGL(k_fk_points<float>, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), c, q, N, P);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+fastron_status fastron_support_prep(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,
+                                    const float* alpha, int64_t S, float gamma, fastron_model* model, void* stream) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(model != nullptr, "model is NULL");
+  FASTRON_CHECK(S >= 0, "S = %lld < 0", (long long)S);
+  FASTRON_CHECK(std::isfinite(gamma) && gamma > 0.f, "gamma must be finite and > 0");
+  FASTRON_CHECK(model->data != nullptr, "model->data is NULL");
+  FASTRON_CHECK(aligned(model->data, 256), "model->data must be 256-byte aligned");
+  const int64_t need = model_bytes(S, c.M);
+  FASTRON_CHECK(model->bytes >= need, "model->bytes = %lld < %lld needed", (long long)model->bytes,
+                (long long)need);
+  FASTRON_CHECK(S == 0 || (support_q && alpha), "support_q and alpha must be non-NULL when S > 0");
+  model->S = S;
+  model->M = c.M;
+  model->gamma = gamma;
+  hipStream_t s = as_stream(stream);
+  char* blob = static_cast<char*>(model->data);
+  hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(blob));
+  FASTRON_HIP(hipGetLastError());
+  const int64_t nt = ntiles_of(S);
+  if (nt > 0) {
+    const int64_t threads = nt * kTile;
+    const unsigned blocks = (unsigned)((threads + 255) / 256);
+    if (c.n >= kFp64Joints)
+      hipLaunchKernelGGL(k_support_prep<double>, dim3(blocks), dim3(256), 0, s, c, support_q, alpha, S, nt, gamma,
+                         blob);
+    else
+      hipLaunchKernelGGL(k_support_prep<float>, dim3(blocks), dim3(256), 0, s, c, support_q, alpha, S, nt, gamma,
+                         blob);
+    FASTRON_HIP(hipGetLastError());
+  }
+  if (S > 0 && c.Mm < c.M) {
+    hipLaunchKernelGGL(k_fixed_term, dim3(1), dim3(1024), 0, s, alpha, S, (float)(c.M - c.Mm) / (float)c.M,
+                       reinterpret_cast<float*>(blob));
+    FASTRON_HIP(hipGetLastError());
+  }
+  return FASTRON_OK;
+}
+
+}  // extern "C"

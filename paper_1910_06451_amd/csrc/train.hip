@@ -1,0 +1,524 @@
+// Gram columns and the Fastron model update (Section III-B, Eq. 5-9 and
+// Algorithm 1) on the device.
+//
+// fastron_gram_update: one thread per training point j evaluates
+//   K_FK(X_j, X_i) = (1/M) sum_m (1 + gamma/2 ||FK_m(X_j) - FK_m(X_i)||^2)^-2
+// with direct differences (HBM-bound: 12M bytes of control points per j) and
+// applies F_j += dalpha * K_ji.
+//
+// fastron_train: Algorithm 1 is strictly sequential -- every iteration needs
+// the global argmin of the margins before the next column can be chosen -- so
+// it runs as ONE persistent, cooperatively launched grid. Each workgroup owns
+// a contiguous slice of the training set. Per iteration each workgroup:
+//   1. publishes one record for its slice (min margin and its index, the
+//      weight at that index, max of y(F - alpha) over alpha != 0 and its
+//      index and weight, and its count of nonzero weights);
+//   2. meets the other workgroups at a grid barrier;
+//   3. reduces all records itself (identically in every workgroup, so every
+//      workgroup takes the same decision without a second barrier);
+//   4. applies the add or the removal to its slice in one pass that also
+//      builds its next record.
+// Records are double-buffered by iteration parity. The barrier spins with a
+// bounded budget and reports FASTRON_EDEVICE instead of hanging.
+#include <cmath>
+
+#include "fastron_internal.h"
+
+namespace fastron {
+
+// ---------------------------------------------------------------------------
+// a4: Gram column + F update
+// ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// a5: persistent Algorithm 1
+// ---------------------------------------------------------------------------
+template <typename T>
+struct Rec {
+  T minval;       // min over the slice of y_j F_j
+  T a_at_min;     // alpha at that index
+  T maxval;       // max over the slice of y_j (F_j - alpha_j), alpha_j != 0
+  T a_at_max;     // alpha at that index
+  int32_t minidx; // -1 if the slice is empty
+  int32_t maxidx; // -1 if no nonzero weight in the slice
+  int32_t count;  // number of nonzero weights in the slice
+  int32_t pad;
+};
+
+template <typename T>
+struct TrainState {
+  const float* P;
+  const int8_t* y;
+  T* alpha;
+  T* F;
+  Rec<T>* rec;         // [2][G]
+  unsigned* bar;       // [0] arrivals, [1] generation
+  int64_t* out;        // [0] updates, [1] status (0 break, 1 iter_max, -5 barrier timeout)
+  int32_t* trace_act;
+  int32_t* trace_idx;
+  int64_t trace_cap;
+  int64_t N;
+  int64_t iter_max;
+  int64_t s_max;
+  T half_g;
+  T beta;
+  int M;
+  int chunk;           // training points per workgroup
+  long long timeout;    // barrier wait limit in constant-clock ticks
+};
+
+template <typename T>
+__device__ __forceinline__ void rec_merge(Rec<T>& a, const Rec<T>& b) {
+  if (b.minidx >= 0 && (a.minidx < 0 || b.minval < a.minval || (b.minval == a.minval && b.minidx < a.minidx))) {
+    a.minval = b.minval;
+    a.a_at_min = b.a_at_min;
+    a.minidx = b.minidx;
+  }
+  if (b.maxidx >= 0 && (a.maxidx < 0 || b.maxval > a.maxval || (b.maxval == a.maxval && b.maxidx < a.maxidx))) {
+    a.maxval = b.maxval;
+    a.a_at_max = b.a_at_max;
+    a.maxidx = b.maxidx;
+  }
+  a.count += b.count;
+}
+
+template <typename T>
+__device__ __forceinline__ Rec<T> rec_empty() {
+  Rec<T> r;
+  r.minval = 0;
+  r.a_at_min = 0;
+  r.maxval = 0;
+  r.a_at_max = 0;
+  r.minidx = -1;
+  r.maxidx = -1;
+  r.count = 0;
+  r.pad = 0;
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ Rec<T> rec_shfl_down(const Rec<T>& r, int off) {
+  Rec<T> o;
+  o.minval = __shfl_down(r.minval, off);
+  o.a_at_min = __shfl_down(r.a_at_min, off);
+  o.maxval = __shfl_down(r.maxval, off);
+  o.a_at_max = __shfl_down(r.a_at_max, off);
+  o.minidx = __shfl_down(r.minidx, off);
+  o.maxidx = __shfl_down(r.maxidx, off);
+  o.count = __shfl_down(r.count, off);
+  o.pad = 0;
+  return o;
+}
+
+// K_FK between a training point (global memory) and the chosen point (LDS),
+// with direct differences. The FP64 form disables FMA contraction so that it
+// rounds operation by operation in the order the definition is written.
+__device__ __forceinline__ float kfk_pair(const float* __restrict__ pj, const float* pi, int M, float half_g) {
+  float s = 0.f;
+  for (int m = 0; m < M; ++m) {
+    const float dx = pj[3 * m] - pi[3 * m], dy = pj[3 * m + 1] - pi[3 * m + 1], dz = pj[3 * m + 2] - pi[3 * m + 2];
+    const float t = 1.0f + half_g * (dx * dx + dy * dy + dz * dz);
+    const float r = __builtin_amdgcn_rcpf(t);
+    s = fmaf(r, r, s);
+  }
+  return s / (float)M;
+}
+
+__device__ __forceinline__ double kfk_pair(const float* __restrict__ pj, const float* pi, int M, double half_g) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+  for (int m = 0; m < M; ++m) {
+    double d2 = 0.0;
+    for (int k = 0; k < 3; ++k) {
+      const double diff = (double)pj[3 * m + k] - (double)pi[3 * m + k];
+      d2 += diff * diff;
+    }
+    const double t = 1.0 + half_g * d2;
+    s += 1.0 / (t * t);
+  }
+  return s / (double)M;
+}
+
+__device__ __forceinline__ float axpy_rn(float a, float x, float y) { return y + a * x; }
+
+// ---------------------------------------------------------------------------
+// a4: Gram column + F update, one thread per training point.
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_gram_update(const float* __restrict__ P, int64_t N, int M, float half_g,
+                                                      int64_t i, float dalpha, float* __restrict__ F,
+                                                      float* __restrict__ kcol) {
+  __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
+  if ((int)threadIdx.x < 3 * M) pi_sh[threadIdx.x] = P[i * (int64_t)M * 3 + threadIdx.x];
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= N) return;
+  const float k = kfk_pair(P + j * (int64_t)M * 3, pi_sh, M, half_g);
+  if (kcol) kcol[j] = k;
+  if (F) F[j] = axpy_rn(dalpha, k, F[j]);
+}
+__device__ __forceinline__ double axpy_rn(double a, double x, double y) {
+#pragma clang fp contract(off)
+  return y + a * x;
+}
+__device__ __forceinline__ float sub_rn(float a, float b) { return a - b; }
+__device__ __forceinline__ double sub_rn(double a, double b) {
+#pragma clang fp contract(off)
+  return a - b;
+}
+
+// Decision shared by the workgroup after each reduction.
+template <typename T>
+struct Decision {
+  T dalpha;
+  int64_t i;
+  int action;  // 1 add, 2 remove, 0 break (converged), 3 stop (iter_max), 4 stop (barrier timeout)
+};
+
+template <typename T>
+__device__ __forceinline__ Rec<T> wave_reduce(Rec<T> r) {
+  for (int off = 32; off > 0; off >>= 1) {
+    Rec<T> o = rec_shfl_down(r, off);
+    if ((int)(threadIdx.x & 63) + off < 64) rec_merge(r, o);
+  }
+  return r;
+}
+
+template <typename T>
+__device__ __forceinline__ void point_record(Rec<T>& r, int64_t j, T yj, T Fj, T aj) {
+  Rec<T> c = rec_empty<T>();
+  c.minval = yj * Fj;
+  c.a_at_min = aj;
+  c.minidx = (int32_t)j;
+  if (aj != (T)0) {
+    c.maxval = yj * (Fj - aj);
+    c.a_at_max = aj;
+    c.maxidx = (int32_t)j;
+    c.count = 1;
+  }
+  rec_merge(r, c);
+}
+
+// One workgroup per slice; PT training points per thread, their y, alpha and
+// F held in registers for the whole run. Wave 0 leads: it publishes the
+// workgroup's record, meets the grid at the barrier, reduces every record and
+// broadcasts the decision (and the chosen point's control points) through LDS.
+template <typename T, int PT>
+__global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
+  __shared__ Rec<T> sh[16];
+  __shared__ Decision<T> dec;
+  __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
+  __shared__ int sh_ok;
+  const unsigned G = gridDim.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int64_t j0 = (int64_t)blockIdx.x * st.chunk;
+  const int64_t j1 = (j0 + st.chunk < st.N) ? j0 + st.chunk : st.N;
+  const int M = st.M;
+  unsigned gen = 0;
+
+  T y[PT], F[PT], a[PT];
+  int64_t jj[PT];
+  Rec<T> r = rec_empty<T>();
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    jj[k] = j0 + threadIdx.x + (int64_t)k * blockDim.x;
+    if (jj[k] < j1) {
+      y[k] = (T)st.y[jj[k]];
+      F[k] = st.F[jj[k]];
+      a[k] = st.alpha[jj[k]];
+      point_record(r, jj[k], y[k], F[k], a[k]);
+    } else {
+      y[k] = 0;
+      F[k] = 0;
+      a[k] = 0;
+    }
+  }
+  r = wave_reduce(r);
+  if (lane == 0) sh[wave] = r;
+  __syncthreads();
+
+  int64_t updates = 0;
+  int64_t status = 1;
+  for (int64_t it = 0;; ++it) {
+    if (wave == 0) {
+      Rec<T> mine = sh[0];
+      for (int w = 1; w < nw; ++w) rec_merge(mine, sh[w]);
+      Rec<T>* slot = st.rec + (it & 1) * G;
+      if (lane == 0) slot[blockIdx.x] = mine;
+      bool ok = true;
+      if (lane == 0) {
+        __threadfence();
+        const unsigned g = gen;
+        const unsigned prev = __hip_atomic_fetch_add(&st.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (prev == G - 1) {
+          __hip_atomic_store(&st.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          __hip_atomic_store(&st.bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        } else {
+          const long long t0 = wall_clock64();
+          while (__hip_atomic_load(&st.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wall_clock64() - t0 > st.timeout) {
+              ok = false;
+              break;
+            }
+          }
+        }
+        __threadfence();
+        gen = g + 1u;
+        sh_ok = ok ? 1 : 0;
+      }
+      __builtin_amdgcn_wave_barrier();
+      ok = __shfl(ok ? 1 : 0, 0) != 0;
+      Rec<T> gr = rec_empty<T>();
+      for (unsigned w = lane; w < G; w += 64) rec_merge(gr, slot[w]);
+      gr = wave_reduce(gr);
+      gr.minval = __shfl(gr.minval, 0);
+      gr.a_at_min = __shfl(gr.a_at_min, 0);
+      gr.maxval = __shfl(gr.maxval, 0);
+      gr.a_at_max = __shfl(gr.a_at_max, 0);
+      gr.minidx = __shfl(gr.minidx, 0);
+      gr.maxidx = __shfl(gr.maxidx, 0);
+      gr.count = __shfl(gr.count, 0);
+      Decision<T> d;
+      d.action = 0;
+      d.i = -1;
+      d.dalpha = 0;
+      if (!ok) {
+        d.action = 4;
+      } else if (updates >= st.iter_max) {
+        d.action = 3;
+      } else if (gr.minidx >= 0 && gr.minval <= (T)0 && ((int64_t)gr.count < st.s_max || gr.a_at_min != (T)0)) {
+        d.i = gr.minidx;
+        const T yi = (T)st.y[d.i];
+        const T Fi = yi * gr.minval;          // y = +-1: y (y F) = F exactly
+        const T bi = yi > 0 ? st.beta : (T)1;  // b_i = beta^(0.5 (y_i + 1)), Eq. 5
+        d.dalpha = sub_rn(bi * yi, Fi);        // Eq. 6
+        d.action = 1;
+      } else if (gr.maxidx >= 0 && gr.maxval > (T)0) {
+        d.i = gr.maxidx;
+        d.dalpha = -gr.a_at_max;
+        d.action = 2;
+      }
+      if (d.action == 1 || d.action == 2) {
+        if (lane < 3 * M) pi_sh[lane] = st.P[d.i * (int64_t)M * 3 + lane];
+        if (blockIdx.x == 0 && lane == 0 && updates < st.trace_cap) {
+          st.trace_act[updates] = d.action;
+          st.trace_idx[updates] = (int32_t)d.i;
+        }
+      }
+      if (lane == 0) dec = d;
+    }
+    __syncthreads();
+    const Decision<T> d = dec;
+    if (d.action != 1 && d.action != 2) {
+      status = d.action == 0 ? 0 : (d.action == 3 ? 1 : -5);
+      break;
+    }
+    ++updates;
+    // column i of K on this thread's points (Eq. 8), fused with the next record
+    r = rec_empty<T>();
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      if (jj[k] < j1) {
+        const T kv = kfk_pair(st.P + jj[k] * (int64_t)M * 3, pi_sh, M, st.half_g);
+        F[k] = axpy_rn(d.dalpha, kv, F[k]);
+        if (jj[k] == d.i) a[k] = (d.action == 1) ? a[k] + d.dalpha : (T)0;  // Eq. 7 / removal
+        point_record(r, jj[k], y[k], F[k], a[k]);
+      }
+    }
+    r = wave_reduce(r);
+    if (lane == 0) sh[wave] = r;
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < PT; ++k)
+    if (jj[k] < j1) {
+      st.F[jj[k]] = F[k];
+      st.alpha[jj[k]] = a[k];
+    }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    st.out[0] = updates;
+    st.out[1] = status;
+  }
+}
+
+__global__ void k_train_init(unsigned* bar, int64_t* out) {
+  if (threadIdx.x < 2) {
+    bar[threadIdx.x] = 0u;
+    out[threadIdx.x] = 0;
+  }
+}
+
+// removeNonsupportPoints: stable compaction of the indices with alpha != 0.
+template <typename T>
+__global__ void __launch_bounds__(1024) k_compact(const T* __restrict__ alpha, int64_t N, int32_t* __restrict__ idx,
+                                                  int64_t* __restrict__ count) {
+  __shared__ int wsum[16];
+  __shared__ int64_t base;
+  if (threadIdx.x == 0) base = 0;
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int64_t start = 0; start < N; start += 1024) {
+    const int64_t j = start + threadIdx.x;
+    const int flag = (j < N && alpha[j] != (T)0) ? 1 : 0;
+    // inclusive scan within the wave
+    int v = flag;
+    for (int off = 1; off < 64; off <<= 1) {
+      int o = __shfl_up(v, off);
+      if (lane >= off) v += o;
+    }
+    if (lane == 63) wsum[wave] = v;
+    __syncthreads();
+    int before = 0;
+    for (int w = 0; w < wave; ++w) before += wsum[w];
+    if (flag) idx[base + before + v - 1] = (int32_t)j;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int tot = 0;
+      for (int w = 0; w < 16; ++w) tot += wsum[w];
+      base += tot;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *count = base;
+}
+
+template <typename T>
+static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int32_t M, T gamma, T beta,
+                                 int64_t iter_max, int64_t s_max, T* alpha, T* F, int32_t* support_idx,
+                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
+                                 int64_t trace_cap, void* stream) {
+  clear_error();
+  FASTRON_CHECK(N >= 1 && N < INT32_MAX, "N = %lld outside [1, 2^31)", (long long)N);
+  FASTRON_CHECK(M >= 1 && M <= FASTRON_MAX_POINTS, "M = %d outside [1, %d]", M, FASTRON_MAX_POINTS);
+  FASTRON_CHECK(P && y && alpha && F && support_idx, "P, y, alpha, F and support_idx must be non-NULL");
+  FASTRON_CHECK(n_support && updates, "n_support and updates must be non-NULL host pointers");
+  FASTRON_CHECK(std::isfinite((double)gamma) && gamma > 0, "gamma must be finite and > 0");
+  FASTRON_CHECK(std::isfinite((double)beta) && beta >= 1, "beta must be >= 1 (Eq. 5)");
+  FASTRON_CHECK(iter_max >= 0, "iter_max < 0");
+  FASTRON_CHECK(s_max >= 1, "s_max must be >= 1");
+  FASTRON_CHECK(trace_cap >= 0 && (trace_cap == 0 || (trace_action && trace_index)),
+                "trace arrays must be non-NULL when trace_cap > 0");
+  hipStream_t s = as_stream(stream);
+  int dev = 0;
+  FASTRON_HIP(hipGetDevice(&dev));
+  int ncu = 0, coop = 0;
+  FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  FASTRON_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return fail(FASTRON_EUNSUPPORTED, "device does not support cooperative launches");
+  // Workgroups: a slice per workgroup, at most one workgroup per CU, each
+  // thread holding PT points in registers (PT in {1, 2, 4, 8, 16}).
+  const int threads = (int)tune_get("train.threads");
+  int64_t G = tune_get("train.blocks");
+  if (G <= 0) G = (N + 2 * threads - 1) / (2 * threads);  // about two points per thread
+  if (G > ncu) G = ncu;
+  if (G < 1) G = 1;
+  int64_t chunk = (N + G - 1) / G;
+  int PT = 1;
+  while ((int64_t)PT * threads < chunk) PT *= 2;
+  if (PT > 16)
+    return fail(FASTRON_EUNSUPPORTED, "N = %lld exceeds %lld training points (16 per thread on %d CUs)",
+                (long long)N, (long long)16 * threads * ncu, ncu);
+  G = (N + chunk - 1) / chunk;
+  const void* kfn = nullptr;
+  switch (PT) {
+    case 1: kfn = reinterpret_cast<const void*>(k_train<T, 1>); break;
+    case 2: kfn = reinterpret_cast<const void*>(k_train<T, 2>); break;
+    case 4: kfn = reinterpret_cast<const void*>(k_train<T, 4>); break;
+    case 8: kfn = reinterpret_cast<const void*>(k_train<T, 8>); break;
+    default: kfn = reinterpret_cast<const void*>(k_train<T, 16>); break;
+  }
+  int per_cu = 0;
+  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, 0));
+  if (per_cu < 1) return fail(FASTRON_EUNSUPPORTED, "training kernel cannot be resident with %d threads", threads);
+
+  const size_t rec_bytes = sizeof(Rec<T>) * 2 * (size_t)G;
+  char* ws = nullptr;
+  FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), rec_bytes + 256 + 256, s));
+  Rec<T>* rec = reinterpret_cast<Rec<T>*>(ws);
+  unsigned* bar = reinterpret_cast<unsigned*>(ws + rec_bytes);
+  int64_t* out = reinterpret_cast<int64_t*>(ws + rec_bytes + 64);
+  int64_t* cnt = reinterpret_cast<int64_t*>(ws + rec_bytes + 128);
+  hipLaunchKernelGGL(k_train_init, dim3(1), dim3(64), 0, s, bar, out);
+  fastron_status rs = FASTRON_OK;
+  hipError_t e = hipGetLastError();
+  if (e == hipSuccess) {
+    TrainState<T> st;
+    st.P = P;
+    st.y = y;
+    st.alpha = alpha;
+    st.F = F;
+    st.rec = rec;
+    st.bar = bar;
+    st.out = out;
+    st.trace_act = trace_action;
+    st.trace_idx = trace_index;
+    st.trace_cap = trace_cap;
+    st.N = N;
+    st.iter_max = iter_max;
+    st.s_max = s_max;
+    st.half_g = gamma / (T)2;
+    st.beta = beta;
+    st.M = M;
+    st.chunk = (int)chunk;
+    st.timeout = 400000000ll;  // 4 s at 100 MHz
+    void* args[] = {&st};
+    e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3((unsigned)threads), args, 0, s);
+  }
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_compact<T>, dim3(1), dim3(1024), 0, s, alpha, N, support_idx, cnt);
+    e = hipGetLastError();
+  }
+  int64_t host[3] = {0, 0, 0};
+  if (e == hipSuccess) e = hipMemcpyAsync(host, out, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(host + 2, cnt, sizeof(int64_t), hipMemcpyDeviceToHost, s);
+  hipError_t ef = hipFreeAsync(ws, s);
+  if (e == hipSuccess) e = ef;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(FASTRON_EHIP, "training launch failed: %s", hipGetErrorString(e));
+  *updates = host[0];
+  *n_support = host[2];
+  if (host[1] == -5) return fail(FASTRON_EDEVICE, "grid barrier timed out after %lld updates", (long long)host[0]);
+  rs = host[1] == 0 ? FASTRON_OK : FASTRON_NOT_CONVERGED;
+  return rs;
+}
+
+}  // namespace fastron
+
+using namespace fastron;
+
+extern "C" {
+
+fastron_status fastron_gram_update(const float* P, int64_t N, int32_t M, float gamma, int64_t i, float delta_alpha,
+                                   float* F, float* kcol, void* stream) {
+  clear_error();
+  FASTRON_CHECK(N >= 1, "N = %lld < 1", (long long)N);
+  FASTRON_CHECK(M >= 1 && M <= FASTRON_MAX_POINTS, "M = %d outside [1, %d]", M, FASTRON_MAX_POINTS);
+  FASTRON_CHECK(i >= 0 && i < N, "i = %lld outside [0, N)", (long long)i);
+  FASTRON_CHECK(P != nullptr, "P is NULL");
+  FASTRON_CHECK(F != nullptr || kcol != nullptr, "F and kcol are both NULL");
+  FASTRON_CHECK(std::isfinite(gamma) && gamma > 0.f, "gamma must be finite and > 0");
+  FASTRON_CHECK(std::isfinite(delta_alpha), "delta_alpha must be finite");
+  const int64_t blocks = (N + 255) / 256;
+  FASTRON_CHECK(blocks <= INT32_MAX, "N too large");
+  hipLaunchKernelGGL(k_gram_update, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), P, N, M, 0.5f * gamma,
+                     i, delta_alpha, F, kcol);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+fastron_status fastron_train(const float* P, const int8_t* y, int64_t N, int32_t M, float gamma, float beta,
+                             int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
+                             int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
+                             int64_t trace_cap, void* stream) {
+  return train_impl<float>(P, y, N, M, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                           trace_action, trace_index, trace_cap, stream);
+}
+
+fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma, double beta,
+                                 int64_t iter_max, int64_t s_max, double* alpha, double* F, int32_t* support_idx,
+                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
+                                 int64_t trace_cap, void* stream) {
+  return train_impl<double>(P, y, N, M, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                            trace_action, trace_index, trace_cap, stream);
+}
+
+}  // extern "C"

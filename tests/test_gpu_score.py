@@ -1,0 +1,183 @@
+"""Parity of the fused FK-kernel score (Section III-B model, Section III-A
+Eq. 4, Section II-B Eq. 3) with the FP64 oracle.
+
+Tolerance (derived from the arithmetic, per query): the kernel forms
+t = c_q + c_s - gamma p.p' in float32 from float32 control points, so each
+t carries an absolute error of at most a few units of 2^-24 times the size of
+the terms it adds, |c_q| + |c_s| + gamma |p||p'|; K_RQ = t^-2 turns an error
+dt into 2 dt / t^3, and the reciprocal adds one float32 ulp. Summed over the
+model with |alpha_s| / M weights this gives the bound used below (with a
+factor-of-8 safety margin on the unit roundoff). Queries whose oracle score
+is smaller than their bound are inherently ambiguous for the sign test and
+are reported, not asserted."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1910_06451_amd import api, workloads as wl
+from conftest import announce, oracle_dh
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+
+
+def error_bound(Ps, alpha, gamma, Pq, safety=8.0):
+    """Per-query first-order bound on |f_gpu - f_oracle| for the float32 expanded form."""
+    M = Ps.shape[1]
+    out = np.zeros(Pq.shape[0])
+    aw = np.abs(alpha.astype(np.float64)) / M
+    ns = np.linalg.norm(Ps, axis=2)  # (S, M)
+    for j in range(Pq.shape[0]):
+        d2 = np.sum((Ps - Pq[j][None]) ** 2, axis=2)  # (S, M)
+        t = 1.0 + 0.5 * gamma * d2
+        nq = np.linalg.norm(Pq[j], axis=1)[None, :]
+        terms = 1.0 + 0.5 * gamma * (nq ** 2 + ns ** 2) + gamma * nq * ns
+        dt = safety * U32 * terms
+        dk = 2.0 * dt / t ** 3 + safety * U32 / t ** 2
+        out[j] = np.sum(aw[:, None] * dk)
+    return out
+
+
+def _sign(f):
+    return np.where(f < 0, -1, 1)
+
+
+def check_scores(f_gpu, lab_gpu, f_ref, tol, min_agree=0.9999):
+    err = np.abs(f_gpu.astype(np.float64) - f_ref)
+    assert np.all(err <= tol), (err.max(), tol[np.argmax(err - tol)])
+    np.testing.assert_array_equal(lab_gpu, _sign(f_gpu))
+    decisive = np.abs(f_ref) > tol
+    assert np.all(lab_gpu[decisive] == _sign(f_ref)[decisive])
+    agree = np.mean(lab_gpu == _sign(f_ref))
+    assert agree >= min_agree, agree
+    return dict(max_abs_df=float(err.max()), sign_agreement=float(agree), ambiguous=int(np.sum(~decisive)))
+
+
+def _case(arm, S, N, gamma, name):
+    sq, al = wl.model(name, S, arm.n)
+    q = wl.configs(name + "/q", N, arm.n)
+    return sq, al, q
+
+
+@pytest.mark.parametrize("arm_name,S,N", [("3dof", 300, 10_037), ("7dof", 4001, 4099), ("7dof", 17, 65),
+                                          ("7dof", 1, 1)])
+def test_score_parity(oracle_mod, dev, arm_name, S, N):
+    arm = wl.arm_3dof() if arm_name == "3dof" else wl.arm_7dof()
+    gamma = 10.0
+    sq, al, q = _case(arm, S, N, gamma, f"score_{arm_name}_{S}_{N}")
+    announce(f"fk_score {arm_name} S={S} N={N}")
+    f, lab = api.fk_score(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma,
+                          torch.from_numpy(q).to(dev))
+    f, lab = f.cpu().numpy(), lab.cpu().numpy()
+    dh = oracle_dh(oracle_mod, arm)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64))
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64))
+    tol = error_bound(Ps, al, gamma, Pq)
+    stats = check_scores(f, lab, ref, tol)
+    print(stats)
+
+
+def test_score_full_size_sampled(oracle_mod, dev):
+    """7-DOF arm, S = 4,000 supports, N = 1,000,000 queries in one launch; the oracle checks a sample."""
+    arm = wl.arm_7dof()
+    gamma, S, N = 10.0, 4000, 1_000_000
+    sq, al = wl.model("bench7", S, arm.n)
+    q = wl.configs("bench7/q", N, arm.n)
+    announce("fk_score full size S=4000 N=1e6")
+    f, lab = api.fk_score(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma,
+                          torch.from_numpy(q).to(dev))
+    f, lab = f.cpu().numpy(), lab.cpu().numpy()
+    idx = np.unique(np.concatenate([wl.rng("bench7/sample").choice(N, 1500, replace=False), [0, N - 1]]))
+    dh = oracle_dh(oracle_mod, arm)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma,
+                           q[idx].astype(np.float64))
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, arm.frames, q[idx].astype(np.float64))
+    stats = check_scores(f[idx], lab[idx], ref, error_bound(Ps, al, gamma, Pq))
+    print(stats)
+    # properties that hold at every index: labels are the signs of f, no NaN
+    assert np.all(np.isfinite(f))
+    np.testing.assert_array_equal(lab, _sign(f))
+
+
+def test_prepared_matches_convenience_and_valu(oracle_mod, dev):
+    arm = wl.arm_7dof()
+    gamma = 10.0
+    sq, al, q = _case(arm, 333, 1000, gamma, "prep_vs_conv")
+    sq_d, al_d, q_d = (torch.from_numpy(x).to(dev) for x in (sq, al, q))
+    announce("prepared vs convenience vs valu")
+    model = api.support_prep(arm, sq_d, al_d, gamma)
+    f1, l1 = api.fk_score_prepared(arm, model, q_d)
+    f2, l2 = api.fk_score(arm, sq_d, al_d, gamma, q_d)
+    torch.testing.assert_close(f1, f2, rtol=0, atol=0)
+    assert torch.equal(l1, l2)
+    fv, lv = api.fk_score_prepared(arm, model, q_d, flags=api.SCORE_VALU)
+    dh = oracle_dh(oracle_mod, arm)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64))
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64))
+    check_scores(fv.cpu().numpy(), lv.cpu().numpy(), ref, error_bound(Ps, al, gamma, Pq))
+    # label-only and f-only requests
+    _, lab_only = api.fk_score_prepared(arm, model, q_d, want_f=False)
+    assert torch.equal(lab_only, l1)
+
+
+@pytest.mark.parametrize("variant", [api.BF16_PLAIN, api.BF16_SPLIT2, api.BF16_SPLIT3])
+def test_bf16_forms(oracle_mod, dev, variant):
+    """Precision form: BF16 cross term with FP32 norms / accumulation. split3 must meet the FP32 bound;
+    the cheaper variants are measured against the oracle and must stay finite and ordered by accuracy."""
+    arm = wl.arm_7dof()
+    gamma = 10.0
+    sq, al, q = _case(arm, 2048, 2000, gamma, "bf16_forms")
+    announce(f"bf16 variant {variant}")
+    model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma)
+    f, lab = api.fk_score_prepared(arm, model, torch.from_numpy(q).to(dev), flags=api.SCORE_BF16 | variant)
+    f, lab = f.cpu().numpy(), lab.cpu().numpy()
+    dh = oracle_dh(oracle_mod, arm)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64))
+    err = np.abs(f - ref)
+    assert np.all(np.isfinite(f))
+    np.testing.assert_array_equal(lab, _sign(f))
+    agree = np.mean(lab == _sign(ref))
+    print(dict(variant=variant, max_abs_df=float(err.max()), sign_agreement=float(agree)))
+    if variant == api.BF16_SPLIT3:
+        Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+        Pq = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64))
+        check_scores(f, lab, ref, error_bound(Ps, al, gamma, Pq))
+    elif variant == api.BF16_SPLIT2:
+        assert err.max() < 0.05 and agree > 0.99
+    else:
+        assert agree > 0.8
+
+
+def test_score_edge_cases(oracle_mod, dev):
+    arm = wl.arm_7dof()
+    gamma = 10.0
+    q = torch.from_numpy(wl.configs("edge/q", 100, 7)).to(dev)
+    announce("edge: empty model")
+    f, lab = api.fk_score(arm, torch.zeros((0, 7), device=dev), torch.zeros(0, device=dev), gamma, q)
+    assert torch.all(f == 0) and torch.all(lab == 1)
+    announce("edge: empty query batch")
+    f, lab = api.fk_score(arm, torch.zeros((3, 7), device=dev), torch.ones(3, device=dev), gamma, q[:0])
+    assert f.shape == (0,)
+    # every control point fixed to the base: K_FK = 1 for every pair, f = sum(alpha)
+    fixed = wl.arm_7dof()
+    fixed.frames = np.zeros(3, dtype=np.int32)
+    al = torch.tensor([0.5, -2.0, 0.25], device=dev)
+    announce("edge: all points fixed")
+    f, _ = api.fk_score(fixed, torch.zeros((3, 7), device=dev), al, gamma, q)
+    torch.testing.assert_close(f, torch.full_like(f, -1.25))
+    # a single moving point (M = 1)
+    one = wl.arm_7dof()
+    one.frames = np.array([7], dtype=np.int32)
+    sq, alp = wl.model("edge/one", 50, 7)
+    announce("edge: M = 1")
+    f, lab = api.fk_score(one, torch.from_numpy(sq).to(dev), torch.from_numpy(alp).to(dev), gamma, q)
+    dh = oracle_dh(oracle_mod, one)
+    ref = oracle_mod.score(dh, one.frames, sq.astype(np.float64), alp.astype(np.float64), gamma,
+                           q.cpu().numpy().astype(np.float64))
+    Ps = oracle_mod.control_points(dh, one.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, one.frames, q.cpu().numpy().astype(np.float64))
+    check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, error_bound(Ps, alp, gamma, Pq), min_agree=0.99)
