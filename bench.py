@@ -26,12 +26,14 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Derived ALU ceiling of the fused score, in control-point kernel evaluations
-# per second: each evaluation needs one reciprocal (transcendental, quarter
-# rate: 32 lanes/clk/CU) and one FMA (full rate: 128 lanes/clk/CU) on the
-# vector ALU once the cross term runs on the matrix cores:
-#   256 CU * 2.4e9 Hz / (1/32 + 1/128) = 15.73e12 evaluations/s.
-ALU_PEAK_CP_PER_S = 256 * 2.4e9 / (1.0 / 32 + 1.0 / 128)
+# Derived ALU ceiling of the FP32 fused score, in control-point kernel
+# evaluations (cp-evals) per second. One cp-eval needs the 4-deep cross term
+# with the norms (4 FMA-equivalents; FP32 MFMA runs on the same ALUs as the
+# vector FMAs and does not overlap with them), one reciprocal (quarter-rate
+# transcendental) and one FMA. With 128 FP32 lanes/clk/CU (the 157.3 TFLOP/s
+# figure) and 32 transcendental lanes/clk/CU:
+#   256 CU * 2.4e9 Hz / (5/128 + 1/32) = 8.74e12 cp-evals/s.
+ALU_PEAK_CP_PER_S = 256 * 2.4e9 / (5.0 / 128 + 1.0 / 32)
 
 
 def log(msg):
