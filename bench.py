@@ -50,6 +50,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
@@ -102,6 +104,13 @@ def main():
         return e0.elapsed_time(e1) / reps
 
     k_ms = kernel_ms(api.SCORE_FP32, args.steps)
+    if args.calibrate_copy:
+        src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     cp_per_launch = N * S * Mm
     achieved = cp_per_launch / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_CP_PER_S / 1e12,

@@ -41,7 +41,7 @@ struct Rec {
   int32_t minidx; // -1 if the slice is empty
   int32_t maxidx; // -1 if no nonzero weight in the slice
   int32_t count;  // number of nonzero weights in the slice
-  int32_t pad;
+  int32_t ymin;   // label y at minidx (so the decision needs no lookup)
 };
 
 template <typename T>
@@ -63,7 +63,8 @@ struct TrainState {
   T beta;
   int M;
   int chunk;           // training points per workgroup
-  long long timeout;    // barrier wait limit in constant-clock ticks
+  long long timeout;    // wait limit for the record exchange, in constant-clock ticks
+  int p_in_lds;         // the slice's control points are staged in LDS
 };
 
 template <typename T>
@@ -72,6 +73,7 @@ __device__ __forceinline__ void rec_merge(Rec<T>& a, const Rec<T>& b) {
     a.minval = b.minval;
     a.a_at_min = b.a_at_min;
     a.minidx = b.minidx;
+    a.ymin = b.ymin;
   }
   if (b.maxidx >= 0 && (a.maxidx < 0 || b.maxval > a.maxval || (b.maxval == a.maxval && b.maxidx < a.maxidx))) {
     a.maxval = b.maxval;
@@ -91,7 +93,7 @@ __device__ __forceinline__ Rec<T> rec_empty() {
   r.minidx = -1;
   r.maxidx = -1;
   r.count = 0;
-  r.pad = 0;
+  r.ymin = 0;
   return r;
 }
 
@@ -105,7 +107,7 @@ __device__ __forceinline__ Rec<T> rec_shfl_down(const Rec<T>& r, int off) {
   o.minidx = __shfl_down(r.minidx, off);
   o.maxidx = __shfl_down(r.maxidx, off);
   o.count = __shfl_down(r.count, off);
-  o.pad = 0;
+  o.ymin = __shfl_down(r.ymin, off);
   return o;
 }
 
@@ -188,6 +190,7 @@ __device__ __forceinline__ void point_record(Rec<T>& r, int64_t j, T yj, T Fj, T
   c.minval = yj * Fj;
   c.a_at_min = aj;
   c.minidx = (int32_t)j;
+  c.ymin = yj > (T)0 ? 1 : -1;
   if (aj != (T)0) {
     c.maxval = yj * (Fj - aj);
     c.a_at_max = aj;
@@ -197,22 +200,106 @@ __device__ __forceinline__ void point_record(Rec<T>& r, int64_t j, T yj, T Fj, T
   rec_merge(r, c);
 }
 
+// Record exchange without a central barrier: each record is published as
+// 64-bit words, each holding 32 payload bits and the 32-bit sequence number of
+// the iteration. A word is stored and loaded with single-copy-atomic,
+// device-coherent 64-bit accesses, so a reader that sees the current
+// sequence number in every word of a record has the whole record; no fence
+// or read-modify-write is needed. Records are double-buffered by iteration
+// parity (a workgroup cannot publish iteration it + 2 before every workgroup
+// has published iteration it + 1, which each does only after reading
+// iteration it).
+template <typename T>
+struct RecWords;
+template <>
+struct RecWords<float> {
+  static constexpr int K = 8;
+  __device__ static uint32_t get(const Rec<float>& r, int k) {
+    switch (k) {
+      case 0: return __float_as_uint(r.minval);
+      case 1: return __float_as_uint(r.a_at_min);
+      case 2: return __float_as_uint(r.maxval);
+      case 3: return __float_as_uint(r.a_at_max);
+      case 4: return (uint32_t)r.minidx;
+      case 5: return (uint32_t)r.maxidx;
+      case 6: return (uint32_t)r.count;
+      default: return (uint32_t)r.ymin;
+    }
+  }
+  __device__ static Rec<float> make(const uint32_t* w) {
+    Rec<float> r;
+    r.minval = __uint_as_float(w[0]);
+    r.a_at_min = __uint_as_float(w[1]);
+    r.maxval = __uint_as_float(w[2]);
+    r.a_at_max = __uint_as_float(w[3]);
+    r.minidx = (int32_t)w[4];
+    r.maxidx = (int32_t)w[5];
+    r.count = (int32_t)w[6];
+    r.ymin = (int32_t)w[7];
+    return r;
+  }
+};
+template <>
+struct RecWords<double> {
+  static constexpr int K = 12;
+  __device__ static uint32_t half(double v, int hi) {
+    const uint64_t u = (uint64_t)__double_as_longlong(v);
+    return hi ? (uint32_t)(u >> 32) : (uint32_t)u;
+  }
+  __device__ static double join(uint32_t lo, uint32_t hi) {
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+  }
+  __device__ static uint32_t get(const Rec<double>& r, int k) {
+    switch (k) {
+      case 0: return half(r.minval, 0);
+      case 1: return half(r.minval, 1);
+      case 2: return half(r.a_at_min, 0);
+      case 3: return half(r.a_at_min, 1);
+      case 4: return half(r.maxval, 0);
+      case 5: return half(r.maxval, 1);
+      case 6: return half(r.a_at_max, 0);
+      case 7: return half(r.a_at_max, 1);
+      case 8: return (uint32_t)r.minidx;
+      case 9: return (uint32_t)r.maxidx;
+      case 10: return (uint32_t)r.count;
+      default: return (uint32_t)r.ymin;
+    }
+  }
+  __device__ static Rec<double> make(const uint32_t* w) {
+    Rec<double> r;
+    r.minval = join(w[0], w[1]);
+    r.a_at_min = join(w[2], w[3]);
+    r.maxval = join(w[4], w[5]);
+    r.a_at_max = join(w[6], w[7]);
+    r.minidx = (int32_t)w[8];
+    r.maxidx = (int32_t)w[9];
+    r.count = (int32_t)w[10];
+    r.ymin = (int32_t)w[11];
+    return r;
+  }
+};
+
 // One workgroup per slice; PT training points per thread, their y, alpha and
 // F held in registers for the whole run. Wave 0 leads: it publishes the
-// workgroup's record, meets the grid at the barrier, reduces every record and
-// broadcasts the decision (and the chosen point's control points) through LDS.
+// workgroup's record, gathers every workgroup's record of the same iteration,
+// reduces them and broadcasts the decision (and the chosen point's control
+// points) through LDS. Every workgroup reduces the same records in the same
+// way, so all take the same decision.
 template <typename T, int PT>
 __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
+  constexpr int K = RecWords<T>::K;
   __shared__ Rec<T> sh[16];
   __shared__ Decision<T> dec;
   __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
-  __shared__ int sh_ok;
+  extern __shared__ float pslice[];  // this slice's control points when they fit (st.p_in_lds)
   const unsigned G = gridDim.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t j0 = (int64_t)blockIdx.x * st.chunk;
   const int64_t j1 = (j0 + st.chunk < st.N) ? j0 + st.chunk : st.N;
   const int M = st.M;
-  unsigned gen = 0;
+  if (st.p_in_lds)
+    for (int64_t e = threadIdx.x; e < (j1 - j0) * 3 * M; e += blockDim.x) pslice[e] = st.P[j0 * 3 * M + e];
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(st.rec);  // [2][G][K]
 
   T y[PT], F[PT], a[PT];
   int64_t jj[PT];
@@ -241,34 +328,43 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
     if (wave == 0) {
       Rec<T> mine = sh[0];
       for (int w = 1; w < nw; ++w) rec_merge(mine, sh[w]);
-      Rec<T>* slot = st.rec + (it & 1) * G;
-      if (lane == 0) slot[blockIdx.x] = mine;
+      const unsigned long long seq = (unsigned long long)(uint32_t)(it + 1) << 32;
+      unsigned long long* slot = words + (size_t)(it & 1) * G * K;
+      if (lane < K)
+        __hip_atomic_store(slot + (size_t)blockIdx.x * K + lane, seq | RecWords<T>::get(mine, lane),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      // gather: lane l reads records l, l + 64, ...
+      Rec<T> gr = rec_empty<T>();
       bool ok = true;
-      if (lane == 0) {
-        __threadfence();
-        const unsigned g = gen;
-        const unsigned prev = __hip_atomic_fetch_add(&st.bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        if (prev == G - 1) {
-          __hip_atomic_store(&st.bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          __hip_atomic_store(&st.bar[1], g + 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        } else {
-          const long long t0 = wall_clock64();
-          while (__hip_atomic_load(&st.bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-            __builtin_amdgcn_s_sleep(1);
-            if (wall_clock64() - t0 > st.timeout) {
-              ok = false;
-              break;
+      for (unsigned base = 0; base < G; base += 64) {
+        const unsigned w = base + lane;
+        uint32_t pay[K];
+        bool ready = w >= G;
+        const long long t0 = wall_clock64();
+        while (true) {
+          if (!ready) {
+            ready = true;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              const unsigned long long v =
+                  __hip_atomic_load(slot + (size_t)w * K + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              pay[k] = (uint32_t)v;
+              ready = ready && ((v & 0xffffffff00000000ull) == seq);
             }
           }
+          if (__all(ready)) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (wall_clock64() - t0 > st.timeout) {
+            ok = false;
+            break;
+          }
         }
-        __threadfence();
-        gen = g + 1u;
-        sh_ok = ok ? 1 : 0;
+        if (!__all(ok)) {
+          ok = false;
+          break;
+        }
+        if (w < G) rec_merge(gr, RecWords<T>::make(pay));
       }
-      __builtin_amdgcn_wave_barrier();
-      ok = __shfl(ok ? 1 : 0, 0) != 0;
-      Rec<T> gr = rec_empty<T>();
-      for (unsigned w = lane; w < G; w += 64) rec_merge(gr, slot[w]);
       gr = wave_reduce(gr);
       gr.minval = __shfl(gr.minval, 0);
       gr.a_at_min = __shfl(gr.a_at_min, 0);
@@ -277,6 +373,7 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
       gr.minidx = __shfl(gr.minidx, 0);
       gr.maxidx = __shfl(gr.maxidx, 0);
       gr.count = __shfl(gr.count, 0);
+      gr.ymin = __shfl(gr.ymin, 0);
       Decision<T> d;
       d.action = 0;
       d.i = -1;
@@ -287,7 +384,7 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
         d.action = 3;
       } else if (gr.minidx >= 0 && gr.minval <= (T)0 && ((int64_t)gr.count < st.s_max || gr.a_at_min != (T)0)) {
         d.i = gr.minidx;
-        const T yi = (T)st.y[d.i];
+        const T yi = (T)gr.ymin;
         const T Fi = yi * gr.minval;          // y = +-1: y (y F) = F exactly
         const T bi = yi > 0 ? st.beta : (T)1;  // b_i = beta^(0.5 (y_i + 1)), Eq. 5
         d.dalpha = sub_rn(bi * yi, Fi);        // Eq. 6
@@ -318,7 +415,9 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
       if (jj[k] < j1) {
-        const T kv = kfk_pair(st.P + jj[k] * (int64_t)M * 3, pi_sh, M, st.half_g);
+        // index the LDS slice relative to its own start (pointer arithmetic stays inside each object)
+        const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)M * 3 : st.P + jj[k] * (int64_t)M * 3;
+        const T kv = kfk_pair(pj, pi_sh, M, st.half_g);
         F[k] = axpy_rn(d.dalpha, kv, F[k]);
         if (jj[k] == d.i) a[k] = (d.action == 1) ? a[k] + d.dalpha : (T)0;  // Eq. 7 / removal
         point_record(r, jj[k], y[k], F[k], a[k]);
@@ -340,8 +439,10 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
   }
 }
 
-__global__ void k_train_init(unsigned* bar, int64_t* out) {
-  if (threadIdx.x < 2) {
+__global__ void k_train_init(unsigned long long* words, int64_t nwords, unsigned* bar, int64_t* out) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i < nwords) words[i] = 0ull;
+  if (blockIdx.x == 0 && threadIdx.x < 2) {
     bar[threadIdx.x] = 0u;
     out[threadIdx.x] = 0;
   }
@@ -426,18 +527,22 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     case 8: kfn = reinterpret_cast<const void*>(k_train<T, 8>); break;
     default: kfn = reinterpret_cast<const void*>(k_train<T, 16>); break;
   }
+  // stage each slice's control points in LDS when they fit (48 KB budget)
+  size_t lds_bytes = (size_t)chunk * 3 * M * sizeof(float);
+  if (lds_bytes > 48 * 1024) lds_bytes = 0;
   int per_cu = 0;
-  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, 0));
+  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
   if (per_cu < 1) return fail(FASTRON_EUNSUPPORTED, "training kernel cannot be resident with %d threads", threads);
 
-  const size_t rec_bytes = sizeof(Rec<T>) * 2 * (size_t)G;
+  const size_t rec_bytes = ((sizeof(unsigned long long) * 2 * (size_t)G * RecWords<T>::K + 255) / 256) * 256;
   char* ws = nullptr;
   FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), rec_bytes + 256 + 256, s));
-  Rec<T>* rec = reinterpret_cast<Rec<T>*>(ws);
+  Rec<T>* rec = reinterpret_cast<Rec<T>*>(ws);  // reinterpreted as record words by the kernel
   unsigned* bar = reinterpret_cast<unsigned*>(ws + rec_bytes);
   int64_t* out = reinterpret_cast<int64_t*>(ws + rec_bytes + 64);
   int64_t* cnt = reinterpret_cast<int64_t*>(ws + rec_bytes + 128);
-  hipLaunchKernelGGL(k_train_init, dim3(1), dim3(64), 0, s, bar, out);
+  hipLaunchKernelGGL(k_train_init, dim3((unsigned)((rec_bytes / 8 + 255) / 256)), dim3(256), 0, s,
+                     reinterpret_cast<unsigned long long*>(ws), (int64_t)(rec_bytes / 8), bar, out);
   fastron_status rs = FASTRON_OK;
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
@@ -460,8 +565,9 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     st.M = M;
     st.chunk = (int)chunk;
     st.timeout = 400000000ll;  // 4 s at 100 MHz
+    st.p_in_lds = lds_bytes > 0 ? 1 : 0;
     void* args[] = {&st};
-    e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3((unsigned)threads), args, 0, s);
+    e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3((unsigned)threads), args, lds_bytes, s);
   }
   if (e == hipSuccess) {
     hipLaunchKernelGGL(k_compact<T>, dim3(1), dim3(1024), 0, s, alpha, N, support_idx, cnt);
