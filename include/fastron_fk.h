@@ -163,6 +163,35 @@ fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int
                                  int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
                                  int64_t trace_cap, void* stream);
 
+/* ---- a7: batched form ----------------------------------------------------
+ * E environments share one arm (chain + control points); environment e has
+ * its own Fastron model (supports support_off[e] .. support_off[e+1] - 1 of
+ * the concatenated support arrays) and its own queries (query_off[e] ..
+ * query_off[e+1] - 1 of the concatenated query array). Offsets are HOST
+ * arrays of E + 1 non-decreasing int64 starting at 0; they are copied.
+ *   fastron_batch_create    allocates the batch's device buffers (synchronous)
+ *   fastron_batch_prepare   support_q [S_total][n], alpha [S_total] (device)
+ *   fastron_batch_score     scores q [N_total][n] into f / label [N_total] in
+ *                           ONE persistent launch (work items claimed in
+ *                           longest-first order from a device counter)
+ *   fastron_batch_autotune  times the work-item shapes (16, 32, 64 queries)
+ *                           on these arguments and keeps the fastest; syncs
+ *   fastron_batch_capture   records {counter reset, scoring launch} with these
+ *                           pointers into a HIP graph on `stream` (non-null)
+ *   fastron_batch_replay    launches the captured graph
+ * Results equal fastron_fk_score_prepared on each environment's model.     */
+typedef struct fastron_batch fastron_batch;
+fastron_status fastron_batch_create(const fastron_chain* chain, const fastron_cpoints* cp, int32_t E,
+                                    const int64_t* support_off, const int64_t* query_off, float gamma,
+                                    fastron_batch** out);
+fastron_status fastron_batch_prepare(fastron_batch* batch, const float* support_q, const float* alpha, void* stream);
+fastron_status fastron_batch_score(fastron_batch* batch, const float* q, float* f, int8_t* label, void* stream);
+fastron_status fastron_batch_autotune(fastron_batch* batch, const float* q, float* f, int8_t* label, void* stream);
+fastron_status fastron_batch_capture(fastron_batch* batch, const float* q, float* f, int8_t* label, void* stream);
+fastron_status fastron_batch_replay(fastron_batch* batch, void* stream);
+int32_t fastron_batch_tile_queries(const fastron_batch* batch);
+void fastron_batch_destroy(fastron_batch* batch);
+
 /* ---- a9: geometric labels -------------------------------------------------
  * Stands in for the ground-truth collision checker of Section IV: link i is a
  * capsule of radius `radius` around the segment between the origins of

@@ -33,7 +33,9 @@ BF16_SPLIT3 = 0x20
 EXPORTED = [
     "fastron_fk_points", "fastron_model_bytes", "fastron_support_prep", "fastron_fk_score_prepared",
     "fastron_fk_score", "fastron_gram_update", "fastron_train", "fastron_train_f64", "fastron_label_capsule_box",
-    "fastron_tune_set", "fastron_tune_get", "fastron_last_error", "fastron_version",
+    "fastron_tune_set", "fastron_tune_get", "fastron_last_error", "fastron_version", "fastron_batch_create",
+    "fastron_batch_prepare", "fastron_batch_score", "fastron_batch_autotune", "fastron_batch_capture",
+    "fastron_batch_replay", "fastron_batch_tile_queries", "fastron_batch_destroy",
 ]
 
 
@@ -89,6 +91,14 @@ def lib():
         "fastron_train": ([vp, vp, i64, i32, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp], i32),
         "fastron_train_f64": ([vp, vp, i64, i32, f64, f64, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp], i32),
         "fastron_label_capsule_box": ([ch, vp, i64, f64, vp, i32, vp, vp, vp], i32),
+        "fastron_batch_create": ([ch, cp, i32, pi64, pi64, f32, ctypes.POINTER(vp)], i32),
+        "fastron_batch_prepare": ([vp, vp, vp, vp], i32),
+        "fastron_batch_score": ([vp, vp, vp, vp, vp], i32),
+        "fastron_batch_autotune": ([vp, vp, vp, vp, vp], i32),
+        "fastron_batch_capture": ([vp, vp, vp, vp, vp], i32),
+        "fastron_batch_replay": ([vp, vp], i32),
+        "fastron_batch_tile_queries": ([vp], i32),
+        "fastron_batch_destroy": ([vp], None),
         "fastron_tune_set": ([ctypes.c_char_p, i64], i32),
         "fastron_tune_get": ([ctypes.c_char_p], i64),
         "fastron_last_error": ([], ctypes.c_char_p),

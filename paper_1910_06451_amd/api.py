@@ -16,7 +16,7 @@ from ._native import HostChain, check
 
 __all__ = [
     "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train",
-    "label_capsule_box", "PreparedModel", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
+    "label_capsule_box", "PreparedModel", "Batch", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
 
@@ -194,3 +194,82 @@ def label_capsule_box(arm, q: torch.Tensor, radius: float, boxes_lo, boxes_hi, w
     check(nat.lib().fastron_label_capsule_box(ctypes.byref(hc.chain), _ptr(q), N, float(radius), _ptr(boxes),
                                               boxes.shape[0], _ptr(lab), _ptr(clr), _stream()))
     return lab, clr
+
+
+class Batch:
+    """Many environments' models (one arm) scored in one persistent launch (the batched form).
+
+    support_counts[e] / query_counts[e] give each environment's support-set and query-batch sizes; the support
+    configurations, weights and queries are the concatenation over environments in that order.
+    """
+
+    def __init__(self, arm, support_counts, query_counts, gamma: float):
+        self.hc = _chain(arm)
+        sc = np.asarray(support_counts, dtype=np.int64)
+        qc = np.asarray(query_counts, dtype=np.int64)
+        if sc.shape != qc.shape or sc.ndim != 1:
+            raise ValueError("support_counts and query_counts must be 1-D and of equal length")
+        self.E = int(sc.shape[0])
+        self.support_off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(sc)]).astype(np.int64))
+        self.query_off = np.ascontiguousarray(np.concatenate([[0], np.cumsum(qc)]).astype(np.int64))
+        self.S_total = int(self.support_off[-1])
+        self.N_total = int(self.query_off[-1])
+        self.gamma = float(gamma)
+        h = ctypes.c_void_p()
+        lp = ctypes.POINTER(ctypes.c_int64)
+        check(nat.lib().fastron_batch_create(ctypes.byref(self.hc.chain), ctypes.byref(self.hc.cpoints), self.E,
+                                             self.support_off.ctypes.data_as(lp), self.query_off.ctypes.data_as(lp),
+                                             self.gamma, ctypes.byref(h)))
+        self._h = h
+        self._keep = None
+
+    def prepare(self, support_q: torch.Tensor, alpha: torch.Tensor):
+        _dev(support_q, torch.float32, "support_q")
+        _dev(alpha, torch.float32, "alpha")
+        if support_q.shape != (self.S_total, self.hc.n) or alpha.shape != (self.S_total,):
+            raise ValueError(f"support_q must be ({self.S_total}, {self.hc.n}) and alpha ({self.S_total},)")
+        check(nat.lib().fastron_batch_prepare(self._h, _ptr(support_q), _ptr(alpha), _stream()))
+        self._keep = (support_q, alpha)
+
+    def _io(self, q, out):
+        _dev(q, torch.float32, "q")
+        if q.shape != (self.N_total, self.hc.n):
+            raise ValueError(f"q must be ({self.N_total}, {self.hc.n})")
+        if out is None:
+            out = (torch.empty(self.N_total, dtype=torch.float32, device=q.device),
+                   torch.empty(self.N_total, dtype=torch.int8, device=q.device))
+        return out
+
+    def score(self, q: torch.Tensor, out=None):
+        f, lab = self._io(q, out)
+        check(nat.lib().fastron_batch_score(self._h, _ptr(q), _ptr(f), _ptr(lab), _stream()))
+        return f, lab
+
+    def autotune(self, q: torch.Tensor, out=None) -> int:
+        f, lab = self._io(q, out)
+        check(nat.lib().fastron_batch_autotune(self._h, _ptr(q), _ptr(f), _ptr(lab), _stream()))
+        return self.tile_queries
+
+    @property
+    def tile_queries(self) -> int:
+        return int(nat.lib().fastron_batch_tile_queries(self._h))
+
+    def capture(self, q: torch.Tensor, out):
+        """Record {counter reset, scoring launch} for these exact buffers on the current (non-default) stream."""
+        f, lab = self._io(q, out)
+        check(nat.lib().fastron_batch_capture(self._h, _ptr(q), _ptr(f), _ptr(lab), _stream()))
+        self._graph_io = (q, f, lab)
+
+    def replay(self):
+        check(nat.lib().fastron_batch_replay(self._h, _stream()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            nat.lib().fastron_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -124,6 +124,12 @@ __device__ __forceinline__ void fk_walk(const ChainArgs& c, const float* q, Emit
   }
 }
 
+// Batched support preparation (fk.hip): FP32 tiles of E support sets and the
+// per-environment fixed-point terms.
+fastron_status launch_prep_batched(const ChainArgs& c, const float* sq, const float* alpha,
+                                   const int64_t* support_off_d, const int64_t* tile_off_d, int E,
+                                   int64_t total_tiles, float gamma, float* tiles, float* f_const, hipStream_t s);
+
 // Threshold from which the chain product runs in FP64.
 constexpr int kFp64Joints = 7;
 

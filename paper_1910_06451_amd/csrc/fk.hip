@@ -131,43 +131,36 @@ __device__ __forceinline__ void bf16_split(float v, int parts, uint16_t out[3]) 
   }
 }
 
+// Writes one support configuration (or a padding row when sq_row is NULL) as
+// row `sl` of its tile T; V (VALU rows) and B16 (bf16 operand of the tile)
+// are optional.
 template <typename R>
-__global__ void __launch_bounds__(256) k_support_prep(ChainArgs c, const float* __restrict__ sq,
-                                                       const float* __restrict__ alpha, int64_t S, int64_t ntiles,
-                                                       float gamma, char* __restrict__ blob) {
-  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (s >= ntiles * kTile) return;
-  const int Mp = (c.M + 3) & ~3;
-  const int64_t tile = s / kTile;
-  const int sl = (int)(s % kTile);
-  float* tiles = reinterpret_cast<float*>(blob + kHeaderBytes);
-  float* T = tiles + tile * tile_floats(Mp);
+__device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq_row, float alpha_s, float gamma,
+                                             float* __restrict__ T, int sl, int Mp, float* __restrict__ V,
+                                             uint16_t* __restrict__ B16) {
   float* A = T;                          // [4][16][Mp]
   float* C = T + tile_c_offset(Mp);      // [4][Mp][4]
   float* W = T + tile_w_offset(Mp);      // [16]
-  const int64_t S_pad = ntiles * kTile;
-  float* V = reinterpret_cast<float*>(blob + kHeaderBytes + ntiles * tile_floats(Mp) * 4) + s * Mp * 4;
-  uint16_t* B16 = reinterpret_cast<uint16_t*>(blob + kHeaderBytes + ntiles * tile_floats(Mp) * 4 +
-                                              S_pad * Mp * 4 * 4) +
-                  tile * (int64_t)Mp * 512;
-  const int g_of = sl;  // row of this support inside its tile
-  // defaults: padding / unused slots contribute nothing
+  // defaults: padding and unused slots contribute nothing
   for (int m = 0; m < Mp; ++m) {
     A[(0 * 16 + sl) * Mp + m] = 0.f;
     A[(1 * 16 + sl) * Mp + m] = 0.f;
     A[(2 * 16 + sl) * Mp + m] = 0.f;
     A[(3 * 16 + sl) * Mp + m] = 1.f;
-    C[((g_of >> 2) * Mp + m) * 4 + (g_of & 3)] = 0.f;
-    V[m * 4 + 0] = 0.f; V[m * 4 + 1] = 0.f; V[m * 4 + 2] = 0.f; V[m * 4 + 3] = 0.f;
+    C[((sl >> 2) * Mp + m) * 4 + (sl & 3)] = 0.f;
+    if (V) {
+      V[m * 4 + 0] = 0.f; V[m * 4 + 1] = 0.f; V[m * 4 + 2] = 0.f; V[m * 4 + 3] = 0.f;
+    }
     // bf16 A operand: row sl, k = 0..31, stored as [g][s][8] per m
-    for (int k = 0; k < 32; ++k) B16[(int64_t)m * 512 + ((k >> 3) * 16 + sl) * 8 + (k & 7)] = 0;
+    if (B16)
+      for (int k = 0; k < 32; ++k) B16[(int64_t)m * 512 + ((k >> 3) * 16 + sl) * 8 + (k & 7)] = 0;
   }
   W[sl] = 0.f;
-  if (s >= S) return;
+  if (!sq_row) return;
   float qv[FASTRON_MAX_JOINTS];
 #pragma unroll
   for (int i = 0; i < FASTRON_MAX_JOINTS; ++i)
-    if (i < c.n) qv[i] = sq[s * c.n + i];
+    if (i < c.n) qv[i] = sq_row[i];
   const float half_g = 0.5f * gamma;
   fk_walk<R>(c, qv, [&](int m, float x, float y, float z) {
     const int slot = c.slot[m];
@@ -177,38 +170,124 @@ __global__ void __launch_bounds__(256) k_support_prep(ChainArgs c, const float* 
     A[(0 * 16 + sl) * Mp + slot] = ax;
     A[(1 * 16 + sl) * Mp + slot] = ay;
     A[(2 * 16 + sl) * Mp + slot] = az;
-    C[((g_of >> 2) * Mp + slot) * 4 + (g_of & 3)] = cs;
-    V[slot * 4 + 0] = ax; V[slot * 4 + 1] = ay; V[slot * 4 + 2] = az; V[slot * 4 + 3] = cs;
-    // bf16 cross-term operand: -gamma p' split into hi + mid + lo bf16 terms, laid out so that the query
-    // side selects the precision: k0-2 hi, k3-5 hi, k6-8 mid, k9-11 hi, k12-14 lo, k15-17 mid, k18-20 = 1
-    // (the query side puts hi/mid/lo of p against them, and the three bf16 parts of c_q against the ones).
-    uint16_t sx[3], sy[3], sz[3];
-    bf16_split(ax, 3, sx);
-    bf16_split(ay, 3, sy);
-    bf16_split(az, 3, sz);
-    uint16_t* row = B16 + (int64_t)slot * 512;
-    auto put = [&](int k, uint16_t v) { row[((k >> 3) * 16 + sl) * 8 + (k & 7)] = v; };
-    auto put3 = [&](int k0, int part) { put(k0, sx[part]); put(k0 + 1, sy[part]); put(k0 + 2, sz[part]); };
-    put3(0, 0); put3(3, 0); put3(6, 1); put3(9, 0); put3(12, 2); put3(15, 1);
-    const uint16_t one = 0x3f80;
-    put(18, one); put(19, one); put(20, one);
+    C[((sl >> 2) * Mp + slot) * 4 + (sl & 3)] = cs;
+    if (V) {
+      V[slot * 4 + 0] = ax; V[slot * 4 + 1] = ay; V[slot * 4 + 2] = az; V[slot * 4 + 3] = cs;
+    }
+    if (B16) {
+      // bf16 cross-term operand: -gamma p' split into hi + mid + lo bf16 terms, laid out so that the query
+      // side selects the precision: k0-2 hi, k3-5 hi, k6-8 mid, k9-11 hi, k12-14 lo, k15-17 mid, k18-20 = 1
+      // (the query side puts hi/mid/lo of p against them, and the three bf16 parts of c_q against the ones).
+      uint16_t sx[3], sy[3], sz[3];
+      bf16_split(ax, 3, sx);
+      bf16_split(ay, 3, sy);
+      bf16_split(az, 3, sz);
+      uint16_t* row = B16 + (int64_t)slot * 512;
+      auto put = [&](int k, uint16_t v) { row[((k >> 3) * 16 + sl) * 8 + (k & 7)] = v; };
+      auto put3 = [&](int k0, int part) { put(k0, sx[part]); put(k0 + 1, sy[part]); put(k0 + 2, sz[part]); };
+      put3(0, 0); put3(3, 0); put3(6, 1); put3(9, 0); put3(12, 2); put3(15, 1);
+      const uint16_t one = 0x3f80;
+      put(18, one); put(19, one); put(20, one);
+    }
   });
-  W[sl] = alpha[s] / (float)c.M;
+  W[sl] = alpha_s / (float)c.M;
 }
 
-// f_const = (#fixed points / M) * sum_s alpha_s, summed by one block in a fixed order.
-__global__ void __launch_bounds__(1024) k_fixed_term(const float* __restrict__ alpha, int64_t S, float scale,
-                                                      float* __restrict__ header) {
-  __shared__ float part[1024];
+template <typename R>
+__global__ void __launch_bounds__(256) k_support_prep(ChainArgs c, const float* __restrict__ sq,
+                                                       const float* __restrict__ alpha, int64_t S, int64_t ntiles,
+                                                       float gamma, char* __restrict__ blob) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= ntiles * kTile) return;
+  const int Mp = (c.M + 3) & ~3;
+  const int64_t tile = s / kTile;
+  const int sl = (int)(s % kTile);
+  float* T = reinterpret_cast<float*>(blob + kHeaderBytes) + tile * tile_floats(Mp);
+  const int64_t S_pad = ntiles * kTile;
+  float* V = reinterpret_cast<float*>(blob + kHeaderBytes + ntiles * tile_floats(Mp) * 4) + s * Mp * 4;
+  uint16_t* B16 = reinterpret_cast<uint16_t*>(blob + kHeaderBytes + ntiles * tile_floats(Mp) * 4 +
+                                              S_pad * Mp * 4 * 4) +
+                  tile * (int64_t)Mp * 512;
+  const bool real = s < S;
+  prep_support<R>(c, real ? sq + s * c.n : nullptr, real ? alpha[s] : 0.f, gamma, T, sl, Mp, V, B16);
+}
+
+// Batched form: E support sets concatenated (support_off[E + 1]), each padded
+// to whole tiles (tile_off[E + 1]); FP32 tiles only. One thread per padded row.
+template <typename R>
+__global__ void __launch_bounds__(256) k_support_prep_batched(ChainArgs c, const float* __restrict__ sq,
+                                                               const float* __restrict__ alpha,
+                                                               const int64_t* __restrict__ support_off,
+                                                               const int64_t* __restrict__ tile_off, int E,
+                                                               float gamma, float* __restrict__ tiles) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total_tiles = tile_off[E];
+  if (p >= total_tiles * kTile) return;
+  const int Mp = (c.M + 3) & ~3;
+  const int64_t tile = p / kTile;
+  const int sl = (int)(p % kTile);
+  int lo = 0, hi = E;  // largest e with tile_off[e] <= tile
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (tile_off[mid] <= tile) lo = mid; else hi = mid;
+  }
+  const int64_t s = support_off[lo] + (tile - tile_off[lo]) * kTile + sl;
+  const bool real = s < support_off[lo + 1];
+  prep_support<R>(c, real ? sq + s * c.n : nullptr, real ? alpha[s] : 0.f, gamma,
+                  tiles + tile * tile_floats(Mp), sl, Mp, nullptr, nullptr);
+}
+
+// sum of alpha[s0..s1) by one 256-thread block in a fixed order (strided
+// partial sums, then a tree); shared by the single-model and batched forms so
+// that both produce the same bits.
+__device__ __forceinline__ float block_alpha_sum(const float* __restrict__ alpha, int64_t s0, int64_t s1,
+                                                 float* part) {
   float acc = 0.f;
-  for (int64_t s = threadIdx.x; s < S; s += 1024) acc += alpha[s];
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += 256) acc += alpha[s];
   part[threadIdx.x] = acc;
   __syncthreads();
-  for (int w = 512; w > 0; w >>= 1) {
+  for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) header[0] = part[0] * scale;
+  return part[0];
+}
+
+// Per-environment fixed-point term: one block per environment.
+__global__ void __launch_bounds__(256) k_fixed_term_batched(const float* __restrict__ alpha,
+                                                            const int64_t* __restrict__ support_off, float scale,
+                                                            float* __restrict__ f_const) {
+  __shared__ float part[256];
+  const int e = blockIdx.x;
+  const float sum = block_alpha_sum(alpha, support_off[e], support_off[e + 1], part);
+  if (threadIdx.x == 0) f_const[e] = sum * scale;
+}
+
+fastron_status launch_prep_batched(const ChainArgs& c, const float* sq, const float* alpha,
+                                   const int64_t* support_off_d, const int64_t* tile_off_d, int E,
+                                   int64_t total_tiles, float gamma, float* tiles, float* f_const, hipStream_t s) {
+  if (total_tiles > 0) {
+    const unsigned blocks = (unsigned)((total_tiles * kTile + 255) / 256);
+    if (c.n >= kFp64Joints)
+      hipLaunchKernelGGL(k_support_prep_batched<double>, dim3(blocks), dim3(256), 0, s, c, sq, alpha, support_off_d,
+                         tile_off_d, E, gamma, tiles);
+    else
+      hipLaunchKernelGGL(k_support_prep_batched<float>, dim3(blocks), dim3(256), 0, s, c, sq, alpha, support_off_d,
+                         tile_off_d, E, gamma, tiles);
+    FASTRON_HIP(hipGetLastError());
+  }
+  const float scale = (float)(c.M - c.Mm) / (float)c.M;
+  hipLaunchKernelGGL(k_fixed_term_batched, dim3((unsigned)E), dim3(256), 0, s, alpha, support_off_d, scale, f_const);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+// f_const = (#fixed points / M) * sum_s alpha_s.
+__global__ void __launch_bounds__(256) k_fixed_term(const float* __restrict__ alpha, int64_t S, float scale,
+                                                     float* __restrict__ header) {
+  __shared__ float part[256];
+  const float sum = block_alpha_sum(alpha, 0, S, part);
+  if (threadIdx.x == 0) header[0] = sum * scale;
 }
 
 __global__ void k_zero_header(float* header) {
@@ -285,7 +364,7 @@ fastron_status fastron_support_prep(const fastron_chain* chain, const fastron_cp
     FASTRON_HIP(hipGetLastError());
   }
   if (S > 0 && c.Mm < c.M) {
-    hipLaunchKernelGGL(k_fixed_term, dim3(1), dim3(1024), 0, s, alpha, S, (float)(c.M - c.Mm) / (float)c.M,
+    hipLaunchKernelGGL(k_fixed_term, dim3(1), dim3(256), 0, s, alpha, S, (float)(c.M - c.Mm) / (float)c.M,
                        reinterpret_cast<float*>(blob));
     FASTRON_HIP(hipGetLastError());
   }
