@@ -192,6 +192,40 @@ fastron_status fastron_batch_replay(fastron_batch* batch, void* stream);
 int32_t fastron_batch_tile_queries(const fastron_batch* batch);
 void fastron_batch_destroy(fastron_batch* batch);
 
+/* ---- a8: learned screening ---------------------------------------------
+ * A small network on the FK control points: 3M inputs -> H -> H -> 1 logit
+ * (ReLU), BF16 matrix-core GEMMs with FP32 accumulation, FP32 master
+ * weights, BCE-with-logits loss (label +1 = collision is the positive class),
+ * Adam (beta1 0.9, beta2 0.999, eps 1e-8). Not part of the paper's method.
+ * Parameters are one FP32 device vector in the order
+ *   W1 [3M][H], b1 [H], W2 [H][H], b2 [H], w3 [H], b3 [1]
+ * (fastron_mlp_param_count values); inputs are standardised by per-feature
+ * mu / sd (device [3M]) before the first layer. Rows of P are the
+ * [M][3] control points of fastron_fk_points. max_rows bounds one batch.
+ * fastron_mlp_screen: queries with |logit| >= tau take sign(logit); the rest
+ * (fell_back[j] = 1) take the sign of the Fastron FK score against `model`
+ * (computed on the compacted subset). workspace: device memory of
+ * fastron_mlp_screen_workspace_bytes(N, n) bytes. The call synchronises.  */
+typedef struct fastron_mlp fastron_mlp;
+fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows, fastron_mlp** out);
+void fastron_mlp_destroy(fastron_mlp* net);
+int64_t fastron_mlp_param_count(const fastron_mlp* net);
+fastron_status fastron_mlp_set_params(fastron_mlp* net, const float* params, const float* mu, const float* sd,
+                                      void* stream);
+fastron_status fastron_mlp_get_params(const fastron_mlp* net, float* params, float* grads, float* mu, float* sd,
+                                      void* stream);
+fastron_status fastron_mlp_fit_standardisation(fastron_mlp* net, const float* P, int64_t N, void* stream);
+fastron_status fastron_mlp_forward(fastron_mlp* net, const float* P, int64_t N, float* logits, void* stream);
+fastron_status fastron_mlp_gradients(fastron_mlp* net, const float* P, const int8_t* y, int64_t N, float* loss,
+                                     void* stream);
+fastron_status fastron_mlp_train_epoch(fastron_mlp* net, const float* P, const int8_t* y, const int32_t* order,
+                                       int64_t N, int64_t batch, float lr, float* mean_loss, void* stream);
+fastron_status fastron_mlp_screen(fastron_mlp* net, const fastron_chain* chain, const fastron_cpoints* cp,
+                                  const fastron_model* model, const float* q, int64_t N, float tau, float* logits,
+                                  int8_t* label, uint8_t* fell_back, int64_t* n_fallback, void* workspace,
+                                  int64_t workspace_bytes, void* stream);
+int64_t fastron_mlp_screen_workspace_bytes(int64_t N, int32_t n_joints);
+
 /* ---- a9: geometric labels -------------------------------------------------
  * Stands in for the ground-truth collision checker of Section IV: link i is a
  * capsule of radius `radius` around the segment between the origins of

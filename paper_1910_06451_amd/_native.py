@@ -35,7 +35,10 @@ EXPORTED = [
     "fastron_fk_score", "fastron_gram_update", "fastron_train", "fastron_train_f64", "fastron_label_capsule_box",
     "fastron_tune_set", "fastron_tune_get", "fastron_last_error", "fastron_version", "fastron_batch_create",
     "fastron_batch_prepare", "fastron_batch_score", "fastron_batch_autotune", "fastron_batch_capture",
-    "fastron_batch_replay", "fastron_batch_tile_queries", "fastron_batch_destroy",
+    "fastron_batch_replay", "fastron_batch_tile_queries", "fastron_batch_destroy", "fastron_mlp_create",
+    "fastron_mlp_destroy", "fastron_mlp_param_count", "fastron_mlp_set_params", "fastron_mlp_get_params",
+    "fastron_mlp_fit_standardisation", "fastron_mlp_forward", "fastron_mlp_gradients", "fastron_mlp_train_epoch",
+    "fastron_mlp_screen", "fastron_mlp_screen_workspace_bytes",
 ]
 
 
@@ -99,6 +102,17 @@ def lib():
         "fastron_batch_replay": ([vp, vp], i32),
         "fastron_batch_tile_queries": ([vp], i32),
         "fastron_batch_destroy": ([vp], None),
+        "fastron_mlp_create": ([i32, i32, i64, ctypes.POINTER(vp)], i32),
+        "fastron_mlp_destroy": ([vp], None),
+        "fastron_mlp_param_count": ([vp], i64),
+        "fastron_mlp_set_params": ([vp, vp, vp, vp, vp], i32),
+        "fastron_mlp_get_params": ([vp, vp, vp, vp, vp, vp], i32),
+        "fastron_mlp_fit_standardisation": ([vp, vp, i64, vp], i32),
+        "fastron_mlp_forward": ([vp, vp, i64, vp, vp], i32),
+        "fastron_mlp_gradients": ([vp, vp, vp, i64, ctypes.POINTER(ctypes.c_float), vp], i32),
+        "fastron_mlp_train_epoch": ([vp, vp, vp, vp, i64, i64, f32, ctypes.POINTER(ctypes.c_float), vp], i32),
+        "fastron_mlp_screen": ([vp, ch, cp, md, vp, i64, f32, vp, vp, vp, pi64, vp, i64, vp], i32),
+        "fastron_mlp_screen_workspace_bytes": ([i64, i32], i64),
         "fastron_tune_set": ([ctypes.c_char_p, i64], i32),
         "fastron_tune_get": ([ctypes.c_char_p], i64),
         "fastron_last_error": ([], ctypes.c_char_p),

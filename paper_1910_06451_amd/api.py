@@ -16,7 +16,7 @@ from ._native import HostChain, check
 
 __all__ = [
     "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train",
-    "label_capsule_box", "PreparedModel", "Batch", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
+    "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
 
@@ -266,6 +266,95 @@ class Batch:
     def close(self):
         if getattr(self, "_h", None):
             nat.lib().fastron_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class MLP:
+    """Learned pre-screen on FK control points: 3M -> H -> H -> 1 (BF16 MFMA, FP32 masters, Adam)."""
+
+    def __init__(self, d_in: int, hidden: int = 256, max_rows: int = 8192):
+        h = ctypes.c_void_p()
+        check(nat.lib().fastron_mlp_create(int(d_in), int(hidden), int(max_rows), ctypes.byref(h)))
+        self._h = h
+        self.d_in, self.hidden, self.max_rows = int(d_in), int(hidden), int(max_rows)
+        self.n_params = int(nat.lib().fastron_mlp_param_count(h))
+
+    def set_params(self, params: torch.Tensor, mu: torch.Tensor | None = None, sd: torch.Tensor | None = None):
+        _dev(params, torch.float32, "params")
+        if params.shape != (self.n_params,):
+            raise ValueError(f"params must be ({self.n_params},)")
+        for t, nm in ((mu, "mu"), (sd, "sd")):
+            if t is not None:
+                _dev(t, torch.float32, nm)
+        check(nat.lib().fastron_mlp_set_params(self._h, _ptr(params), _ptr(mu), _ptr(sd), _stream()))
+
+    def get_params(self, device):
+        p = torch.empty(self.n_params, dtype=torch.float32, device=device)
+        g = torch.empty(self.n_params, dtype=torch.float32, device=device)
+        mu = torch.empty(self.d_in, dtype=torch.float32, device=device)
+        sd = torch.empty(self.d_in, dtype=torch.float32, device=device)
+        check(nat.lib().fastron_mlp_get_params(self._h, _ptr(p), _ptr(g), _ptr(mu), _ptr(sd), _stream()))
+        return p, g, mu, sd
+
+    def _points(self, P):
+        _dev(P, torch.float32, "P")
+        if P.dim() != 3 or P.shape[1] * P.shape[2] != self.d_in:
+            raise ValueError(f"P must be (N, M, 3) with 3M = {self.d_in}")
+        return P
+
+    def fit_standardisation(self, P: torch.Tensor):
+        self._points(P)
+        check(nat.lib().fastron_mlp_fit_standardisation(self._h, _ptr(P), P.shape[0], _stream()))
+
+    def forward(self, P: torch.Tensor) -> torch.Tensor:
+        self._points(P)
+        z = torch.empty(P.shape[0], dtype=torch.float32, device=P.device)
+        check(nat.lib().fastron_mlp_forward(self._h, _ptr(P), P.shape[0], _ptr(z), _stream()))
+        return z
+
+    def gradients(self, P: torch.Tensor, y: torch.Tensor) -> float:
+        self._points(P)
+        _dev(y, torch.int8, "y")
+        loss = ctypes.c_float(0.0)
+        check(nat.lib().fastron_mlp_gradients(self._h, _ptr(P), _ptr(y), P.shape[0], ctypes.byref(loss), _stream()))
+        return float(loss.value)
+
+    def train_epoch(self, P: torch.Tensor, y: torch.Tensor, order: torch.Tensor | None = None, batch: int = 8192,
+                    lr: float = 1e-3) -> float:
+        self._points(P)
+        _dev(y, torch.int8, "y")
+        if order is not None:
+            _dev(order, torch.int32, "order")
+        loss = ctypes.c_float(0.0)
+        check(nat.lib().fastron_mlp_train_epoch(self._h, _ptr(P), _ptr(y), _ptr(order), P.shape[0], int(batch),
+                                                float(lr), ctypes.byref(loss), _stream()))
+        return float(loss.value)
+
+    def screen(self, arm, model: "PreparedModel", q: torch.Tensor, tau: float):
+        """Returns (label int8, logit float32, fell_back uint8, n_fallback)."""
+        hc = _chain(arm)
+        _dev(q, torch.float32, "q")
+        N = q.shape[0]
+        lab = torch.empty(N, dtype=torch.int8, device=q.device)
+        logit = torch.empty(N, dtype=torch.float32, device=q.device)
+        fb = torch.empty(N, dtype=torch.uint8, device=q.device)
+        nb = int(nat.lib().fastron_mlp_screen_workspace_bytes(N, hc.n))
+        ws = torch.empty(max(nb, 256), dtype=torch.uint8, device=q.device)
+        nfb = ctypes.c_int64(0)
+        check(nat.lib().fastron_mlp_screen(self._h, ctypes.byref(hc.chain), ctypes.byref(hc.cpoints),
+                                           ctypes.byref(model.desc), _ptr(q), N, float(tau), _ptr(logit), _ptr(lab),
+                                           _ptr(fb), ctypes.byref(nfb), _ptr(ws), ws.numel(), _stream()))
+        return lab, logit, fb, int(nfb.value)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            nat.lib().fastron_mlp_destroy(self._h)
             self._h = None
 
     def __del__(self):

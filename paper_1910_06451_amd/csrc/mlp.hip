@@ -1,0 +1,738 @@
+// Learned screening: a small MLP on the FK control points (3M inputs ->
+// H -> H -> 1 logit, ReLU), trained with BCE-with-logits and Adam, run as a
+// pre-screen whose uncertain queries (|logit| < tau) fall back to the Fastron
+// FK score. Not part of the paper's method; the paper cites a network on
+// control points (for self-collision cost) as prior art.
+//
+// Precision: BF16 operands on the matrix cores (v_mfma_f32_16x16x32_bf16)
+// with FP32 accumulation; FP32 master weights, biases, pre-activations,
+// head, loss and optimiser state.
+//
+// Kernels:
+//   k_gemm_bf16      C = act(A B + bias), A / B bf16 with arbitrary strides
+//                    (so transposes are free), 64 x 64 output tile per
+//                    workgroup, K staged through LDS in chunks of 32; the
+//                    epilogue can write FP32 and/or BF16, or reduce the row
+//                    against the head weights (fused last layer).
+//   k_mlp_input      gathers / computes FK features and standardises them
+//   k_colsum         deterministic two-pass column sums (bias gradients)
+//   k_head_*         logit, loss and dlogit; last-layer gradients
+//   k_adam           Adam on the FP32 masters + BF16 copies
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "fastron_internal.h"
+
+struct fastron_mlp;
+
+namespace fastron {
+
+typedef float f4m __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8m __attribute__((ext_vector_type(8)));
+typedef unsigned short u8m __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ uint16_t to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan pass through
+  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------------------
+// Generic BF16 GEMM
+// ---------------------------------------------------------------------------
+struct GemmArgs {
+  const uint16_t* A;
+  int64_t sam, sak;  // A(m, k) = A[m * sam + k * sak]
+  const uint16_t* B;
+  int64_t sbk, sbn;  // B(k, n) = B[k * sbk + n * sbn]
+  float* C;          // optional FP32 output C[m * ldc + n]
+  int64_t ldc;
+  uint16_t* Cb;      // optional BF16 output Cb[m * ldcb + n]
+  int64_t ldcb;
+  const float* bias; // optional [N]
+  const float* head; // optional [N]: fused last layer, partial[n_tile][m] = sum_n act(..) * head[n]
+  float* partial;    // [ceil(N / 64)][M] when head is set
+  int relu;
+  int M, N, K;
+};
+
+constexpr int kGT = 64;   // output tile edge
+constexpr int kGK = 32;   // K chunk
+constexpr int kGPad = 8;  // LDS row padding (elements)
+
+__global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
+  __shared__ __align__(16) uint16_t As[kGT][kGK + kGPad];
+  __shared__ __align__(16) uint16_t Bs[kGT][kGK + kGPad];  // stored transposed: Bs[n][k]
+  __shared__ float hsum[4][kGT];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+  f4m acc[4];
+#pragma unroll
+  for (int t = 0; t < 4; ++t) acc[t] = (f4m){0.f, 0.f, 0.f, 0.f};
+  for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int e = tid * 8 + i;  // 2048 elements per operand chunk
+      const int r = e / kGK, kk = e % kGK;
+      const int64_t gm = m0 + r, gk = k0 + kk, gn = n0 + r;
+      As[r][kk] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
+      Bs[r][kk] = (gn < g.N && gk < g.K) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
+    }
+    __syncthreads();
+    const int row = 16 * wave + (lane & 15), kq = 8 * (lane >> 4);
+    const bf8m a = __builtin_bit_cast(bf8m, *reinterpret_cast<const u8m*>(&As[row][kq]));
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const bf8m b = __builtin_bit_cast(bf8m, *reinterpret_cast<const u8m*>(&Bs[16 * t + (lane & 15)][kq]));
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[t], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // epilogue: lane holds rows 16 wave + 4 (lane / 16) + r, column 16 t + lane % 16
+  float hpart[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int64_t n = n0 + 16 * t + (lane & 15);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t m = m0 + 16 * wave + 4 * (lane >> 4) + r;
+      if (m < g.M && n < g.N) {
+        float v = acc[t][r];
+        if (g.bias) v += g.bias[n];
+        if (g.relu) v = fmaxf(v, 0.f);
+        if (g.C) g.C[m * g.ldc + n] = v;
+        if (g.Cb) g.Cb[m * g.ldcb + n] = to_bf16(v);
+        if (g.head) hpart[r] += v * g.head[n];
+      }
+    }
+  }
+  if (g.head) {
+    // reduce the 64 columns of this tile for each row: lanes sharing lane / 16 hold the same rows
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      float v = hpart[r];
+      v += __shfl_xor(v, 1);
+      v += __shfl_xor(v, 2);
+      v += __shfl_xor(v, 4);
+      v += __shfl_xor(v, 8);
+      if ((lane & 15) == 0) hsum[wave][4 * (lane >> 4) + r] = v;
+    }
+    __syncthreads();
+    if (tid < kGT) {
+      const int w = tid >> 4, rr = tid & 15;
+      const int64_t m = m0 + 16 * w + rr;
+      if (m < g.M) g.partial[(int64_t)blockIdx.y * g.M + m] = hsum[w][rr];
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Inputs: standardised control points as BF16 rows of width kin_pad
+// ---------------------------------------------------------------------------
+// From stored control points P [N][M][3], rows selected by `order` (or identity).
+__global__ void __launch_bounds__(256) k_mlp_input_points(const float* __restrict__ P, const int32_t* __restrict__ order,
+                                                           int64_t row0, int64_t rows, int d_in, int kin_pad,
+                                                           const float* __restrict__ mu, const float* __restrict__ sd,
+                                                           uint16_t* __restrict__ X, float* __restrict__ Xf) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * kin_pad) return;
+  const int64_t r = e / kin_pad;
+  const int c = (int)(e % kin_pad);
+  const int64_t src = order ? (int64_t)order[row0 + r] : row0 + r;
+  const float v = c < d_in ? (P[src * d_in + c] - mu[c]) / sd[c] : 0.f;
+  X[e] = to_bf16(v);
+  if (Xf) Xf[e] = v;
+}
+
+// From joint configurations: FK fused (one thread per query).
+template <typename R>
+__global__ void __launch_bounds__(256) k_mlp_input_fk(ChainArgs c, const float* __restrict__ q, int64_t row0,
+                                                       int64_t rows, int kin_pad, const float* __restrict__ mu,
+                                                       const float* __restrict__ sd, uint16_t* __restrict__ X) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  float qv[FASTRON_MAX_JOINTS];
+  for (int i = 0; i < c.n; ++i) qv[i] = q[(row0 + r) * c.n + i];
+  uint16_t* row = X + r * kin_pad;
+  for (int k = 3 * c.M; k < kin_pad; ++k) row[k] = 0;
+  fk_walk<R>(c, qv, [&](int m, float x, float y, float z) {
+    row[3 * m + 0] = to_bf16((x - mu[3 * m + 0]) / sd[3 * m + 0]);
+    row[3 * m + 1] = to_bf16((y - mu[3 * m + 1]) / sd[3 * m + 1]);
+    row[3 * m + 2] = to_bf16((z - mu[3 * m + 2]) / sd[3 * m + 2]);
+  });
+}
+
+// Feature statistics over N rows (one block per feature, fixed order): mean and
+// standard deviation; a constant feature gets sd = 1.
+__global__ void __launch_bounds__(256) k_feat_stats(const float* __restrict__ P, int64_t N, int d_in,
+                                                     float* __restrict__ mu, float* __restrict__ sd) {
+  __shared__ double part[256];
+  const int c = blockIdx.x;
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += 256) s += (double)P[i * d_in + c];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double mean = part[0] / (double)N;
+  __syncthreads();
+  double v = 0.0;
+  for (int64_t i = threadIdx.x; i < N; i += 256) {
+    const double d = (double)P[i * d_in + c] - mean;
+    v += d * d;
+  }
+  part[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double var = part[0] / (double)N;
+    mu[c] = (float)mean;
+    sd[c] = var > 1e-12 ? (float)sqrt(var) : 1.0f;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Head: z = sum of the fused partials + b3; BCE loss and dz = (sigmoid(z) - t) / B
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_head_forward(const float* __restrict__ partial, int ntiles, int64_t rows,
+                                                       const float* __restrict__ b3, float* __restrict__ z) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  float v = b3[0];
+  for (int t = 0; t < ntiles; ++t) v += partial[(int64_t)t * rows + r];
+  z[r] = v;
+}
+
+__global__ void __launch_bounds__(256) k_bce(const float* __restrict__ z, const int8_t* __restrict__ y,
+                                              const int32_t* __restrict__ order, int64_t row0, int64_t rows,
+                                              float* __restrict__ dz, float* __restrict__ loss_part) {
+  __shared__ float part[256];
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  float l = 0.f;
+  if (r < rows) {
+    const int64_t src = order ? (int64_t)order[row0 + r] : row0 + r;
+    const float t = y[src] > 0 ? 1.f : 0.f;
+    const float zz = z[r];
+    l = fmaxf(zz, 0.f) + log1pf(expf(-fabsf(zz))) - t * zz;
+    const float sig = 1.f / (1.f + expf(-zz));
+    dz[r] = (sig - t) / (float)rows;
+  }
+  part[threadIdx.x] = l;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) loss_part[blockIdx.x] = part[0];
+}
+
+// dZ2 = dz w3 [Z2 > 0] (FP32 and BF16)
+__global__ void __launch_bounds__(256) k_head_back(const float* __restrict__ dz, const float* __restrict__ w3,
+                                                    const float* __restrict__ Z2, int64_t rows, int H,
+                                                    float* __restrict__ dZ2, uint16_t* __restrict__ dZ2b) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= rows * H) return;
+  const int64_t r = e / H;
+  const int c = (int)(e % H);
+  const float v = Z2[e] > 0.f ? dz[r] * w3[c] : 0.f;
+  dZ2[e] = v;
+  dZ2b[e] = to_bf16(v);
+}
+
+// dZ1 = dH1 [Z1 > 0]
+__global__ void __launch_bounds__(256) k_relu_back(const float* __restrict__ dH, const float* __restrict__ Z,
+                                                    int64_t n, float* __restrict__ dZ, uint16_t* __restrict__ dZb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e >= n) return;
+  const float v = Z[e] > 0.f ? dH[e] : 0.f;
+  dZ[e] = v;
+  dZb[e] = to_bf16(v);
+}
+
+// out[c] = sum_r X[r * ld + c] * (s ? s[r] : 1), two passes with a fixed order:
+// pass 1 writes partials[chunk][c] for 64 row chunks, pass 2 sums them.
+constexpr int kColChunks = 64;
+__global__ void __launch_bounds__(256) k_colsum_pass1(const float* __restrict__ X, int64_t rows, int cols, int64_t ld,
+                                                       const float* __restrict__ s, float* __restrict__ partials) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  const int chunk = blockIdx.y;
+  if (c >= cols) return;
+  const int64_t per = (rows + kColChunks - 1) / kColChunks;
+  const int64_t r0 = chunk * per, r1 = r0 + per < rows ? r0 + per : rows;
+  float acc = 0.f;
+  for (int64_t r = r0; r < r1; ++r) acc += X[r * ld + c] * (s ? s[r] : 1.f);
+  partials[(int64_t)chunk * cols + c] = acc;
+}
+__global__ void __launch_bounds__(256) k_colsum_pass2(const float* __restrict__ partials, int cols,
+                                                       float* __restrict__ out) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= cols) return;
+  float acc = 0.f;
+  for (int k = 0; k < kColChunks; ++k) acc += partials[(int64_t)k * cols + c];
+  out[c] = acc;
+}
+
+// relu(Z2) . w  -> used for gw3 = sum_r relu(Z2[r]) dz[r]: relu applied on the fly
+__global__ void __launch_bounds__(256) k_relu_copy(const float* __restrict__ Z, int64_t n, float* __restrict__ H) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < n) H[e] = fmaxf(Z[e], 0.f);
+}
+
+// Adam (Kingma & Ba) on FP32 masters; c1 = 1 / (1 - beta1^t), c2 = 1 / (1 - beta2^t).
+__global__ void __launch_bounds__(256) k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m,
+                                               float* __restrict__ v, int64_t n, float lr, float b1, float b2,
+                                               float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.f - b1) * gi;
+  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi * c1) / (sqrtf(vi * c2) + eps);
+}
+
+// BF16 copies of the weight matrices (W1 padded to kin_pad rows).
+__global__ void __launch_bounds__(256) k_weights_bf16(const float* __restrict__ w1, const float* __restrict__ w2,
+                                                       int d_in, int kin_pad, int H, uint16_t* __restrict__ w1b,
+                                                       uint16_t* __restrict__ w2b) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t n1 = (int64_t)kin_pad * H, n2 = (int64_t)H * H;
+  if (e < n1) {
+    const int64_t r = e / H;
+    w1b[e] = r < d_in ? to_bf16(w1[e]) : (uint16_t)0;
+  } else if (e < n1 + n2) {
+    w2b[e - n1] = to_bf16(w2[e - n1]);
+  }
+}
+
+// Screening decision: confident logits give the label directly; the others are
+// appended to the fallback list (order of appends is irrelevant: each query's
+// result depends only on itself).
+__global__ void __launch_bounds__(256) k_screen(const float* __restrict__ z, int64_t row0, int64_t rows, float tau,
+                                                 float* __restrict__ logit_out, int8_t* __restrict__ label,
+                                                 uint8_t* __restrict__ fell_back, int32_t* __restrict__ fb_idx,
+                                                 unsigned long long* __restrict__ fb_count) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= rows) return;
+  const float v = z[r];
+  const int64_t j = row0 + r;
+  if (logit_out) logit_out[j] = v;
+  const bool fb = fabsf(v) < tau;
+  if (fell_back) fell_back[j] = fb ? 1 : 0;
+  if (fb) {
+    const unsigned long long k = atomicAdd(fb_count, 1ull);
+    fb_idx[k] = (int32_t)j;
+  } else {
+    label[j] = v >= 0.f ? (int8_t)1 : (int8_t)-1;
+  }
+}
+
+__global__ void __launch_bounds__(256) k_gather_rows(const float* __restrict__ q, int n, const int32_t* __restrict__ idx,
+                                                      const unsigned long long* __restrict__ count,
+                                                      float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t cnt = (int64_t)*count;
+  if (e >= cnt * n) return;
+  const int64_t r = e / n;
+  out[e] = q[(int64_t)idx[r] * n + (e % n)];
+}
+
+__global__ void __launch_bounds__(256) k_scatter_labels(const int8_t* __restrict__ lab_sub, const float* __restrict__ f_sub,
+                                                         const int32_t* __restrict__ idx,
+                                                         const unsigned long long* __restrict__ count,
+                                                         int8_t* __restrict__ label, float* __restrict__ f_out) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= (int64_t)*count) return;
+  label[idx[r]] = lab_sub[r];
+  if (f_out) f_out[idx[r]] = f_sub[r];
+}
+
+__global__ void k_zero_u64(unsigned long long* p) {
+  if (threadIdx.x == 0) *p = 0ull;
+}
+
+static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
+
+}  // namespace fastron
+
+using namespace fastron;
+
+// ---------------------------------------------------------------------------
+// Network object
+// ---------------------------------------------------------------------------
+struct fastron_mlp {
+  int d_in = 0, kin_pad = 0, H = 0;
+  int64_t n_params = 0;
+  int64_t cap_rows = 0;  // capacity of the activation buffers
+  float* params = nullptr;  // [w1 d_in*H][b1 H][w2 H*H][b2 H][w3 H][b3 1]
+  float* grads = nullptr;
+  float* adam_m = nullptr;
+  float* adam_v = nullptr;
+  float* mu = nullptr;
+  float* sd = nullptr;
+  uint16_t* w1b = nullptr;  // [kin_pad][H]
+  uint16_t* w2b = nullptr;  // [H][H]
+  int64_t step = 0;
+  // activations for a batch of cap_rows
+  uint16_t* Xb = nullptr;
+  float* Z1 = nullptr;
+  uint16_t* H1b = nullptr;
+  float* Z2 = nullptr;
+  float* partial = nullptr;
+  float* z = nullptr;
+  float* dz = nullptr;
+  float* dZ2 = nullptr;
+  uint16_t* dZ2b = nullptr;
+  float* dH1 = nullptr;
+  float* dZ1 = nullptr;
+  uint16_t* dZ1b = nullptr;
+  float* colpart = nullptr;
+  float* loss_part = nullptr;
+  float* hbuf = nullptr;  // relu(Z2)
+  float* w1() { return params; }
+  float* b1() { return params + (int64_t)d_in * H; }
+  float* w2() { return b1() + H; }
+  float* b2() { return w2() + (int64_t)H * H; }
+  float* w3() { return b2() + H; }
+  float* b3() { return w3() + H; }
+};
+
+namespace {
+
+int64_t param_count(int d_in, int H) { return (int64_t)d_in * H + H + (int64_t)H * H + H + H + 1; }
+
+void free_mlp(fastron_mlp* n) {
+  if (!n) return;
+  void* ps[] = {n->params, n->grads, n->adam_m, n->adam_v, n->mu, n->sd, n->w1b, n->w2b, n->Xb, n->Z1, n->H1b,
+                n->Z2, n->partial, n->z, n->dz, n->dZ2, n->dZ2b, n->dH1, n->dZ1, n->dZ1b, n->colpart, n->loss_part,
+                n->hbuf};
+  for (void* p : ps) (void)hipFree(p);
+  delete n;
+}
+
+fastron_status gemm(hipStream_t s, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
+                    int64_t sbn, int M, int N, int K, float* C, int64_t ldc, uint16_t* Cb, int64_t ldcb,
+                    const float* bias, int relu, const float* head = nullptr, float* partial = nullptr) {
+  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, Cb, ldcb, bias, head, partial, relu, M, N, K};
+  dim3 grid((unsigned)((M + kGT - 1) / kGT), (unsigned)((N + kGT - 1) / kGT));
+  hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+fastron_status colsum(hipStream_t s, fastron_mlp* n, const float* X, int64_t rows, int cols, int64_t ld,
+                      const float* scale, float* out) {
+  dim3 g1((unsigned)((cols + 255) / 256), kColChunks);
+  hipLaunchKernelGGL(k_colsum_pass1, g1, dim3(256), 0, s, X, rows, cols, ld, scale, n->colpart);
+  FASTRON_HIP(hipGetLastError());
+  hipLaunchKernelGGL(k_colsum_pass2, dim3((unsigned)((cols + 255) / 256)), dim3(256), 0, s, n->colpart, cols, out);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+#define TRY(x)                                   \
+  do {                                           \
+    fastron_status st_ = (x);                    \
+    if (st_ != FASTRON_OK) return st_;           \
+  } while (0)
+
+// Forward over `rows` rows already staged in Xb; fills Z1, H1b, Z2 and the logits z.
+fastron_status forward_staged(fastron_mlp* n, int64_t rows, bool keep, hipStream_t s) {
+  const int H = n->H;
+  // layer 1: Z1 = X W1 + b1, H1 = relu(Z1)
+  TRY(gemm(s, n->Xb, n->kin_pad, 1, n->w1b, H, 1, (int)rows, H, n->kin_pad, keep ? n->Z1 : nullptr, H, n->H1b, H,
+           n->b1(), 1));
+  // layer 2 (+ fused head): Z2 = H1 W2 + b2; partial = relu(Z2) . w3 per 64-column tile
+  TRY(gemm(s, n->H1b, H, 1, n->w2b, H, 1, (int)rows, H, H, keep ? n->Z2 : nullptr, H, nullptr, 0, n->b2(), 1,
+           n->w3(), n->partial));
+  const int ntile = (H + kGT - 1) / kGT;
+  hipLaunchKernelGGL(k_head_forward, dim3(nblk(rows)), dim3(256), 0, s, n->partial, ntile, rows, n->b3(), n->z);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+// Gradients of the mean BCE over the staged rows into n->grads (Z1, Z2 must be kept).
+fastron_status backward(fastron_mlp* n, int64_t rows, const int8_t* y, const int32_t* order, int64_t row0,
+                        hipStream_t s) {
+  const int H = n->H;
+  float* g = n->grads;
+  float* gw1 = g;
+  float* gb1 = g + (int64_t)n->d_in * H;
+  float* gw2 = gb1 + H;
+  float* gb2 = gw2 + (int64_t)H * H;
+  float* gw3 = gb2 + H;
+  float* gb3 = gw3 + H;
+  hipLaunchKernelGGL(k_bce, dim3(nblk(rows)), dim3(256), 0, s, n->z, y, order, row0, rows, n->dz, n->loss_part);
+  FASTRON_HIP(hipGetLastError());
+  // last layer: gw3 = relu(Z2)^T dz, gb3 = sum dz
+  hipLaunchKernelGGL(k_relu_copy, dim3(nblk(rows * H)), dim3(256), 0, s, n->Z2, rows * H, n->hbuf);
+  FASTRON_HIP(hipGetLastError());
+  TRY(colsum(s, n, n->hbuf, rows, H, H, n->dz, gw3));
+  TRY(colsum(s, n, n->dz, rows, 1, 1, nullptr, gb3));
+  // layer 2: dZ2 = dz w3 [Z2 > 0]; gW2 = H1^T dZ2; gb2 = sum dZ2
+  hipLaunchKernelGGL(k_head_back, dim3(nblk(rows * H)), dim3(256), 0, s, n->dz, n->w3(), n->Z2, rows, H, n->dZ2,
+                     n->dZ2b);
+  FASTRON_HIP(hipGetLastError());
+  TRY(gemm(s, n->H1b, 1, H, n->dZ2b, H, 1, H, H, (int)rows, gw2, H, nullptr, 0, nullptr, 0));
+  TRY(colsum(s, n, n->dZ2, rows, H, H, nullptr, gb2));
+  // layer 1: dH1 = dZ2 W2^T; dZ1 = dH1 [Z1 > 0]; gW1 = X^T dZ1; gb1 = sum dZ1
+  TRY(gemm(s, n->dZ2b, H, 1, n->w2b, 1, H, (int)rows, H, H, n->dH1, H, nullptr, 0, nullptr, 0));
+  hipLaunchKernelGGL(k_relu_back, dim3(nblk(rows * H)), dim3(256), 0, s, n->dH1, n->Z1, rows * H, n->dZ1, n->dZ1b);
+  FASTRON_HIP(hipGetLastError());
+  TRY(gemm(s, n->Xb, 1, n->kin_pad, n->dZ1b, H, 1, n->d_in, H, (int)rows, gw1, H, nullptr, 0, nullptr, 0));
+  TRY(colsum(s, n, n->dZ1, rows, H, H, nullptr, gb1));
+  return FASTRON_OK;
+}
+
+fastron_status refresh_bf16(fastron_mlp* n, hipStream_t s) {
+  const int64_t tot = (int64_t)n->kin_pad * n->H + (int64_t)n->H * n->H;
+  hipLaunchKernelGGL(k_weights_bf16, dim3(nblk(tot)), dim3(256), 0, s, n->w1(), n->w2(), n->d_in, n->kin_pad, n->H,
+                     n->w1b, n->w2b);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+fastron_status stage_points(fastron_mlp* n, const float* P, const int32_t* order, int64_t row0, int64_t rows,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_mlp_input_points, dim3(nblk(rows * n->kin_pad)), dim3(256), 0, s, P, order, row0, rows,
+                     n->d_in, n->kin_pad, n->mu, n->sd, n->Xb, nullptr);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows, fastron_mlp** out) {
+  clear_error();
+  FASTRON_CHECK(out != nullptr, "out is NULL");
+  *out = nullptr;
+  FASTRON_CHECK(d_in >= 1 && d_in <= 3 * FASTRON_MAX_POINTS, "d_in = %d outside [1, %d]", d_in,
+                3 * FASTRON_MAX_POINTS);
+  FASTRON_CHECK(hidden >= 16 && hidden <= 1024 && hidden % 16 == 0, "hidden = %d must be a multiple of 16 in [16, 1024]",
+                hidden);
+  FASTRON_CHECK(max_rows >= 1 && max_rows <= (1ll << 24), "max_rows = %lld outside [1, 2^24]", (long long)max_rows);
+  fastron_mlp* n = new fastron_mlp();
+  n->d_in = d_in;
+  n->kin_pad = (d_in + 31) / 32 * 32;
+  n->H = hidden;
+  n->n_params = param_count(d_in, hidden);
+  n->cap_rows = max_rows;
+  const int64_t R = max_rows, H = hidden;
+  hipError_t e = hipSuccess;
+  auto alloc = [&](auto** p, int64_t count, size_t elem) {
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void**>(p), (size_t)(count > 0 ? count : 1) * elem);
+  };
+  alloc(&n->params, n->n_params, 4);
+  alloc(&n->grads, n->n_params, 4);
+  alloc(&n->adam_m, n->n_params, 4);
+  alloc(&n->adam_v, n->n_params, 4);
+  alloc(&n->mu, d_in, 4);
+  alloc(&n->sd, d_in, 4);
+  alloc(&n->w1b, n->kin_pad * H, 2);
+  alloc(&n->w2b, H * H, 2);
+  alloc(&n->Xb, R * n->kin_pad, 2);
+  alloc(&n->Z1, R * H, 4);
+  alloc(&n->H1b, R * H, 2);
+  alloc(&n->Z2, R * H, 4);
+  alloc(&n->partial, R * ((H + kGT - 1) / kGT), 4);
+  alloc(&n->z, R, 4);
+  alloc(&n->dz, R, 4);
+  alloc(&n->dZ2, R * H, 4);
+  alloc(&n->dZ2b, R * H, 2);
+  alloc(&n->dH1, R * H, 4);
+  alloc(&n->dZ1, R * H, 4);
+  alloc(&n->dZ1b, R * H, 2);
+  alloc(&n->colpart, (int64_t)kColChunks * H, 4);
+  alloc(&n->loss_part, (R + 255) / 256, 4);
+  alloc(&n->hbuf, R * H, 4);
+  if (e == hipSuccess) e = hipMemset(n->adam_m, 0, n->n_params * 4);
+  if (e == hipSuccess) e = hipMemset(n->adam_v, 0, n->n_params * 4);
+  if (e != hipSuccess) {
+    free_mlp(n);
+    return fail(e == hipErrorOutOfMemory ? FASTRON_ENOMEM : FASTRON_EHIP, "MLP allocation failed: %s",
+                hipGetErrorString(e));
+  }
+  *out = n;
+  return FASTRON_OK;
+}
+
+void fastron_mlp_destroy(fastron_mlp* n) { free_mlp(n); }
+
+int64_t fastron_mlp_param_count(const fastron_mlp* n) { return n ? n->n_params : -1; }
+
+fastron_status fastron_mlp_set_params(fastron_mlp* n, const float* params, const float* mu, const float* sd,
+                                      void* stream) {
+  clear_error();
+  FASTRON_CHECK(n && params, "network and params must be non-NULL");
+  hipStream_t s = as_stream(stream);
+  FASTRON_HIP(hipMemcpyAsync(n->params, params, n->n_params * 4, hipMemcpyDeviceToDevice, s));
+  if (mu) FASTRON_HIP(hipMemcpyAsync(n->mu, mu, n->d_in * 4, hipMemcpyDeviceToDevice, s));
+  if (sd) FASTRON_HIP(hipMemcpyAsync(n->sd, sd, n->d_in * 4, hipMemcpyDeviceToDevice, s));
+  FASTRON_HIP(hipMemsetAsync(n->adam_m, 0, n->n_params * 4, s));
+  FASTRON_HIP(hipMemsetAsync(n->adam_v, 0, n->n_params * 4, s));
+  n->step = 0;
+  return refresh_bf16(n, s);
+}
+
+fastron_status fastron_mlp_get_params(const fastron_mlp* n, float* params, float* grads, float* mu, float* sd,
+                                      void* stream) {
+  clear_error();
+  FASTRON_CHECK(n != nullptr, "network is NULL");
+  hipStream_t s = as_stream(stream);
+  if (params) FASTRON_HIP(hipMemcpyAsync(params, n->params, n->n_params * 4, hipMemcpyDeviceToDevice, s));
+  if (grads) FASTRON_HIP(hipMemcpyAsync(grads, n->grads, n->n_params * 4, hipMemcpyDeviceToDevice, s));
+  if (mu) FASTRON_HIP(hipMemcpyAsync(mu, n->mu, n->d_in * 4, hipMemcpyDeviceToDevice, s));
+  if (sd) FASTRON_HIP(hipMemcpyAsync(sd, n->sd, n->d_in * 4, hipMemcpyDeviceToDevice, s));
+  return FASTRON_OK;
+}
+
+fastron_status fastron_mlp_fit_standardisation(fastron_mlp* n, const float* P, int64_t N, void* stream) {
+  clear_error();
+  FASTRON_CHECK(n && P, "network and P must be non-NULL");
+  FASTRON_CHECK(N >= 1, "N < 1");
+  hipLaunchKernelGGL(k_feat_stats, dim3((unsigned)n->d_in), dim3(256), 0, as_stream(stream), P, N, n->d_in, n->mu,
+                     n->sd);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+fastron_status fastron_mlp_forward(fastron_mlp* n, const float* P, int64_t N, float* logits, void* stream) {
+  clear_error();
+  FASTRON_CHECK(n && (N == 0 || (P && logits)), "network, P and logits must be non-NULL");
+  FASTRON_CHECK(N >= 0, "N < 0");
+  hipStream_t s = as_stream(stream);
+  for (int64_t r0 = 0; r0 < N; r0 += n->cap_rows) {
+    const int64_t rows = N - r0 < n->cap_rows ? N - r0 : n->cap_rows;
+    TRY(stage_points(n, P, nullptr, r0, rows, s));
+    TRY(forward_staged(n, rows, false, s));
+    FASTRON_HIP(hipMemcpyAsync(logits + r0, n->z, rows * 4, hipMemcpyDeviceToDevice, s));
+  }
+  return FASTRON_OK;
+}
+
+fastron_status fastron_mlp_gradients(fastron_mlp* n, const float* P, const int8_t* y, int64_t N, float* loss,
+                                     void* stream) {
+  clear_error();
+  FASTRON_CHECK(n && P && y, "network, P and y must be non-NULL");
+  FASTRON_CHECK(N >= 1 && N <= n->cap_rows, "N = %lld outside [1, max_rows]", (long long)N);
+  hipStream_t s = as_stream(stream);
+  TRY(stage_points(n, P, nullptr, 0, N, s));
+  TRY(forward_staged(n, N, true, s));
+  TRY(backward(n, N, y, nullptr, 0, s));
+  if (loss) {
+    const int nb = (int)((N + 255) / 256);
+    std::vector<float> lp(nb);
+    FASTRON_HIP(hipMemcpyAsync(lp.data(), n->loss_part, nb * 4, hipMemcpyDeviceToHost, s));
+    FASTRON_HIP(hipStreamSynchronize(s));
+    double acc = 0.0;
+    for (float v : lp) acc += v;
+    *loss = (float)(acc / (double)N);
+  }
+  return FASTRON_OK;
+}
+
+fastron_status fastron_mlp_train_epoch(fastron_mlp* n, const float* P, const int8_t* y, const int32_t* order,
+                                       int64_t N, int64_t batch, float lr, float* mean_loss, void* stream) {
+  clear_error();
+  FASTRON_CHECK(n && P && y, "network, P and y must be non-NULL");
+  FASTRON_CHECK(N >= 1 && batch >= 1 && batch <= n->cap_rows, "need N >= 1 and 1 <= batch <= max_rows");
+  FASTRON_CHECK(std::isfinite(lr) && lr > 0.f, "lr must be > 0");
+  hipStream_t s = as_stream(stream);
+  const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  std::vector<float> lp;
+  double loss_acc = 0.0;
+  for (int64_t r0 = 0; r0 < N; r0 += batch) {
+    const int64_t rows = N - r0 < batch ? N - r0 : batch;
+    TRY(stage_points(n, P, order, r0, rows, s));
+    TRY(forward_staged(n, rows, true, s));
+    TRY(backward(n, rows, y, order, r0, s));
+    n->step += 1;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)n->step)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)n->step)));
+    hipLaunchKernelGGL(k_adam, dim3(nblk(n->n_params)), dim3(256), 0, s, n->params, n->grads, n->adam_m, n->adam_v,
+                       n->n_params, lr, b1, b2, eps, c1, c2);
+    FASTRON_HIP(hipGetLastError());
+    TRY(refresh_bf16(n, s));
+    if (mean_loss) {
+      const int nb = (int)((rows + 255) / 256);
+      lp.resize(nb);
+      FASTRON_HIP(hipMemcpyAsync(lp.data(), n->loss_part, nb * 4, hipMemcpyDeviceToHost, s));
+      FASTRON_HIP(hipStreamSynchronize(s));
+      for (float v : lp) loss_acc += v;
+    }
+  }
+  if (mean_loss) *mean_loss = (float)(loss_acc / (double)N);
+  return FASTRON_OK;
+}
+
+fastron_status fastron_mlp_screen(fastron_mlp* n, const fastron_chain* chain, const fastron_cpoints* cp,
+                                  const fastron_model* model, const float* q, int64_t N, float tau, float* logits,
+                                  int8_t* label, uint8_t* fell_back, int64_t* n_fallback, void* workspace,
+                                  int64_t workspace_bytes, void* stream) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(n != nullptr, "network is NULL");
+  FASTRON_CHECK(3 * c.M == n->d_in, "network input width %d != 3 M = %d", n->d_in, 3 * c.M);
+  FASTRON_CHECK(N >= 0, "N < 0");
+  FASTRON_CHECK(N == 0 || (q && label), "q and label must be non-NULL");
+  FASTRON_CHECK(std::isfinite(tau) && tau >= 0.f, "tau must be >= 0");
+  FASTRON_CHECK(model != nullptr && model->M == c.M, "model missing or prepared for another M");
+  FASTRON_CHECK(N < INT32_MAX, "N too large");
+  const int64_t need = 256 + N * 4 + N * (int64_t)c.n * 4 + N * 5;
+  FASTRON_CHECK(workspace && workspace_bytes >= need, "workspace needs %lld bytes", (long long)need);
+  hipStream_t s = as_stream(stream);
+  char* ws = static_cast<char*>(workspace);
+  unsigned long long* count = reinterpret_cast<unsigned long long*>(ws);
+  int32_t* fb_idx = reinterpret_cast<int32_t*>(ws + 256);
+  float* q_sub = reinterpret_cast<float*>(ws + 256 + N * 4);
+  float* f_sub = reinterpret_cast<float*>(ws + 256 + N * 4 + N * (int64_t)c.n * 4);
+  int8_t* l_sub = reinterpret_cast<int8_t*>(ws + 256 + N * 8 + N * (int64_t)c.n * 4);
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, count);
+  FASTRON_HIP(hipGetLastError());
+  for (int64_t r0 = 0; r0 < N; r0 += n->cap_rows) {
+    const int64_t rows = N - r0 < n->cap_rows ? N - r0 : n->cap_rows;
+    if (c.n >= kFp64Joints)
+      hipLaunchKernelGGL(k_mlp_input_fk<double>, dim3(nblk(rows)), dim3(256), 0, s, c, q, r0, rows, n->kin_pad, n->mu,
+                         n->sd, n->Xb);
+    else
+      hipLaunchKernelGGL(k_mlp_input_fk<float>, dim3(nblk(rows)), dim3(256), 0, s, c, q, r0, rows, n->kin_pad, n->mu,
+                         n->sd, n->Xb);
+    FASTRON_HIP(hipGetLastError());
+    TRY(forward_staged(n, rows, false, s));
+    hipLaunchKernelGGL(k_screen, dim3(nblk(rows)), dim3(256), 0, s, n->z, r0, rows, tau, logits, label, fell_back,
+                       fb_idx, count);
+    FASTRON_HIP(hipGetLastError());
+  }
+  unsigned long long h_count = 0;
+  FASTRON_HIP(hipMemcpyAsync(&h_count, count, 8, hipMemcpyDeviceToHost, s));
+  FASTRON_HIP(hipStreamSynchronize(s));
+  if (n_fallback) *n_fallback = (int64_t)h_count;
+  if (h_count == 0) return FASTRON_OK;
+  hipLaunchKernelGGL(k_gather_rows, dim3(nblk((int64_t)h_count * c.n)), dim3(256), 0, s, q, c.n, fb_idx, count, q_sub);
+  FASTRON_HIP(hipGetLastError());
+  st = fastron_fk_score_prepared(chain, cp, model, q_sub, (int64_t)h_count, f_sub, l_sub, FASTRON_SCORE_FP32, stream);
+  if (st != FASTRON_OK) return st;
+  hipLaunchKernelGGL(k_scatter_labels, dim3(nblk((int64_t)h_count)), dim3(256), 0, s, l_sub, f_sub, fb_idx, count,
+                     label, nullptr);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+int64_t fastron_mlp_screen_workspace_bytes(int64_t N, int32_t n_joints) {
+  if (N < 0 || n_joints < 1) return -1;
+  return 256 + N * 4 + N * (int64_t)n_joints * 4 + N * 5;
+}
+
+}  // extern "C"

@@ -140,3 +140,25 @@ def unit_directions(name: str, count: int, seed: int = MASTER_SEED) -> np.ndarra
     """Uniformly random unit vectors in R^3 (count, 3)."""
     v = rng(name, seed).standard_normal(size=(count, 3))
     return v / np.linalg.norm(v, axis=1, keepdims=True)
+
+
+def mlp_init(d_in: int, hidden: int = 256, seed: int = MASTER_SEED, name: str = "mlp_init") -> np.ndarray:
+    """He-normal initial weights (zero biases) for the screening network, flattened in the order
+    W1 [d_in][H], b1 [H], W2 [H][H], b2 [H], w3 [H], b3 [1] as float32."""
+    g = rng(name, seed)
+    w1 = g.standard_normal((d_in, hidden)) * np.sqrt(2.0 / d_in)
+    w2 = g.standard_normal((hidden, hidden)) * np.sqrt(2.0 / hidden)
+    w3 = g.standard_normal(hidden) * np.sqrt(2.0 / hidden)
+    parts = [w1.ravel(), np.zeros(hidden), w2.ravel(), np.zeros(hidden), w3, np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
+
+
+def split_mlp_params(flat: np.ndarray, d_in: int, hidden: int = 256):
+    """Views of a flat parameter vector as [W1, b1, W2, b2, w3, b3]."""
+    sizes = [d_in * hidden, hidden, hidden * hidden, hidden, hidden, 1]
+    shapes = [(d_in, hidden), (hidden,), (hidden, hidden), (hidden,), (hidden,), ()]
+    out, o = [], 0
+    for sz, sh in zip(sizes, shapes):
+        out.append(flat[o:o + sz].reshape(sh))
+        o += sz
+    return out

@@ -1,0 +1,105 @@
+"""Learned screening network: the device forward pass and gradients against
+the FP64 oracle (same weights, same standardised inputs), training progress,
+and the exact semantics of the tau-margin fallback to the Fastron score."""
+import numpy as np
+import pytest
+import torch
+
+from oracle import mlp_oracle as mo
+from paper_1910_06451_amd import api, workloads as wl
+from conftest import announce, oracle_dh
+
+pytestmark = pytest.mark.gpu
+
+
+def _data(oracle_mod, N, name, n_cubes=20):
+    arm = wl.arm_7dof()
+    dh = oracle_dh(oracle_mod, arm)
+    q = wl.configs(name, N, 7)
+    lo, hi = wl.cubes("bench7/cubes", n_cubes, 0.1, 0.25)
+    y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+    P = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
+    return arm, q, P, y.astype(np.int8)
+
+
+def test_forward_and_gradients_match_oracle(oracle_mod, dev):
+    arm, q, P, y = _data(oracle_mod, 700, "mlp_grad")
+    d_in = 24
+    params = wl.mlp_init(d_in, 256, name="mlp_grad_init")
+    X = P.reshape(-1, d_in).astype(np.float64)
+    mu = X.mean(axis=0)
+    sd = X.std(axis=0)
+    sd[sd < 1e-6] = 1.0
+    mu32, sd32 = mu.astype(np.float32), sd.astype(np.float32)
+    net = api.MLP(d_in, 256, max_rows=1024)
+    net.set_params(torch.from_numpy(params).to(dev), torch.from_numpy(mu32).to(dev), torch.from_numpy(sd32).to(dev))
+    P_d = torch.from_numpy(P).to(dev)
+    announce("mlp forward")
+    z = net.forward(P_d).cpu().numpy().astype(np.float64)
+    announce("mlp gradients")
+    loss = net.gradients(P_d, torch.from_numpy(y).to(dev))
+    _, g, _, _ = net.get_params(dev)
+    g = g.cpu().numpy().astype(np.float64)
+    ps = [p.astype(np.float64) for p in wl.split_mlp_params(params, d_in)]
+    z_ref, cache = mo.forward(ps, X, mu32.astype(np.float64), sd32.astype(np.float64))
+    g_ref = mo.backward(ps, cache, z_ref, y)
+    # BF16 operands: relative errors of order 2^-8 per product, averaged over 256-wide sums
+    rel_z = np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref)
+    assert rel_z < 2e-2, rel_z
+    assert abs(loss - mo.bce_loss(z_ref, y)) < 2e-2 * abs(mo.bce_loss(z_ref, y)) + 1e-3
+    gs = wl.split_mlp_params(g, d_in)
+    for k, (a, b) in enumerate(zip(gs, g_ref)):
+        rel = np.linalg.norm(np.ravel(a) - np.ravel(b)) / max(np.linalg.norm(np.ravel(b)), 1e-12)
+        assert rel < 2e-2, (k, rel)
+    net.close()
+
+
+def test_training_learns(oracle_mod, dev):
+    arm, q, P, y = _data(oracle_mod, 60000, "mlp_train")
+    d_in = 24
+    Ptr, ytr = torch.from_numpy(P[:50000]).to(dev), torch.from_numpy(y[:50000]).to(dev)
+    Pte, yte = torch.from_numpy(P[50000:]).to(dev), y[50000:]
+    net = api.MLP(d_in, 256, max_rows=4096)
+    net.set_params(torch.from_numpy(wl.mlp_init(d_in, 256, name="mlp_train_init")).to(dev))
+    net.fit_standardisation(Ptr)
+    losses = []
+    for ep in range(6):
+        perm = torch.from_numpy(wl.rng(f"mlp_train/perm{ep}").permutation(50000).astype(np.int32)).to(dev)
+        announce(f"mlp epoch {ep}")
+        losses.append(net.train_epoch(Ptr, ytr, perm, batch=4096, lr=2e-3))
+    z = net.forward(Pte).cpu().numpy()
+    acc = np.mean(np.where(z >= 0, 1, -1) == yte)
+    majority = max(np.mean(yte == 1), np.mean(yte == -1))
+    print(dict(losses=losses, acc=float(acc), majority=float(majority)))
+    assert losses[-1] < losses[0] * 0.8
+    assert acc > majority + 0.05
+    net.close()
+
+
+def test_screen_semantics(oracle_mod, dev):
+    arm = wl.arm_7dof()
+    gamma = 10.0
+    sq, al = wl.model("mlp_screen_model", 500, 7)
+    q = wl.configs("mlp_screen/q", 3001, 7)
+    sq_d, al_d, q_d = (torch.from_numpy(x).to(dev) for x in (sq, al, q))
+    model = api.support_prep(arm, sq_d, al_d, gamma)
+    _, plain = api.fk_score_prepared(arm, model, q_d)
+    net = api.MLP(24, 256, max_rows=1024)
+    net.set_params(torch.from_numpy(wl.mlp_init(24, 256, name="mlp_screen_init")).to(dev))
+    net.fit_standardisation(api.fk_points(arm, q_d))
+    announce("screen tau=0")
+    lab0, z0, fb0, n0 = net.screen(arm, model, q_d, 0.0)
+    assert n0 == 0 and int(fb0.sum()) == 0
+    assert torch.equal(lab0, torch.where(z0 >= 0, 1, -1).to(torch.int8))
+    announce("screen tau=inf")
+    labi, zi, fbi, ni = net.screen(arm, model, q_d, 1e30)
+    assert ni == 3001 and torch.equal(labi, plain)
+    tau = float(torch.median(z0.abs()))
+    announce("screen tau=median")
+    lab, z, fb, nf = net.screen(arm, model, q_d, tau)
+    expect_fb = (z.abs() < tau)
+    assert torch.equal(fb.bool(), expect_fb) and nf == int(expect_fb.sum())
+    assert torch.equal(lab[~expect_fb], torch.where(z[~expect_fb] >= 0, 1, -1).to(torch.int8))
+    assert torch.equal(lab[expect_fb], plain[expect_fb])
+    torch.testing.assert_close(z, z0, rtol=0, atol=0)
+    net.close()
