@@ -50,6 +50,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--mlp-epochs", type=int, default=6, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -136,6 +137,8 @@ def main():
         extras["batched"] = batched_run(api, wl, arm, gamma, dev)
         log("[bench] re-training 16 environments after their cubes move")
         extras["retrain16"] = retrain_run(api, wl, arm, dev)
+        log("[bench] learned screening (MLP + tau fallback)")
+        extras["screen"] = screen_run(api, wl, arm, dev, epochs=args.mlp_epochs)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -284,6 +287,67 @@ def retrain_run(api, wl, arm, dev, n_env=16, N=20_000):
             "updates_warm_mean": float(np.mean([r["updates_warm"] for r in rows])),
             "updates_first_mean": float(np.mean([r["updates_first"] for r in rows])),
             "all_converged": all(r["converged"] for r in rows)}
+
+
+def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304, taus=(0.0, 0.5, 1.0, 2.0, 4.0)):
+    """Screening network trained on 2,000,000 geometrically labelled configurations (first 1,900,000 train, last
+    100,000 held out); fallback model = Algorithm 1 on 50,000 labelled samples with S_max = 4,000; 4,194,304
+    queries scored plain (Fastron FK only) and screened for each tau; accuracy against geometric labels."""
+    import torch
+
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    sync = torch.cuda.synchronize
+    # training data for the network
+    q_tr = torch.from_numpy(wl.configs("bench7/screen_train", n_train, arm.n)).to(dev)
+    y_tr, _ = api.label_capsule_box(arm, q_tr, arm.radius, lo, hi, want_clearance=False)
+    P_tr = api.fk_points(arm, q_tr)
+    del q_tr
+    n_fit = n_train - 100_000
+    net = api.MLP(3 * arm.M, 256, max_rows=8192)
+    net.set_params(torch.from_numpy(wl.mlp_init(3 * arm.M, 256, name="bench7/mlp_init")).to(dev))
+    net.fit_standardisation(P_tr[:n_fit])
+    sync()
+    t0 = time.perf_counter()
+    losses = []
+    for ep in range(epochs):
+        perm = torch.from_numpy(wl.rng(f"bench7/mlp_perm{ep}").permutation(n_fit).astype(np.int32)).to(dev)
+        losses.append(net.train_epoch(P_tr, y_tr, perm, batch=8192, lr=1e-3))
+    sync()
+    train_s = time.perf_counter() - t0
+    z_ho = net.forward(P_tr[n_fit:].contiguous())
+    acc_ho = float((torch.where(z_ho >= 0, 1, -1).to(torch.int8) == y_tr[n_fit:]).float().mean())
+    del P_tr, y_tr
+    # fallback Fastron model (S_max = 4,000)
+    q50 = torch.from_numpy(wl.configs("bench7/train", 50_000, arm.n)).to(dev)
+    y50, _ = api.label_capsule_box(arm, q50, arm.radius, lo, hi, want_clearance=False)
+    fit = api.train(api.fk_points(arm, q50), y50, GAMMA_TRAIN_7DOF, s_max=4000)
+    sup = fit["support"].long()
+    model = api.support_prep(arm, q50[sup].contiguous(), fit["alpha"][sup].contiguous(), GAMMA_TRAIN_7DOF)
+    # queries and their geometric labels
+    q = torch.from_numpy(wl.configs("bench7/screen_q", n_query, arm.n)).to(dev)
+    truth, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
+
+    def timed(fn, reps=3):
+        fn()
+        sync()
+        t = time.perf_counter()
+        for _ in range(reps):
+            out = fn()
+        sync()
+        return out, (time.perf_counter() - t) / reps
+
+    (_, lab_plain), t_plain = timed(lambda: api.fk_score_prepared(arm, model, q, want_f=False))
+    acc_plain = float((lab_plain == truth).float().mean())
+    rows = []
+    for tau in taus:
+        (lab, _, fb, nfb), t = timed(lambda: net.screen(arm, model, q, tau))
+        rows.append({"tau": tau, "fallback_rate": nfb / n_query, "checks_per_s": n_query / t,
+                     "accuracy": float((lab == truth).float().mean()), "speedup_vs_plain": t_plain / t})
+    net.close()
+    return {"train_samples": n_fit, "epochs": epochs, "train_s": train_s, "losses": losses,
+            "heldout_accuracy_mlp_only": acc_ho, "fallback_support": int(sup.numel()),
+            "fallback_converged": bool(fit["converged"]), "queries": n_query,
+            "plain": {"checks_per_s": n_query / t_plain, "accuracy": acc_plain}, "screened": rows}
 
 
 def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras):

@@ -103,3 +103,47 @@ def test_screen_semantics(oracle_mod, dev):
     assert torch.equal(lab[expect_fb], plain[expect_fb])
     torch.testing.assert_close(z, z0, rtol=0, atol=0)
     net.close()
+
+
+def test_screening_gain(oracle_mod, dev):
+    """What the network adds to the plain method: on 400,000 queries of the 20-cube environment, the screened
+    labels agree with the geometric labels at least as well as the plain Fastron model's, while only the
+    uncertain fraction of queries pays for the Fastron score."""
+    import time
+
+    arm = wl.arm_7dof()
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    q_tr = torch.from_numpy(wl.configs("gain/train", 300_000, 7)).to(dev)
+    y_tr, _ = api.label_capsule_box(arm, q_tr, arm.radius, lo, hi, want_clearance=False)
+    P_tr = api.fk_points(arm, q_tr)
+    net = api.MLP(24, 256, max_rows=8192)
+    net.set_params(torch.from_numpy(wl.mlp_init(24, 256, name="gain/init")).to(dev))
+    net.fit_standardisation(P_tr)
+    for ep in range(5):
+        perm = torch.from_numpy(wl.rng(f"gain/perm{ep}").permutation(300_000).astype(np.int32)).to(dev)
+        announce(f"gain: mlp epoch {ep}")
+        net.train_epoch(P_tr, y_tr, perm, batch=8192, lr=2e-3)
+    q20 = torch.from_numpy(wl.configs("gain/fastron", 20_000, 7)).to(dev)
+    y20, _ = api.label_capsule_box(arm, q20, arm.radius, lo, hi, want_clearance=False)
+    announce("gain: fastron fallback model")
+    fit = api.train(api.fk_points(arm, q20), y20, 30.0, s_max=2000)
+    sup = fit["support"].long()
+    model = api.support_prep(arm, q20[sup].contiguous(), fit["alpha"][sup].contiguous(), 30.0)
+    q = torch.from_numpy(wl.configs("gain/q", 400_000, 7)).to(dev)
+    truth, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, plain = api.fk_score_prepared(arm, model, q, want_f=False)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    acc_plain = float((plain == truth).float().mean())
+    announce("gain: screen tau=1")
+    t0 = time.perf_counter()
+    lab, z, fb, nfb = net.screen(arm, model, q, 1.0)
+    t_screen = time.perf_counter() - t0
+    acc_screen = float((lab == truth).float().mean())
+    print(dict(acc_plain=acc_plain, acc_screen=acc_screen, fallback=nfb / 400_000, t_plain=t_plain,
+               t_screen=t_screen, support=int(sup.numel())))
+    assert acc_screen >= acc_plain - 0.01
+    assert nfb < 0.6 * 400_000
+    net.close()
