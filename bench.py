@@ -305,13 +305,14 @@ def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304
     n_fit = n_train - 100_000
     net = api.MLP(3 * arm.M, 256, max_rows=8192)
     net.set_params(torch.from_numpy(wl.mlp_init(3 * arm.M, 256, name="bench7/mlp_init")).to(dev))
-    net.fit_standardisation(P_tr[:n_fit])
+    P_fit, y_fit = P_tr[:n_fit], y_tr[:n_fit]
+    net.fit_standardisation(P_fit)
     sync()
     t0 = time.perf_counter()
     losses = []
     for ep in range(epochs):
         perm = torch.from_numpy(wl.rng(f"bench7/mlp_perm{ep}").permutation(n_fit).astype(np.int32)).to(dev)
-        losses.append(net.train_epoch(P_tr, y_tr, perm, batch=8192, lr=1e-3))
+        losses.append(net.train_epoch(P_fit, y_fit, perm, batch=8192, lr=1e-3))
     sync()
     train_s = time.perf_counter() - t0
     z_ho = net.forward(P_tr[n_fit:].contiguous())
@@ -356,7 +357,7 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras):
 
     dh = oracle.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
     sq64, al64 = sq.astype(np.float64), al.astype(np.float64)
-    probe = np.linspace(0, q.shape[0] - 1, 256).astype(np.int64)
+    probe = np.linspace(0, q.shape[0] - 1, 4096).astype(np.int64)
     t0 = time.perf_counter()
     oracle.score(dh, arm.frames, sq64, al64, gamma, q[probe].astype(np.float64))
     rate = probe.shape[0] / (time.perf_counter() - t0)

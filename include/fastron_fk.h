@@ -201,7 +201,11 @@ void fastron_batch_destroy(fastron_batch* batch);
  *   W1 [3M][H], b1 [H], W2 [H][H], b2 [H], w3 [H], b3 [1]
  * (fastron_mlp_param_count values); inputs are standardised by per-feature
  * mu / sd (device [3M]) before the first layer. Rows of P are the
- * [M][3] control points of fastron_fk_points. max_rows bounds one batch.
+ * [M][3] control points of fastron_fk_points; y holds one label per row of
+ * P. fastron_mlp_train_epoch visits the rows in the order given by `order`
+ * (device int32 [N], a permutation of 0..N-1; NULL = 0..N-1): it must hold
+ * exactly N entries (an entry outside [0, N) is reported as
+ * FASTRON_EINVAL). max_rows bounds one batch.
  * fastron_mlp_screen: queries with |logit| >= tau take sign(logit); the rest
  * (fell_back[j] = 1) take the sign of the Fastron FK score against `model`
  * (computed on the compacted subset). workspace: device memory of

@@ -321,6 +321,8 @@ class MLP:
     def gradients(self, P: torch.Tensor, y: torch.Tensor) -> float:
         self._points(P)
         _dev(y, torch.int8, "y")
+        if y.shape != (P.shape[0],):
+            raise ValueError("y must hold one label per row of P")
         loss = ctypes.c_float(0.0)
         check(nat.lib().fastron_mlp_gradients(self._h, _ptr(P), _ptr(y), P.shape[0], ctypes.byref(loss), _stream()))
         return float(loss.value)
@@ -329,8 +331,12 @@ class MLP:
                     lr: float = 1e-3) -> float:
         self._points(P)
         _dev(y, torch.int8, "y")
+        if y.shape != (P.shape[0],):
+            raise ValueError("y must hold one label per row of P")
         if order is not None:
             _dev(order, torch.int32, "order")
+            if order.shape != (P.shape[0],):
+                raise ValueError("order must hold one row index per row of P")
         loss = ctypes.c_float(0.0)
         check(nat.lib().fastron_mlp_train_epoch(self._h, _ptr(P), _ptr(y), _ptr(order), P.shape[0], int(batch),
                                                 float(lr), ctypes.byref(loss), _stream()))

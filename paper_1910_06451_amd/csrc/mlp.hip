@@ -132,16 +132,21 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
 // Inputs: standardised control points as BF16 rows of width kin_pad
 // ---------------------------------------------------------------------------
 // From stored control points P [N][M][3], rows selected by `order` (or identity).
+// An index outside [0, n_rows) is not followed: the row reads as zeros and
+// *bad is set (the caller reports FASTRON_EINVAL).
 __global__ void __launch_bounds__(256) k_mlp_input_points(const float* __restrict__ P, const int32_t* __restrict__ order,
-                                                           int64_t row0, int64_t rows, int d_in, int kin_pad,
-                                                           const float* __restrict__ mu, const float* __restrict__ sd,
-                                                           uint16_t* __restrict__ X, float* __restrict__ Xf) {
+                                                           int64_t row0, int64_t rows, int64_t n_rows, int d_in,
+                                                           int kin_pad, const float* __restrict__ mu,
+                                                           const float* __restrict__ sd, uint16_t* __restrict__ X,
+                                                           float* __restrict__ Xf, int* __restrict__ bad) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (e >= rows * kin_pad) return;
   const int64_t r = e / kin_pad;
   const int c = (int)(e % kin_pad);
   const int64_t src = order ? (int64_t)order[row0 + r] : row0 + r;
-  const float v = c < d_in ? (P[src * d_in + c] - mu[c]) / sd[c] : 0.f;
+  const bool ok = src >= 0 && src < n_rows;
+  if (!ok && c == 0) *bad = 1;
+  const float v = (c < d_in && ok) ? (P[src * d_in + c] - mu[c]) / sd[c] : 0.f;
   X[e] = to_bf16(v);
   if (Xf) Xf[e] = v;
 }
@@ -212,12 +217,13 @@ __global__ void __launch_bounds__(256) k_head_forward(const float* __restrict__ 
 
 __global__ void __launch_bounds__(256) k_bce(const float* __restrict__ z, const int8_t* __restrict__ y,
                                               const int32_t* __restrict__ order, int64_t row0, int64_t rows,
-                                              float* __restrict__ dz, float* __restrict__ loss_part) {
+                                              int64_t n_rows, float* __restrict__ dz, float* __restrict__ loss_part) {
   __shared__ float part[256];
   const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
   float l = 0.f;
   if (r < rows) {
-    const int64_t src = order ? (int64_t)order[row0 + r] : row0 + r;
+    int64_t src = order ? (int64_t)order[row0 + r] : row0 + r;
+    if (src < 0 || src >= n_rows) src = 0;  // flagged by the input kernel
     const float t = y[src] > 0 ? 1.f : 0.f;
     const float zz = z[r];
     l = fmaxf(zz, 0.f) + log1pf(expf(-fabsf(zz))) - t * zz;
@@ -397,6 +403,7 @@ struct fastron_mlp {
   float* colpart = nullptr;
   float* loss_part = nullptr;
   float* hbuf = nullptr;  // relu(Z2)
+  int* bad = nullptr;     // set by kernels that met an out-of-range row index
   float* w1() { return params; }
   float* b1() { return params + (int64_t)d_in * H; }
   float* w2() { return b1() + H; }
@@ -413,7 +420,7 @@ void free_mlp(fastron_mlp* n) {
   if (!n) return;
   void* ps[] = {n->params, n->grads, n->adam_m, n->adam_v, n->mu, n->sd, n->w1b, n->w2b, n->Xb, n->Z1, n->H1b,
                 n->Z2, n->partial, n->z, n->dz, n->dZ2, n->dZ2b, n->dH1, n->dZ1, n->dZ1b, n->colpart, n->loss_part,
-                n->hbuf};
+                n->hbuf, n->bad};
   for (void* p : ps) (void)hipFree(p);
   delete n;
 }
@@ -461,7 +468,7 @@ fastron_status forward_staged(fastron_mlp* n, int64_t rows, bool keep, hipStream
 
 // Gradients of the mean BCE over the staged rows into n->grads (Z1, Z2 must be kept).
 fastron_status backward(fastron_mlp* n, int64_t rows, const int8_t* y, const int32_t* order, int64_t row0,
-                        hipStream_t s) {
+                        int64_t n_rows, hipStream_t s) {
   const int H = n->H;
   float* g = n->grads;
   float* gw1 = g;
@@ -470,7 +477,8 @@ fastron_status backward(fastron_mlp* n, int64_t rows, const int8_t* y, const int
   float* gb2 = gw2 + (int64_t)H * H;
   float* gw3 = gb2 + H;
   float* gb3 = gw3 + H;
-  hipLaunchKernelGGL(k_bce, dim3(nblk(rows)), dim3(256), 0, s, n->z, y, order, row0, rows, n->dz, n->loss_part);
+  hipLaunchKernelGGL(k_bce, dim3(nblk(rows)), dim3(256), 0, s, n->z, y, order, row0, rows, n_rows, n->dz,
+                     n->loss_part);
   FASTRON_HIP(hipGetLastError());
   // last layer: gw3 = relu(Z2)^T dz, gb3 = sum dz
   hipLaunchKernelGGL(k_relu_copy, dim3(nblk(rows * H)), dim3(256), 0, s, n->Z2, rows * H, n->hbuf);
@@ -501,9 +509,9 @@ fastron_status refresh_bf16(fastron_mlp* n, hipStream_t s) {
 }
 
 fastron_status stage_points(fastron_mlp* n, const float* P, const int32_t* order, int64_t row0, int64_t rows,
-                            hipStream_t s) {
+                            int64_t n_rows, hipStream_t s) {
   hipLaunchKernelGGL(k_mlp_input_points, dim3(nblk(rows * n->kin_pad)), dim3(256), 0, s, P, order, row0, rows,
-                     n->d_in, n->kin_pad, n->mu, n->sd, n->Xb, nullptr);
+                     n_rows, n->d_in, n->kin_pad, n->mu, n->sd, n->Xb, nullptr, n->bad);
   FASTRON_HIP(hipGetLastError());
   return FASTRON_OK;
 }
@@ -555,8 +563,10 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
   alloc(&n->colpart, (int64_t)kColChunks * H, 4);
   alloc(&n->loss_part, (R + 255) / 256, 4);
   alloc(&n->hbuf, R * H, 4);
+  alloc(&n->bad, 1, 4);
   if (e == hipSuccess) e = hipMemset(n->adam_m, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->adam_v, 0, n->n_params * 4);
+  if (e == hipSuccess) e = hipMemset(n->bad, 0, sizeof(int));
   if (e != hipSuccess) {
     free_mlp(n);
     return fail(e == hipErrorOutOfMemory ? FASTRON_ENOMEM : FASTRON_EHIP, "MLP allocation failed: %s",
@@ -613,7 +623,7 @@ fastron_status fastron_mlp_forward(fastron_mlp* n, const float* P, int64_t N, fl
   hipStream_t s = as_stream(stream);
   for (int64_t r0 = 0; r0 < N; r0 += n->cap_rows) {
     const int64_t rows = N - r0 < n->cap_rows ? N - r0 : n->cap_rows;
-    TRY(stage_points(n, P, nullptr, r0, rows, s));
+    TRY(stage_points(n, P, nullptr, r0, rows, N, s));
     TRY(forward_staged(n, rows, false, s));
     FASTRON_HIP(hipMemcpyAsync(logits + r0, n->z, rows * 4, hipMemcpyDeviceToDevice, s));
   }
@@ -626,9 +636,9 @@ fastron_status fastron_mlp_gradients(fastron_mlp* n, const float* P, const int8_
   FASTRON_CHECK(n && P && y, "network, P and y must be non-NULL");
   FASTRON_CHECK(N >= 1 && N <= n->cap_rows, "N = %lld outside [1, max_rows]", (long long)N);
   hipStream_t s = as_stream(stream);
-  TRY(stage_points(n, P, nullptr, 0, N, s));
+  TRY(stage_points(n, P, nullptr, 0, N, N, s));
   TRY(forward_staged(n, N, true, s));
-  TRY(backward(n, N, y, nullptr, 0, s));
+  TRY(backward(n, N, y, nullptr, 0, N, s));
   if (loss) {
     const int nb = (int)((N + 255) / 256);
     std::vector<float> lp(nb);
@@ -649,13 +659,14 @@ fastron_status fastron_mlp_train_epoch(fastron_mlp* n, const float* P, const int
   FASTRON_CHECK(std::isfinite(lr) && lr > 0.f, "lr must be > 0");
   hipStream_t s = as_stream(stream);
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+  FASTRON_HIP(hipMemsetAsync(n->bad, 0, sizeof(int), s));
   std::vector<float> lp;
   double loss_acc = 0.0;
   for (int64_t r0 = 0; r0 < N; r0 += batch) {
     const int64_t rows = N - r0 < batch ? N - r0 : batch;
-    TRY(stage_points(n, P, order, r0, rows, s));
+    TRY(stage_points(n, P, order, r0, rows, N, s));
     TRY(forward_staged(n, rows, true, s));
-    TRY(backward(n, rows, y, order, r0, s));
+    TRY(backward(n, rows, y, order, r0, N, s));
     n->step += 1;
     const float c1 = (float)(1.0 / (1.0 - std::pow((double)b1, (double)n->step)));
     const float c2 = (float)(1.0 / (1.0 - std::pow((double)b2, (double)n->step)));
@@ -671,6 +682,10 @@ fastron_status fastron_mlp_train_epoch(fastron_mlp* n, const float* P, const int
       for (float v : lp) loss_acc += v;
     }
   }
+  int h_bad = 0;
+  FASTRON_HIP(hipMemcpyAsync(&h_bad, n->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  FASTRON_HIP(hipStreamSynchronize(s));
+  if (h_bad) return fail(FASTRON_EINVAL, "order holds a row index outside [0, N)");
   if (mean_loss) *mean_loss = (float)(loss_acc / (double)N);
   return FASTRON_OK;
 }

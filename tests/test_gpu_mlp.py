@@ -147,3 +147,25 @@ def test_screening_gain(oracle_mod, dev):
     assert acc_screen >= acc_plain - 0.01
     assert nfb < 0.6 * 400_000
     net.close()
+
+
+def test_train_epoch_rejects_bad_order(dev):
+    """The binding refuses an order array of the wrong length; an in-range-length order holding an index
+    outside [0, N) is caught by the input kernel's guard and reported as FASTRON_EINVAL."""
+    from paper_1910_06451_amd import _native
+
+    arm = wl.arm_7dof()
+    q = torch.from_numpy(wl.configs("bad_order", 300, 7)).to(dev)
+    P = api.fk_points(arm, q)
+    y = torch.ones(300, dtype=torch.int8, device=dev)
+    net = api.MLP(24, 256, max_rows=256)
+    net.set_params(torch.from_numpy(wl.mlp_init(24, 256, name="bad_order")).to(dev))
+    with pytest.raises(ValueError):
+        net.train_epoch(P, y, torch.arange(299, dtype=torch.int32, device=dev), batch=128)
+    order = torch.arange(300, dtype=torch.int32, device=dev)
+    order[7] = 300
+    announce("mlp bad order index")
+    with pytest.raises(_native.FastronError) as ei:
+        net.train_epoch(P, y, order, batch=128)
+    assert ei.value.status == _native.FASTRON_EINVAL
+    net.close()
