@@ -35,6 +35,35 @@ sys.path.insert(0, ROOT)
 #   256 CU * 2.4e9 Hz / (5/128 + 1/32) = 8.74e12 cp-evals/s.
 ALU_PEAK_CP_PER_S = 256 * 2.4e9 / (5.0 / 128 + 1.0 / 32)
 
+# HBM bytes per launch of the FP32 score kernel on this workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled
+# by what the same counter reads for a plain 256 MiB device copy (FETCH_SIZE
+# reads 131,083.5 KiB for 262,144 KiB moved, WRITE_SIZE 262,144 KiB). The
+# figures hold for the kernel sources whose hash is recorded here; once those
+# change, the counters must be taken again and traffic is reported as null.
+SCORE_COUNTERS = {
+    "src_sha256_16": "c83ffd75380566bb",
+    "workload": (7, 4000, 1_000_000),  # (M_moving, S, N)
+    "fetch_kib": 16304.875, "fetch_scale": 262144.0 / 131083.5,
+    "write_kib": 4882.8125, "write_scale": 1.0,
+}
+SCORE_SOURCES = ("paper_1910_06451_amd/csrc/score.hip", "paper_1910_06451_amd/csrc/score_device.h",
+                 "paper_1910_06451_amd/csrc/model_layout.h", "paper_1910_06451_amd/csrc/fastron_internal.h",
+                 "paper_1910_06451_amd/build.py")
+
+
+def score_traffic(Mm, S, N):
+    """Measured HBM bytes per score launch, or None if the counters do not cover this kernel build."""
+    import hashlib
+    h = hashlib.sha256()
+    for rel in SCORE_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    c = SCORE_COUNTERS
+    if h.hexdigest()[:16] != c["src_sha256_16"] or (Mm, S, N) != c["workload"]:
+        return None
+    return 1024.0 * (c["fetch_kib"] * c["fetch_scale"] + c["write_kib"] * c["write_scale"])
+
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
@@ -115,7 +144,11 @@ def main():
     cp_per_launch = N * S * Mm
     achieved = cp_per_launch / (k_ms * 1e-3)
     roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_CP_PER_S / 1e12,
-                "unit": "Tcp-eval/s", "frac": achieved / ALU_PEAK_CP_PER_S, "traffic": None,
+                "unit": "Tcp-eval/s", "frac": achieved / ALU_PEAK_CP_PER_S, "traffic": score_traffic(Mm, S, N),
+                "traffic_unit": "HBM bytes per launch",
+                # queries (n floats each) + the FP32 part of the packed support set (256 B header,
+                # 16-support tiles of 80 * Mp + 16 floats) + outputs (float score + int8 label)
+                "algorithmic_bytes": N * arm.n * 4 + 256 + -(-S // 16) * (80 * ((arm.M + 3) & ~3) + 16) * 4 + N * 5,
                 "kernel": f"k_score_mfma<{Mm},double>", "kernel_ms": k_ms, "cp_evals_per_launch": cp_per_launch}
     f_gpu = f.clone()
     lab_gpu = lab.cpu().numpy()

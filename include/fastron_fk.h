@@ -77,6 +77,15 @@ typedef struct {
   const double* offset;  /* [M*3] or NULL = frame origins */
 } fastron_cpoints;
 
+/* Control-point placement of Section III-A (host only, no device work): one
+ * point at the origin of each joint frame 1..n, except that a revolute joint
+ * with a_i = 0 and d_i = 0 gets none, since its origin coincides with the
+ * preceding one. With include_base != 0, frame 0 (the base origin, the same
+ * for every configuration) is listed first. frame is HOST memory with room
+ * for n + 1 entries; *M receives the number written.                       */
+fastron_status fastron_control_point_frames(const fastron_chain* chain, int32_t include_base, int32_t* frame,
+                                           int32_t* M);
+
 /* ---- a1: batched forward kinematics (Section II-A, Eq. 1-2) --------------
  * q [N][n] float joint values -> P [N][M][3] float control-point positions.
  * One thread per configuration; the chain product runs in FP64 when n >= 7,

@@ -16,6 +16,7 @@ for Improved Proxy Collision Checking"):
 * ``dh_link``          -- Section II-A, Eq. 1 (D-H link transform)
 * ``frames``           -- Section II-A, chain product of link transforms
 * ``control_points``   -- Section II-A, Eq. 2 (FK_m(x) = pos(wA_{j_m} T_m))
+* ``control_point_frames`` -- Section III-A, placement of control points at frame origins
 * ``k_rq``             -- Section II-B, Eq. 3 (second-order rational quadratic)
 * ``k_fk``, ``gram``   -- Section III-A, Eq. 4 (FK kernel) and the kernel matrix
 * ``score``            -- Section III-B, model f(x) = sum_i K(S_i, x) alpha_i
@@ -63,6 +64,8 @@ def _load():
     i64 = ctypes.c_int64
     lib.oracle_dh_link.argtypes = [ctypes.c_double] * 4 + [dp]
     lib.oracle_frames.argtypes = [ctypes.c_int, dp, dp, dp, dp]
+    lib.oracle_control_point_frames.argtypes = [ctypes.c_int, dp, ctypes.c_int, ip]
+    lib.oracle_control_point_frames.restype = ctypes.c_int
     lib.oracle_control_points_batch.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, dp, i64, dp, dp]
     lib.oracle_k_rq.argtypes = [dp, dp, ctypes.c_int, ctypes.c_double]
     lib.oracle_k_rq.restype = ctypes.c_double
@@ -141,6 +144,15 @@ def frames(dh, q, base=None) -> np.ndarray:
     T = np.zeros((n + 1) * 16)
     _load().oracle_frames(n, _ptr(dh), _ptr(_d(base)) if base is not None else None, _ptr(q), _ptr(T))
     return T.reshape(n + 1, 4, 4)
+
+
+def control_point_frames(dh, include_base=False) -> np.ndarray:
+    """Section III-A placement rule: frame origins 1..n, skipping revolute joints with a_i = d_i = 0
+    (their origin coincides with the preceding one); frame 0 first when include_base."""
+    dh, n, _ = _check_chain(dh)
+    out = np.zeros(n + 1, dtype=np.int32)
+    M = _load().oracle_control_point_frames(n, _ptr(dh), int(bool(include_base)), _ptr(out, ctypes.c_int))
+    return out[:M].copy()
 
 
 def control_points(dh, frame, q, offset=None, base=None) -> np.ndarray:

@@ -96,6 +96,23 @@ void oracle_control_points(int n, const double* dh, const double* base, int M, c
   free(T);
 }
 
+/* Section III-A, placement of control points: one point at each joint frame
+ * origin, except that a revolute joint with a_i = d_i = 0 gets none, because
+ * its origin always coincides with the preceding one. Frame i (1..n) is the
+ * origin after D-H row i-1. With include_base, frame 0 (the base origin) is
+ * listed first. Returns M; frame receives the kept frame indices in order.   */
+int oracle_control_point_frames(int n, const double* dh, int include_base, int* frame) {
+  int M = 0;
+  if (include_base) frame[M++] = 0;
+  for (int i = 1; i <= n; ++i) {
+    const double* row = dh + DH_COLS * (i - 1);
+    int revolute = (int)row[4] == 0;
+    if (revolute && row[0] == 0.0 && row[2] == 0.0) continue;
+    frame[M++] = i;
+  }
+  return M;
+}
+
 /* Batched control points for N configurations (q is N x n, P is N x M x 3). */
 void oracle_control_points_batch(int n, const double* dh, const double* base, int M, const int* frame,
                                  const double* offset, int64_t N, const double* q, double* P) {

@@ -31,7 +31,7 @@ BF16_SPLIT2 = 0x10
 BF16_SPLIT3 = 0x20
 
 EXPORTED = [
-    "fastron_fk_points", "fastron_model_bytes", "fastron_support_prep", "fastron_fk_score_prepared",
+    "fastron_control_point_frames", "fastron_fk_points", "fastron_model_bytes", "fastron_support_prep", "fastron_fk_score_prepared",
     "fastron_fk_score", "fastron_gram_update", "fastron_train", "fastron_train_f64", "fastron_label_capsule_box",
     "fastron_tune_set", "fastron_tune_get", "fastron_last_error", "fastron_version", "fastron_batch_create",
     "fastron_batch_prepare", "fastron_batch_score", "fastron_batch_autotune", "fastron_batch_capture",
@@ -85,6 +85,8 @@ def lib():
     ch, cp, md = ctypes.POINTER(Chain), ctypes.POINTER(CPoints), ctypes.POINTER(Model)
     pi64 = ctypes.POINTER(ctypes.c_int64)
     sig = {
+        "fastron_control_point_frames": ([ch, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
+                                         i32),
         "fastron_fk_points": ([ch, cp, vp, i64, vp, vp], i32),
         "fastron_model_bytes": ([i64, i32], i64),
         "fastron_support_prep": ([ch, cp, vp, vp, i64, f32, md, vp], i32),

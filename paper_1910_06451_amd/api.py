@@ -15,7 +15,7 @@ from . import _native as nat
 from ._native import HostChain, check
 
 __all__ = [
-    "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train",
+    "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
@@ -46,6 +46,18 @@ def _ptr(t):
 
 def _chain(arm):
     return arm if isinstance(arm, HostChain) else HostChain(arm)
+
+
+def control_point_frames(arm, include_base: bool = False) -> np.ndarray:
+    """Frame indices of the control points placed by the library's Section III-A rule (frame origins,
+    none for a revolute joint with a_i = d_i = 0; frame 0 first when include_base)."""
+    hc = nat.HostChain(arm)
+    out = np.zeros(hc.n + 1, dtype=np.int32)
+    M = ctypes.c_int32(0)
+    nat.check(nat.lib().fastron_control_point_frames(ctypes.byref(hc.chain), int(bool(include_base)),
+                                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                                     ctypes.byref(M)))
+    return out[:M.value].copy()
 
 
 def fk_points(arm, q: torch.Tensor) -> torch.Tensor:

@@ -304,6 +304,25 @@ const char* fastron_last_error(void) { return g_err; }
 
 const char* fastron_version(void) { return "fastron-fk gfx950 1.0"; }
 
+fastron_status fastron_control_point_frames(const fastron_chain* chain, int32_t include_base, int32_t* frame,
+                                           int32_t* M) {
+  clear_error();
+  FASTRON_CHECK(chain != nullptr && frame != nullptr && M != nullptr, "chain, frame and M must be non-NULL");
+  FASTRON_CHECK(chain->n >= 1 && chain->n <= FASTRON_MAX_JOINTS, "chain->n = %d outside [1, %d]", chain->n,
+                FASTRON_MAX_JOINTS);
+  FASTRON_CHECK(chain->a && chain->d, "chain->a and d must be non-NULL");
+  int32_t count = 0;
+  if (include_base) frame[count++] = 0;
+  for (int32_t i = 1; i <= chain->n; ++i) {
+    const bool prismatic = chain->type && chain->type[i - 1] == 1;
+    // a revolute joint with no link length and no offset keeps the preceding origin
+    if (!prismatic && chain->a[i - 1] == 0.0 && chain->d[i - 1] == 0.0) continue;
+    frame[count++] = i;
+  }
+  *M = count;
+  return FASTRON_OK;
+}
+
 int64_t fastron_model_bytes(int64_t S, int32_t M) {
   if (S < 0 || M < 1 || M > FASTRON_MAX_POINTS) return -1;
   return model_bytes(S, M);

@@ -12,14 +12,17 @@
 // a contiguous slice of the training set. Per iteration each workgroup:
 //   1. publishes one record for its slice (min margin and its index, the
 //      weight at that index, max of y(F - alpha) over alpha != 0 and its
-//      index and weight, and its count of nonzero weights);
-//   2. meets the other workgroups at a grid barrier;
+//      index and weight, and its count of nonzero weights), every word tagged
+//      with the iteration's sequence number;
+//   2. waits until it has read every workgroup's record of this iteration
+//      (no central barrier: a record is complete when all its words carry the
+//      current sequence number);
 //   3. reduces all records itself (identically in every workgroup, so every
-//      workgroup takes the same decision without a second barrier);
+//      workgroup takes the same decision without a second exchange);
 //   4. applies the add or the removal to its slice in one pass that also
 //      builds its next record.
-// Records are double-buffered by iteration parity. The barrier spins with a
-// bounded budget and reports FASTRON_EDEVICE instead of hanging.
+// Records are double-buffered by iteration parity. The wait is bounded by a
+// constant-clock budget and reports FASTRON_EDEVICE instead of hanging.
 #include <cmath>
 
 #include "fastron_internal.h"

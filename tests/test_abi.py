@@ -1,0 +1,126 @@
+"""The C ABI without a GPU: the library loads, exports exactly the entry
+points that include/fastron_fk.h declares, the header compiles as C and C++,
+and host-side validation rejects bad arguments before any device work.
+Also checks the library's control-point placement rule (host code, Section
+III-A) against the oracle's."""
+import ctypes
+import os
+import re
+import subprocess
+
+import numpy as np
+import pytest
+
+from paper_1910_06451_amd import _native as nat
+from paper_1910_06451_amd import workloads as wl
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "fastron_fk.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(fastron_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(nat.LIB_PATH):
+        from paper_1910_06451_amd import build
+
+        build.build()
+    return nat.lib()
+
+
+def test_header_declares_what_the_binding_marshals():
+    assert declared_functions() == sorted(nat.EXPORTED)
+
+
+@pytest.mark.parametrize("lang,std", [("c", "-std=c99"), ("c++", "-std=c++17")])
+def test_header_compiles(tmp_path, lang, std):
+    src = tmp_path / ("t.c" if lang == "c" else "t.cpp")
+    src.write_text('#include "fastron_fk.h"\nint main(void) { return (int)FASTRON_OK; }\n')
+    cc = "gcc" if lang == "c" else "g++"
+    subprocess.run([cc, std, "-Wall", "-Wextra", "-Werror", "-pedantic", "-I", os.path.dirname(HEADER),
+                    "-fsyntax-only", str(src)], check=True)
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", nat.LIB_PATH], check=True, capture_output=True,
+                         text=True).stdout
+    exported = sorted({ln.split()[-1] for ln in out.splitlines() if re.search(r" T fastron_", ln)})
+    assert exported == declared_functions()
+
+
+def test_host_only_entry_points(lib):
+    assert lib.fastron_version().decode().startswith("fastron-fk")
+    assert lib.fastron_tune_get(b"train.threads") in (256, 512, 1024)
+    assert lib.fastron_tune_get(b"no.such.key") == -1
+    assert lib.fastron_tune_set(b"no.such.key", 1) == nat.FASTRON_EINVAL
+    assert "no.such.key" in nat.last_error()
+    assert lib.fastron_tune_set(b"train.threads", 300) == nat.FASTRON_EINVAL
+    assert lib.fastron_model_bytes(-1, 8) == -1
+    assert lib.fastron_model_bytes(4000, 17) == -1
+    assert lib.fastron_model_bytes(4000, 8) > 4000 * 8 * 4
+
+
+def test_validation_before_device_work(lib):
+    arm = wl.arm_7dof()
+    hc = nat.HostChain(arm)
+    ch, cp = ctypes.byref(hc.chain), ctypes.byref(hc.cpoints)
+    vp = ctypes.c_void_p
+    # N == 0 is a no-op that needs no device
+    assert lib.fastron_fk_points(ch, cp, None, 0, None, None) == nat.FASTRON_OK
+    assert nat.last_error() == ""
+    assert lib.fastron_fk_points(None, cp, None, 0, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_fk_points(ch, cp, None, -1, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_fk_points(ch, cp, None, 5, None, None) == nat.FASTRON_EINVAL
+    bad = nat.CPoints(1, (ctypes.c_int32 * 1)(8), None)  # frame 8 > n = 7
+    assert lib.fastron_fk_points(ch, ctypes.byref(bad), None, 0, None, None) == nat.FASTRON_EINVAL
+    many = nat.CPoints(17, (ctypes.c_int32 * 17)(*([1] * 17)), None)
+    assert lib.fastron_fk_points(ch, ctypes.byref(many), None, 0, None, None) == nat.FASTRON_EINVAL
+    zero_n = nat.Chain(0, hc.chain.a, hc.chain.alpha, hc.chain.d, None, None, None)
+    assert lib.fastron_fk_points(ctypes.byref(zero_n), cp, None, 0, None, None) == nat.FASTRON_EINVAL
+    ns, up = ctypes.c_int64(0), ctypes.c_int64(0)
+    fake = vp(256)  # never dereferenced: validation fails first
+    args = lambda beta, s_max, gamma=10.0: (fake, fake, 100, 8, gamma, beta, 10, s_max, fake, fake, fake,
+                                            ctypes.byref(ns), ctypes.byref(up), None, None, 0, None)
+    assert lib.fastron_train(*args(0.5, 10)) == nat.FASTRON_EINVAL  # beta < 1 (Eq. 5)
+    assert "beta" in nat.last_error()
+    assert lib.fastron_train(*args(1.0, 0)) == nat.FASTRON_EINVAL  # s_max < 1
+    assert lib.fastron_train(*args(1.0, 10, gamma=0.0)) == nat.FASTRON_EINVAL
+    assert lib.fastron_train(*args(1.0, 10, gamma=float("nan"))) == nat.FASTRON_EINVAL
+    assert lib.fastron_gram_update(fake, 100, 8, 10.0, 100, 1.0, fake, None, None) == nat.FASTRON_EINVAL  # i >= N
+
+
+def _frames_lib(lib, a, d, types, include_base):
+    n = len(a)
+    a = np.asarray(a, np.float64)
+    d = np.asarray(d, np.float64)
+    z = np.zeros(n)
+    t = np.asarray(types, np.int32)
+    dp = lambda x: x.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    chain = nat.Chain(n, dp(a), dp(z), dp(d), None, t.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), None)
+    out = (ctypes.c_int32 * (n + 1))()
+    M = ctypes.c_int32(0)
+    assert lib.fastron_control_point_frames(ctypes.byref(chain), int(include_base), out, ctypes.byref(M)) == 0
+    return list(out[:M.value])
+
+
+def test_control_point_frames_match_oracle(lib, oracle_mod):
+    # hand case: joint 2 is revolute with a = d = 0 (dropped); joint 4 is prismatic with a = d = 0 (kept)
+    a, d, types = [0.3, 0.0, 0.2, 0.0], [0.0, 0.0, 0.1, 0.0], [0, 0, 0, 1]
+    assert _frames_lib(lib, a, d, types, True) == [0, 1, 3, 4]
+    assert _frames_lib(lib, a, d, types, False) == [1, 3, 4]
+    g = wl.rng("abi/frames")
+    for _ in range(50):
+        n = int(g.integers(1, 17))
+        a = np.where(g.random(n) < 0.4, 0.0, g.uniform(0.1, 0.5, n))
+        d = np.where(g.random(n) < 0.5, 0.0, g.uniform(-0.3, 0.3, n))
+        types = (g.random(n) < 0.2).astype(np.int32)
+        for inc in (False, True):
+            ref = oracle_mod.control_point_frames(oracle_mod.dh_table(a, np.zeros(n), d, None, types), inc)
+            assert _frames_lib(lib, a, d, types, inc) == list(ref)

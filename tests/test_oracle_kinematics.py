@@ -118,3 +118,27 @@ def test_7dof_workload_shape(oracle_mod):
     # frame 0 never moves; the end effector stays within the reach sum(a)
     np.testing.assert_array_equal(P[:, 0], 0.0)
     assert np.all(np.linalg.norm(P[:, -1], axis=1) <= arm.a.sum() + 1e-12)
+
+
+def test_control_point_frames_drop_exactly_the_coincident_origins(oracle_mod):
+    """Section III-A placement: a frame is dropped iff its origin coincides with the preceding one for
+    every configuration. Checked against FK itself on random configurations."""
+    g = wl.rng("oracle/placement")
+    a = np.array([0.3, 0.0, 0.2, 0.0, 0.0, 0.25])
+    d = np.array([0.0, 0.0, 0.1, 0.0, 0.15, 0.0])
+    types = np.array([0, 0, 0, 1, 0, 0])  # joint 4 prismatic with a = d = 0: it moves, so it keeps a point
+    alpha = np.array([0.0, np.pi / 2, -np.pi / 2, np.pi / 2, 0.0, -np.pi / 2])
+    dh = oracle_mod.dh_table(a, alpha, d, None, types)
+    kept = list(oracle_mod.control_point_frames(dh, include_base=True))
+    assert kept == [0, 1, 3, 4, 5, 6]
+    assert list(oracle_mod.control_point_frames(dh)) == [1, 3, 4, 5, 6]
+    for _ in range(20):
+        q = g.uniform(-np.pi, np.pi, 6)
+        T = oracle_mod.frames(dh, q)
+        o = T[:, :3, 3]
+        gaps = np.linalg.norm(o[1:] - o[:-1], axis=1)  # gap between origin i and i-1, i = 1..n
+        for i in range(1, 7):
+            if i in kept:
+                assert gaps[i - 1] > 1e-3
+            else:
+                assert gaps[i - 1] <= 1e-15
