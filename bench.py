@@ -164,6 +164,8 @@ def main():
             forms[name] = {"kernel_ms": t, "checks_per_s": N / (t * 1e-3), "vs_fp32": k_ms / t,
                            "labels": lab.cpu().numpy()}
         extras["forms"] = forms
+        log("[bench] precision form: S=16,384, N=4,194,304")
+        extras["precision"] = precision_run(api, wl, arm, gamma, dev, fp64_sample=0 if args.no_cpu_baseline else 262_144)
         log("[bench] training run on 50,000 labelled samples")
         extras["train"] = train_run(api, wl, arm, dev)
         log("[bench] batched form: 256 environments")
@@ -212,6 +214,61 @@ def main():
 # grid search over {10, 30, 100} on 5,000 labelled samples (held-out accuracy
 # 0.832 / 0.846 / 0.834), as the paper selects its parameters by grid search.
 GAMMA_TRAIN_7DOF = 30.0
+
+
+def precision_run(api, wl, arm, gamma, dev, S=16_384, N=4_194_304, fp64_sample=262_144, reps=5):
+    """FP32 score versus the BF16 cross-term forms on S = 16,384 supports and N = 4,194,304 queries: kernel time
+    of each form, max |df| and sign agreement against the FP32 path (all queries) and against the FP64 oracle
+    (an evenly spaced sample of fp64_sample queries; the queries whose |f_fp64| is below a form's max |df| are
+    counted as inherently ambiguous for that form)."""
+    import torch
+
+    sq_np, al_np = wl.model("prec7", S, arm.n)
+    q_np = wl.configs("prec7/q", N, arm.n)
+    sq, al, q = (torch.from_numpy(x).to(dev) for x in (sq_np, al_np, q_np))
+    model = api.support_prep(arm, sq, al, gamma)
+    stream = torch.cuda.current_stream()
+    forms = {"fp32": api.SCORE_FP32, "bf16_plain": api.SCORE_BF16 | api.BF16_PLAIN,
+             "bf16_split2": api.SCORE_BF16 | api.BF16_SPLIT2, "bf16_split3": api.SCORE_BF16 | api.BF16_SPLIT3}
+    res, outs = {}, {}
+    for name, flags in forms.items():
+        f = torch.empty(N, dtype=torch.float32, device=dev)
+        lab = torch.empty(N, dtype=torch.int8, device=dev)
+        api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
+        e1.record(stream)
+        e1.synchronize()
+        t = e0.elapsed_time(e1) / reps
+        outs[name] = (f, lab)
+        res[name] = {"kernel_ms": t, "checks_per_s": N / (t * 1e-3),
+                     "cp_evals_per_s": N * S * int(np.sum(arm.frames > 0)) / (t * 1e-3)}
+    f32, l32 = outs["fp32"]
+    for name, (f, lab) in outs.items():
+        res[name]["vs_fp32"] = {"max_abs_df": float((f - f32).abs().max()),
+                                "sign_agreement": float((lab == l32).float().mean())}
+        res[name]["speed_vs_fp32"] = res["fp32"]["kernel_ms"] / res[name]["kernel_ms"]
+    out = {"S": S, "N": N, "forms": res}
+    if fp64_sample:
+        import oracle
+
+        dh = oracle.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
+        idx = np.linspace(0, N - 1, fp64_sample).astype(np.int64)
+        t0 = time.perf_counter()
+        ref = oracle.score(dh, arm.frames, sq_np.astype(np.float64), al_np.astype(np.float64), gamma,
+                           q_np[idx].astype(np.float64))
+        sign_ref = np.where(ref < 0, -1, 1)
+        out["fp64_sample"] = int(fp64_sample)
+        out["fp64_seconds"] = time.perf_counter() - t0
+        for name, (f, lab) in outs.items():
+            fs = f.cpu().numpy()[idx].astype(np.float64)
+            ls = lab.cpu().numpy()[idx]
+            df = float(np.max(np.abs(fs - ref)))
+            res[name]["vs_fp64"] = {"max_abs_df": df, "sign_agreement": float(np.mean(ls == sign_ref)),
+                                    "ambiguous": int(np.sum(np.abs(ref) < df))}
+    return out
 
 
 def train_run(api, wl, arm, dev):

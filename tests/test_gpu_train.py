@@ -126,3 +126,47 @@ def test_train_edge_cases(oracle_mod, dev):
     announce("train: iter_max = 0")
     out = api.train(P, -torch.ones(300, dtype=torch.int8, device=dev), 10.0, iter_max=0)
     assert not out["converged"] and out["updates"] == 0 and out["support"].numel() == 0
+
+
+def test_three_dof_end_to_end(oracle_mod, dev):
+    """3-DOF workload end to end: 2,000 labelled configurations (5 cubes of side 0.15) -> Algorithm 1 in
+    FP64 on the device -> the trained model scores 10,000 fresh queries in FP32 on the device. The scores
+    must match the oracle's scores of the same model within the FP32 bound, and the accuracy / TPR / TNR
+    against the geometric labels (Eq. 10-12) must match the oracle's up to the inherently ambiguous queries."""
+    from test_gpu_score import check_scores, error_bound
+
+    arm = wl.arm_3dof()
+    dh = oracle_dh(oracle_mod, arm)
+    for seed in range(wl.MASTER_SEED, wl.MASTER_SEED + 200):
+        q = wl.configs("train3", 2000, arm.n, seed=seed)
+        lo, hi = wl.cubes("train3/cubes", 5, 0.15, None, seed=seed)
+        y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+        if 0.1 <= np.mean(y == 1) <= 0.9:
+            break
+    y = y.astype(np.int8)
+    P32 = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
+    ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 10.0)
+    announce("3dof end to end: train_f64 N=2000")
+    q_d = torch.from_numpy(q).to(dev)
+    # training input: the oracle's control points rounded to FP32, so both trajectories see the same values
+    out = api.train(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, fp64=True)
+    sup = out["support"].cpu().numpy()
+    np.testing.assert_array_equal(sup, ref["support"])
+    a32 = out["alpha"].cpu().numpy()[sup].astype(np.float32)
+    qq = wl.configs("train3/queries", 10000, arm.n, seed=seed)
+    yq, _ = oracle_mod.capsule_box_labels(dh, qq.astype(np.float64), arm.radius, lo, hi)
+    announce("3dof end to end: score 10,000 queries")
+    model = api.support_prep(arm, q_d[torch.from_numpy(sup).long().to(dev)].contiguous(),
+                             torch.from_numpy(a32).to(dev), 10.0)
+    f, lab = api.fk_score_prepared(arm, model, torch.from_numpy(qq).to(dev))
+    f, lab = f.cpu().numpy(), lab.cpu().numpy()
+    s64 = q[sup].astype(np.float64)
+    f_ref = oracle_mod.score(dh, arm.frames, s64, a32.astype(np.float64), 10.0, qq.astype(np.float64))
+    tol = error_bound(oracle_mod.control_points(dh, arm.frames, s64), a32, 10.0,
+                      oracle_mod.control_points(dh, arm.frames, qq.astype(np.float64)))
+    stats = check_scores(f, lab, f_ref, tol)
+    m_gpu = oracle_mod.metrics(lab, yq)
+    m_ref = oracle_mod.metrics(np.where(f_ref < 0, -1, 1), yq)
+    print({"support": int(sup.size), **stats, "gpu": m_gpu, "oracle": m_ref})
+    assert abs(m_gpu["accuracy"] - m_ref["accuracy"]) * yq.size <= stats["ambiguous"]
+    assert m_gpu["accuracy"] >= 0.95
