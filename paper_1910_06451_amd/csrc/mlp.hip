@@ -365,6 +365,177 @@ __global__ void k_zero_u64(unsigned long long* p) {
   if (threadIdx.x == 0) *p = 0ull;
 }
 
+// ---------------------------------------------------------------------------
+// Fused screening inference for the 3M (<= 32) -> 256 -> 256 -> 1 network
+// ---------------------------------------------------------------------------
+// One persistent workgroup per CU holds W2 (BF16, 128 KB) in LDS for its whole
+// life and walks tiles of 256 queries; each of its 4 waves owns 64 queries
+// (four 16-query blocks). Per tile a wave
+//   1. computes the FK of its 64 queries (one per lane), standardises them and
+//      stages the BF16 features in LDS;
+//   2. layer 1 on the matrix cores in transposed form, H1^T = W1^T X^T, so
+//      that every lane ends up holding exactly the H1 values it must feed to
+//      layer 2 as an MFMA operand (no trip through LDS): the rows of each W1^T
+//      fragment are permuted so that lane group g (lanes 16g..16g+15) receives
+//      hidden units 32c + 8g .. 32c + 8g + 7 of chunk c;
+//   3. layer 2 as H2^T = W2^T H1^T, each W2 fragment read from LDS once and
+//      applied to the four query blocks, with bias, ReLU and the head
+//      (dot with w3) in the epilogue;
+//   4. reduces the head partials across lane groups, adds b3 and takes the
+//      screening decision (wave-aggregated append to the fallback list).
+// The BF16 rounding points (X, H1) and the FP32 accumulation are the same as
+// in the staged GEMM path.
+constexpr int kInfH = 256;           // hidden width served by the fused kernel
+constexpr int kInfK = 32;            // padded input width
+constexpr int kInfWaves = 4;
+constexpr int kInfTile = 64 * kInfWaves;
+constexpr int kInfXRow = kInfK + 8;  // LDS row of staged features (elements), padded
+
+// Layer-1 fragment v (0..15) covers hidden units 32 (v / 2) + 8 g + 4 (v % 2) + i at MFMA output
+// row 4 g + i of the transposed product.
+__device__ __host__ __forceinline__ int inf_unit1(int v, int row) {
+  return 32 * (v >> 1) + 8 * (row >> 2) + 4 * (v & 1) + (row & 3);
+}
+
+// Packs the FP32 masters into MFMA operand order:
+//   w1p[v][lane][j] = W1[8 (lane / 16) + j][inf_unit1(v, lane % 16)]   (zero past d_in)
+//   w2p[nb][c][lane][j] = W2[32 c + 8 (lane / 16) + j][16 nb + lane % 16]
+__global__ void __launch_bounds__(256) k_pack_infer(const float* __restrict__ w1, const float* __restrict__ w2,
+                                                     int d_in, uint16_t* __restrict__ w1p,
+                                                     uint16_t* __restrict__ w2p) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int64_t n1 = 16 * 64 * 8, n2 = (int64_t)kInfH * kInfH;
+  if (e < n1) {
+    const int j = (int)(e & 7), lane = (int)((e >> 3) & 63), v = (int)(e >> 9);
+    const int k = 8 * (lane >> 4) + j;
+    w1p[e] = k < d_in ? to_bf16(w1[(int64_t)k * kInfH + inf_unit1(v, lane & 15)]) : (uint16_t)0;
+  } else if (e < n1 + n2) {
+    const int64_t f = e - n1;
+    const int j = (int)(f & 7), lane = (int)((f >> 3) & 63), c = (int)((f >> 9) & 7), nb = (int)(f >> 12);
+    const int k = 32 * c + 8 * (lane >> 4) + j;
+    w2p[f] = to_bf16(w2[(int64_t)k * kInfH + 16 * nb + (lane & 15)]);
+  }
+}
+
+struct InferArgs {
+  ChainArgs c;
+  const float* q;
+  int64_t N;
+  int64_t ntiles;
+  const float* mu;
+  const float* sd;
+  const uint16_t* w1p;
+  const float* b1;
+  const uint16_t* w2p;
+  const float* b2;
+  const float* w3;
+  const float* b3;
+  float tau;
+  float* logit;
+  int8_t* label;
+  uint8_t* fell_back;
+  int32_t* fb_idx;
+  unsigned long long* fb_count;
+};
+
+template <typename R>
+__global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
+  __shared__ __align__(16) uint16_t w2s[kInfH * kInfH];
+  __shared__ __align__(16) uint16_t xs[kInfWaves][64][kInfXRow];
+  __shared__ __align__(16) float b1s[kInfH], b2s[kInfH], w3s[kInfH];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
+  {
+    const u8m* src = reinterpret_cast<const u8m*>(a.w2p);
+    u8m* dst = reinterpret_cast<u8m*>(w2s);
+    for (int i = tid; i < kInfH * kInfH / 8; i += kInfTile) dst[i] = src[i];
+    for (int i = tid; i < kInfH; i += kInfTile) {
+      b1s[i] = a.b1[i];
+      b2s[i] = a.b2[i];
+      w3s[i] = a.w3[i];
+    }
+  }
+  const float b3 = a.b3[0];
+  const int din = 3 * a.c.M;
+  uint16_t* xrow = &xs[wave][lane][0];
+  for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
+    __syncthreads();  // W2 staged (first tile); this wave's previous features consumed
+    const int64_t qi = tile * kInfTile + 64 * wave + lane;
+    // 1. FK + standardisation of this lane's query into its LDS row
+#pragma unroll
+    for (int t = 0; t < kInfK / 8; ++t) *reinterpret_cast<u8m*>(xrow + 8 * t) = (u8m){0, 0, 0, 0, 0, 0, 0, 0};
+    if (qi < a.N) {
+      float qv[FASTRON_MAX_JOINTS];
+      for (int i = 0; i < a.c.n; ++i) qv[i] = a.q[qi * a.c.n + i];
+      fk_walk<R>(a.c, qv, [&](int m, float x, float y, float z) {
+        xrow[3 * m + 0] = to_bf16((x - a.mu[3 * m + 0]) / a.sd[3 * m + 0]);
+        xrow[3 * m + 1] = to_bf16((y - a.mu[3 * m + 1]) / a.sd[3 * m + 1]);
+        xrow[3 * m + 2] = to_bf16((z - a.mu[3 * m + 2]) / a.sd[3 * m + 2]);
+      });
+    }
+    (void)din;
+    __syncthreads();
+    // 2. layer 1 (transposed): per fragment v, D[row = unit][col = query]
+    bf8m xb[4];
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb)
+      xb[qb] = __builtin_bit_cast(bf8m, *reinterpret_cast<const u8m*>(&xs[wave][16 * qb + (lane & 15)][8 * g]));
+    u8m h1[4][8];
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(a.w1p)[v * 64 + lane]);
+      const f4m bias = *reinterpret_cast<const f4m*>(&b1s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) {
+        const f4m d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xb[qb], (f4m){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h1[qb][v >> 1][4 * (v & 1) + i] = to_bf16(fmaxf(d[i] + bias[i], 0.f));
+      }
+    }
+    // 3. layer 2 (transposed) with bias, ReLU and the head in the epilogue
+    float lp[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int nb = 0; nb < kInfH / 16; ++nb) {
+      f4m acc[4];
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb) acc[qb] = (f4m){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int c = 0; c < 8; ++c) {
+        const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(w2s)[(nb * 8 + c) * 64 + lane]);
+#pragma unroll
+        for (int qb = 0; qb < 4; ++qb)
+          acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, __builtin_bit_cast(bf8m, h1[qb][c]), acc[qb], 0, 0, 0);
+      }
+      const f4m bias = *reinterpret_cast<const f4m*>(&b2s[16 * nb + 4 * g]);
+      const f4m head = *reinterpret_cast<const f4m*>(&w3s[16 * nb + 4 * g]);
+#pragma unroll
+      for (int qb = 0; qb < 4; ++qb)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) lp[qb] += fmaxf(acc[qb][i] + bias[i], 0.f) * head[i];
+    }
+    // 4. head: sum the four lane groups; lane l then owns query 64 wave + l
+#pragma unroll
+    for (int qb = 0; qb < 4; ++qb) {
+      lp[qb] += __shfl_xor(lp[qb], 16);
+      lp[qb] += __shfl_xor(lp[qb], 32);
+    }
+    const float z = (g == 0 ? lp[0] : g == 1 ? lp[1] : g == 2 ? lp[2] : lp[3]) + b3;
+    const bool valid = qi < a.N;
+    const bool fb = valid && fabsf(z) < a.tau;
+    if (valid) {
+      if (a.logit) a.logit[qi] = z;
+      if (a.fell_back) a.fell_back[qi] = fb ? 1 : 0;
+      if (!fb) a.label[qi] = z >= 0.f ? (int8_t)1 : (int8_t)-1;
+    }
+    const unsigned long long ballot = __ballot(fb);
+    if (ballot) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(a.fb_count, (unsigned long long)__popcll(ballot));
+      base = __shfl(base, 0);
+      if (fb) a.fb_idx[base + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)qi;
+    }
+  }
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace fastron
@@ -386,6 +557,8 @@ struct fastron_mlp {
   float* sd = nullptr;
   uint16_t* w1b = nullptr;  // [kin_pad][H]
   uint16_t* w2b = nullptr;  // [H][H]
+  uint16_t* w1p = nullptr;  // fused-inference operand order (H == 256, d_in <= 32 only)
+  uint16_t* w2p = nullptr;
   int64_t step = 0;
   // activations for a batch of cap_rows
   uint16_t* Xb = nullptr;
@@ -420,7 +593,7 @@ void free_mlp(fastron_mlp* n) {
   if (!n) return;
   void* ps[] = {n->params, n->grads, n->adam_m, n->adam_v, n->mu, n->sd, n->w1b, n->w2b, n->Xb, n->Z1, n->H1b,
                 n->Z2, n->partial, n->z, n->dz, n->dZ2, n->dZ2b, n->dH1, n->dZ1, n->dZ1b, n->colpart, n->loss_part,
-                n->hbuf, n->bad};
+                n->hbuf, n->bad, n->w1p, n->w2p};
   for (void* p : ps) (void)hipFree(p);
   delete n;
 }
@@ -516,6 +689,47 @@ fastron_status stage_points(fastron_mlp* n, const float* P, const int32_t* order
   return FASTRON_OK;
 }
 
+// Fused screening pass (hidden width 256, input width <= 32): packs the
+// operands, then one persistent launch sized to the resident capacity.
+fastron_status screen_fused(fastron_mlp* n, const ChainArgs& c, const float* q, int64_t N, float tau, float* logits,
+                            int8_t* label, uint8_t* fell_back, int32_t* fb_idx, unsigned long long* count,
+                            hipStream_t s) {
+  const int64_t tot = 16 * 64 * 8 + (int64_t)kInfH * kInfH;
+  hipLaunchKernelGGL(k_pack_infer, dim3(nblk(tot)), dim3(256), 0, s, n->w1(), n->w2(), n->d_in, n->w1p, n->w2p);
+  FASTRON_HIP(hipGetLastError());
+  InferArgs a;
+  a.c = c;
+  a.q = q;
+  a.N = N;
+  a.ntiles = (N + kInfTile - 1) / kInfTile;
+  a.mu = n->mu;
+  a.sd = n->sd;
+  a.w1p = n->w1p;
+  a.b1 = n->b1();
+  a.w2p = n->w2p;
+  a.b2 = n->b2();
+  a.w3 = n->w3();
+  a.b3 = n->b3();
+  a.tau = tau;
+  a.logit = logits;
+  a.label = label;
+  a.fell_back = fell_back;
+  a.fb_idx = fb_idx;
+  a.fb_count = count;
+  const void* kfn = c.n >= kFp64Joints ? reinterpret_cast<const void*>(k_mlp_screen_fused<double>)
+                                       : reinterpret_cast<const void*>(k_mlp_screen_fused<float>);
+  int dev = 0, ncu = 0, per_cu = 0;
+  FASTRON_HIP(hipGetDevice(&dev));
+  FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, kInfTile, 0));
+  if (per_cu < 1) return fail(FASTRON_EUNSUPPORTED, "fused screening kernel cannot be resident");
+  int64_t grid = (int64_t)ncu * per_cu;
+  if (grid > a.ntiles) grid = a.ntiles;
+  void* args[] = {&a};
+  FASTRON_HIP(hipLaunchKernel(kfn, dim3((unsigned)grid), dim3(kInfTile), args, 0, s));
+  return FASTRON_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -564,6 +778,10 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
   alloc(&n->loss_part, (R + 255) / 256, 4);
   alloc(&n->hbuf, R * H, 4);
   alloc(&n->bad, 1, 4);
+  if (hidden == kInfH && n->kin_pad == kInfK) {
+    alloc(&n->w1p, 16 * 64 * 8, 2);
+    alloc(&n->w2p, (int64_t)kInfH * kInfH, 2);
+  }
   if (e == hipSuccess) e = hipMemset(n->adam_m, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->adam_v, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->bad, 0, sizeof(int));
@@ -716,6 +934,9 @@ fastron_status fastron_mlp_screen(fastron_mlp* n, const fastron_chain* chain, co
   int8_t* l_sub = reinterpret_cast<int8_t*>(ws + 256 + N * 8 + N * (int64_t)c.n * 4);
   hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, count);
   FASTRON_HIP(hipGetLastError());
+  if (n->w1p && N > 0) {
+    TRY(screen_fused(n, c, q, N, tau, logits, label, fell_back, fb_idx, count, s));
+  } else
   for (int64_t r0 = 0; r0 < N; r0 += n->cap_rows) {
     const int64_t rows = N - r0 < n->cap_rows ? N - r0 : n->cap_rows;
     if (c.n >= kFp64Joints)

@@ -76,7 +76,47 @@ def test_training_learns(oracle_mod, dev):
     net.close()
 
 
-def test_screen_semantics(oracle_mod, dev):
+@pytest.mark.parametrize("N", [1, 63, 3001])
+def test_fused_screen_logits(oracle_mod, dev, N):
+    """The fused screening pass (FK + both layers + head in one persistent kernel) against the staged GEMM
+    forward on the same control points, and against the FP64 oracle; ragged sizes (one query, less than a
+    wave, several tiles plus a partial one)."""
+    arm = wl.arm_7dof()
+    dh = oracle_dh(oracle_mod, arm)
+    q = wl.configs(f"fused_screen/{N}", N, 7)
+    q_d = torch.from_numpy(q).to(dev)
+    P_d = api.fk_points(arm, q_d)
+    params = wl.mlp_init(24, 256, name="fused_screen_init")
+    params[24 * 256:24 * 256 + 256] = wl.rng("fused_screen/b1").normal(0, 0.1, 256)  # nonzero biases
+    params[-257:-1] = wl.rng("fused_screen/w3").normal(0, 0.2, 256)
+    P_stats = api.fk_points(arm, torch.from_numpy(wl.configs("fused_screen/stats", 4096, 7)).to(dev))
+    net = api.MLP(24, 256, max_rows=4096)
+    net.set_params(torch.from_numpy(params).to(dev))
+    net.fit_standardisation(P_stats)
+    sq, al = wl.model("fused_screen_model", 64, 7)
+    model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), 10.0)
+    announce(f"fused screen N={N}")
+    lab, z, fb, nf = net.screen(arm, model, q_d, 0.0)
+    announce(f"staged forward N={N}")
+    z_st = net.forward(P_d)
+    z, z_st = z.cpu().numpy().astype(np.float64), z_st.cpu().numpy().astype(np.float64)
+    diff = np.linalg.norm(z - z_st) / max(np.linalg.norm(z_st), 1e-30)
+    _, _, mu, sd = net.get_params(dev)
+    ps = [p_.astype(np.float64) for p_ in wl.split_mlp_params(params, 24)]
+    X = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).reshape(N, 24)
+    z_ref, _ = mo.forward(ps, X, mu.cpu().numpy().astype(np.float64), sd.cpu().numpy().astype(np.float64))
+    rel = np.linalg.norm(z - z_ref) / max(np.linalg.norm(z_ref), 1e-30)
+    print(dict(N=N, rel_vs_staged=float(diff), rel_vs_oracle=float(rel), max_abs_vs_staged=float(np.abs(z - z_st).max())))
+    assert diff < 1e-3, diff
+    assert rel < 2e-2, rel
+    assert nf == 0
+    assert np.array_equal(lab.cpu().numpy(), np.where(z >= 0, 1, -1).astype(np.int8))
+    net.close()
+
+
+@pytest.mark.parametrize("hidden", [256, 128])
+def test_screen_semantics(oracle_mod, dev, hidden):
+    """hidden = 256 runs the fused screening kernel, hidden = 128 the staged GEMM path."""
     arm = wl.arm_7dof()
     gamma = 10.0
     sq, al = wl.model("mlp_screen_model", 500, 7)
@@ -84,10 +124,10 @@ def test_screen_semantics(oracle_mod, dev):
     sq_d, al_d, q_d = (torch.from_numpy(x).to(dev) for x in (sq, al, q))
     model = api.support_prep(arm, sq_d, al_d, gamma)
     _, plain = api.fk_score_prepared(arm, model, q_d)
-    net = api.MLP(24, 256, max_rows=1024)
-    net.set_params(torch.from_numpy(wl.mlp_init(24, 256, name="mlp_screen_init")).to(dev))
+    net = api.MLP(24, hidden, max_rows=1024)
+    net.set_params(torch.from_numpy(wl.mlp_init(24, hidden, name="mlp_screen_init")).to(dev))
     net.fit_standardisation(api.fk_points(arm, q_d))
-    announce("screen tau=0")
+    announce(f"screen hidden={hidden} tau=0")
     lab0, z0, fb0, n0 = net.screen(arm, model, q_d, 0.0)
     assert n0 == 0 and int(fb0.sum()) == 0
     assert torch.equal(lab0, torch.where(z0 >= 0, 1, -1).to(torch.int8))
