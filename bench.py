@@ -78,6 +78,8 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
+    ap.add_argument("--legs", default="forms,precision,train,batched,retrain,screen",
+                    help="comma-separated extra legs to run (forms, precision, train, batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=6, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -155,7 +157,12 @@ def main():
     f_np = f_gpu.cpu().numpy()
 
     extras = {}
-    if not args.no_extras:
+    legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
+    unknown = legs - {"forms", "precision", "train", "batched", "retrain", "screen"}
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    if "forms" in legs:
         forms = {}
         for name, flags in (("valu", api.SCORE_VALU), ("bf16_plain", api.SCORE_BF16 | api.BF16_PLAIN),
                             ("bf16_split3", api.SCORE_BF16 | api.BF16_SPLIT3)):
@@ -164,14 +171,19 @@ def main():
             forms[name] = {"kernel_ms": t, "checks_per_s": N / (t * 1e-3), "vs_fp32": k_ms / t,
                            "labels": lab.cpu().numpy()}
         extras["forms"] = forms
+    if "precision" in legs:
         log("[bench] precision form: S=16,384, N=4,194,304")
         extras["precision"] = precision_run(api, wl, arm, gamma, dev, fp64_sample=0 if args.no_cpu_baseline else 262_144)
+    if "train" in legs:
         log("[bench] training run on 50,000 labelled samples")
         extras["train"] = train_run(api, wl, arm, dev)
+    if "batched" in legs:
         log("[bench] batched form: 256 environments")
         extras["batched"] = batched_run(api, wl, arm, gamma, dev)
+    if "retrain" in legs:
         log("[bench] re-training 16 environments after their cubes move")
         extras["retrain16"] = retrain_run(api, wl, arm, dev)
+    if "screen" in legs:
         log("[bench] learned screening (MLP + tau fallback)")
         extras["screen"] = screen_run(api, wl, arm, dev, epochs=args.mlp_epochs)
 

@@ -32,10 +32,22 @@ typedef float f4m __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8m __attribute__((ext_vector_type(8)));
 typedef unsigned short u8m __attribute__((ext_vector_type(8)));
 
+typedef float f2m __attribute__((ext_vector_type(2)));
+typedef __bf16 b2m __attribute__((ext_vector_type(2)));
+typedef short s2m __attribute__((ext_vector_type(2)));
+typedef unsigned u4m __attribute__((ext_vector_type(4)));
+
+// FP32 -> BF16, round to nearest even (the hardware conversion).
 __device__ __forceinline__ uint16_t to_bf16(float x) {
-  uint32_t u = __float_as_uint(x);
-  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf / nan pass through
-  return (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  const b2m h = __builtin_convertvector((f2m){x, 0.f}, b2m);
+  return (uint16_t)__builtin_bit_cast(uint32_t, h);
+}
+// Two FP32 values -> packed BF16 pair (RNE) with ReLU applied on the BF16 bit
+// patterns: a BF16 value is negative exactly when its bits, read as int16,
+// are negative, so an int16 max with 0 is the ReLU.
+__device__ __forceinline__ uint32_t relu_bf16x2(float a, float b) {
+  const b2m h = __builtin_convertvector((f2m){a, b}, b2m);
+  return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(__builtin_bit_cast(s2m, h), (s2m){0, 0}));
 }
 __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
@@ -366,10 +378,10 @@ __global__ void k_zero_u64(unsigned long long* p) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused screening inference for the 3M (<= 32) -> 256 -> 256 -> 1 network
+// Fused screening inference for the 3M (<= 24) -> 256 -> 256 -> 1 network
 // ---------------------------------------------------------------------------
 // One persistent workgroup per CU holds W2 (BF16, 128 KB) in LDS for its whole
-// life and walks tiles of 256 queries; each of its 4 waves owns 64 queries
+// life and walks tiles of 512 queries; each of its 8 waves owns 64 queries
 // (four 16-query blocks). Per tile a wave
 //   1. computes the FK of its 64 queries (one per lane), standardises them and
 //      stages the BF16 features in LDS;
@@ -383,13 +395,14 @@ __global__ void k_zero_u64(unsigned long long* p) {
 //      (dot with w3) in the epilogue;
 //   4. reduces the head partials across lane groups, adds b3 and takes the
 //      screening decision (wave-aggregated append to the fallback list).
-// The BF16 rounding points (X, H1) and the FP32 accumulation are the same as
-// in the staged GEMM path.
-constexpr int kInfH = 256;           // hidden width served by the fused kernel
-constexpr int kInfK = 32;            // padded input width
-constexpr int kInfWaves = 4;
+// The BF16 rounding points (X, H1) and the FP32 accumulation are those of the
+// staged GEMM path; the biases enter as the accumulators' initial values
+// instead of being added after the product (rounding differs in the last FP32
+// place).
+constexpr int kInfH = 256;    // hidden width served by the fused kernel
+constexpr int kInfXRow = 24;  // staged features per query (input width <= 24, i.e. M <= 8)
+constexpr int kInfWaves = 8;  // two waves per SIMD: one's VALU work overlaps the other's MFMAs
 constexpr int kInfTile = 64 * kInfWaves;
-constexpr int kInfXRow = kInfK + 8;  // LDS row of staged features (elements), padded
 
 // Layer-1 fragment v (0..15) covers hidden units 32 (v / 2) + 8 g + 4 (v % 2) + i at MFMA output
 // row 4 g + i of the transposed product.
@@ -455,14 +468,13 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
     }
   }
   const float b3 = a.b3[0];
-  const int din = 3 * a.c.M;
   uint16_t* xrow = &xs[wave][lane][0];
   for (int64_t tile = blockIdx.x; tile < a.ntiles; tile += gridDim.x) {
     __syncthreads();  // W2 staged (first tile); this wave's previous features consumed
     const int64_t qi = tile * kInfTile + 64 * wave + lane;
     // 1. FK + standardisation of this lane's query into its LDS row
 #pragma unroll
-    for (int t = 0; t < kInfK / 8; ++t) *reinterpret_cast<u8m*>(xrow + 8 * t) = (u8m){0, 0, 0, 0, 0, 0, 0, 0};
+    for (int t = 0; t < kInfXRow / 8; ++t) *reinterpret_cast<u8m*>(xrow + 8 * t) = (u8m){0, 0, 0, 0, 0, 0, 0, 0};
     if (qi < a.N) {
       float qv[FASTRON_MAX_JOINTS];
       for (int i = 0; i < a.c.n; ++i) qv[i] = a.q[qi * a.c.n + i];
@@ -472,32 +484,37 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
         xrow[3 * m + 2] = to_bf16((z - a.mu[3 * m + 2]) / a.sd[3 * m + 2]);
       });
     }
-    (void)din;
     __syncthreads();
     // 2. layer 1 (transposed): per fragment v, D[row = unit][col = query]
+    // lane group g holds features 8g .. 8g + 7 (group 3: the zero padding 24 .. 31)
     bf8m xb[4];
 #pragma unroll
     for (int qb = 0; qb < 4; ++qb)
-      xb[qb] = __builtin_bit_cast(bf8m, *reinterpret_cast<const u8m*>(&xs[wave][16 * qb + (lane & 15)][8 * g]));
-    u8m h1[4][8];
+      xb[qb] = g < 3 ? __builtin_bit_cast(bf8m, *reinterpret_cast<const u8m*>(&xs[wave][16 * qb + (lane & 15)][8 * g]))
+                     : __builtin_bit_cast(bf8m, (u8m){0, 0, 0, 0, 0, 0, 0, 0});
+    // the bias enters as the accumulator's initial value; ReLU and the BF16
+    // rounding are applied to pairs of outputs
+    u4m h1[4][8];
 #pragma unroll
     for (int v = 0; v < 16; ++v) {
       const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(a.w1p)[v * 64 + lane]);
       const f4m bias = *reinterpret_cast<const f4m*>(&b1s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb) {
-        const f4m d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xb[qb], (f4m){0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h1[qb][v >> 1][4 * (v & 1) + i] = to_bf16(fmaxf(d[i] + bias[i], 0.f));
+        const f4m d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xb[qb], bias, 0, 0, 0);
+        h1[qb][v >> 1][2 * (v & 1)] = relu_bf16x2(d[0], d[1]);
+        h1[qb][v >> 1][2 * (v & 1) + 1] = relu_bf16x2(d[2], d[3]);
       }
     }
-    // 3. layer 2 (transposed) with bias, ReLU and the head in the epilogue
+    // 3. layer 2 (transposed): bias as the initial accumulator, ReLU and the
+    //    head (dot with w3) in the epilogue
     float lp[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll 2
+#pragma unroll 1
     for (int nb = 0; nb < kInfH / 16; ++nb) {
+      const f4m bias = *reinterpret_cast<const f4m*>(&b2s[16 * nb + 4 * g]);
       f4m acc[4];
 #pragma unroll
-      for (int qb = 0; qb < 4; ++qb) acc[qb] = (f4m){0.f, 0.f, 0.f, 0.f};
+      for (int qb = 0; qb < 4; ++qb) acc[qb] = bias;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(w2s)[(nb * 8 + c) * 64 + lane]);
@@ -505,12 +522,11 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
         for (int qb = 0; qb < 4; ++qb)
           acc[qb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, __builtin_bit_cast(bf8m, h1[qb][c]), acc[qb], 0, 0, 0);
       }
-      const f4m bias = *reinterpret_cast<const f4m*>(&b2s[16 * nb + 4 * g]);
       const f4m head = *reinterpret_cast<const f4m*>(&w3s[16 * nb + 4 * g]);
 #pragma unroll
       for (int qb = 0; qb < 4; ++qb)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) lp[qb] += fmaxf(acc[qb][i] + bias[i], 0.f) * head[i];
+        for (int i = 0; i < 4; ++i) lp[qb] = fmaf(fmaxf(acc[qb][i], 0.f), head[i], lp[qb]);
     }
     // 4. head: sum the four lane groups; lane l then owns query 64 wave + l
 #pragma unroll
@@ -557,7 +573,7 @@ struct fastron_mlp {
   float* sd = nullptr;
   uint16_t* w1b = nullptr;  // [kin_pad][H]
   uint16_t* w2b = nullptr;  // [H][H]
-  uint16_t* w1p = nullptr;  // fused-inference operand order (H == 256, d_in <= 32 only)
+  uint16_t* w1p = nullptr;  // fused-inference operand order (H == 256, d_in <= 24 only)
   uint16_t* w2p = nullptr;
   int64_t step = 0;
   // activations for a batch of cap_rows
@@ -689,7 +705,7 @@ fastron_status stage_points(fastron_mlp* n, const float* P, const int32_t* order
   return FASTRON_OK;
 }
 
-// Fused screening pass (hidden width 256, input width <= 32): packs the
+// Fused screening pass (hidden width 256, input width <= 24): packs the
 // operands, then one persistent launch sized to the resident capacity.
 fastron_status screen_fused(fastron_mlp* n, const ChainArgs& c, const float* q, int64_t N, float tau, float* logits,
                             int8_t* label, uint8_t* fell_back, int32_t* fb_idx, unsigned long long* count,
@@ -778,7 +794,7 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
   alloc(&n->loss_part, (R + 255) / 256, 4);
   alloc(&n->hbuf, R * H, 4);
   alloc(&n->bad, 1, 4);
-  if (hidden == kInfH && n->kin_pad == kInfK) {
+  if (hidden == kInfH && d_in <= kInfXRow) {
     alloc(&n->w1p, 16 * 64 * 8, 2);
     alloc(&n->w2p, (int64_t)kInfH * kInfH, 2);
   }
