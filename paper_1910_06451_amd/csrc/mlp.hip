@@ -383,8 +383,8 @@ __global__ void k_zero_u64(unsigned long long* p) {
 // One persistent workgroup per CU holds W2 (BF16, 128 KB) in LDS for its whole
 // life and walks tiles of 512 queries; each of its 8 waves owns 64 queries
 // (four 16-query blocks). Per tile a wave
-//   1. computes the FK of its 64 queries (one per lane), standardises them and
-//      stages the BF16 features in LDS;
+//   1. computes the FK of its 64 queries (one per lane, FP32 chain),
+//      standardises them and stages the BF16 features in LDS;
 //   2. layer 1 on the matrix cores in transposed form, H1^T = W1^T X^T, so
 //      that every lane ends up holding exactly the H1 values it must feed to
 //      layer 2 as an MFMA operand (no trip through LDS): the rows of each W1^T
@@ -394,7 +394,8 @@ __global__ void k_zero_u64(unsigned long long* p) {
 //      applied to the four query blocks, with bias, ReLU and the head
 //      (dot with w3) in the epilogue;
 //   4. reduces the head partials across lane groups, adds b3 and takes the
-//      screening decision (wave-aggregated append to the fallback list).
+//      screening decision (one atomic per workgroup and tile reserves the
+//      room for its fallback queries).
 // The BF16 rounding points (X, H1) and the FP32 accumulation are those of the
 // staged GEMM path; the biases enter as the accumulators' initial values
 // instead of being added after the product (rounding differs in the last FP32
@@ -414,9 +415,11 @@ __device__ __host__ __forceinline__ int inf_unit1(int v, int row) {
 //   w1p[v][lane][j] = W1[8 (lane / 16) + j][inf_unit1(v, lane % 16)]   (zero past d_in)
 //   w2p[nb][c][lane][j] = W2[32 c + 8 (lane / 16) + j][16 nb + lane % 16]
 __global__ void __launch_bounds__(256) k_pack_infer(const float* __restrict__ w1, const float* __restrict__ w2,
-                                                     int d_in, uint16_t* __restrict__ w1p,
-                                                     uint16_t* __restrict__ w2p) {
+                                                     const float* __restrict__ sd, int d_in,
+                                                     uint16_t* __restrict__ w1p, uint16_t* __restrict__ w2p,
+                                                     float* __restrict__ isd) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e < d_in) isd[e] = 1.0f / sd[e];
   constexpr int64_t n1 = 16 * 64 * 8, n2 = (int64_t)kInfH * kInfH;
   if (e < n1) {
     const int j = (int)(e & 7), lane = (int)((e >> 3) & 63), v = (int)(e >> 9);
@@ -436,7 +439,7 @@ struct InferArgs {
   int64_t N;
   int64_t ntiles;
   const float* mu;
-  const float* sd;
+  const float* isd;  // 1 / sd
   const uint16_t* w1p;
   const float* b1;
   const uint16_t* w2p;
@@ -451,11 +454,12 @@ struct InferArgs {
   unsigned long long* fb_count;
 };
 
-template <typename R>
 __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
   __shared__ __align__(16) uint16_t w2s[kInfH * kInfH];
   __shared__ __align__(16) uint16_t xs[kInfWaves][64][kInfXRow];
   __shared__ __align__(16) float b1s[kInfH], b2s[kInfH], w3s[kInfH];
+  __shared__ unsigned fb_wave[kInfWaves];
+  __shared__ unsigned long long fb_base;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4;
   {
     const u8m* src = reinterpret_cast<const u8m*>(a.w2p);
@@ -478,10 +482,10 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
     if (qi < a.N) {
       float qv[FASTRON_MAX_JOINTS];
       for (int i = 0; i < a.c.n; ++i) qv[i] = a.q[qi * a.c.n + i];
-      fk_walk<R>(a.c, qv, [&](int m, float x, float y, float z) {
-        xrow[3 * m + 0] = to_bf16((x - a.mu[3 * m + 0]) / a.sd[3 * m + 0]);
-        xrow[3 * m + 1] = to_bf16((y - a.mu[3 * m + 1]) / a.sd[3 * m + 1]);
-        xrow[3 * m + 2] = to_bf16((z - a.mu[3 * m + 2]) / a.sd[3 * m + 2]);
+      fk_walk<float>(a.c, qv, [&](int m, float x, float y, float z) {
+        xrow[3 * m + 0] = to_bf16((x - a.mu[3 * m + 0]) * a.isd[3 * m + 0]);
+        xrow[3 * m + 1] = to_bf16((y - a.mu[3 * m + 1]) * a.isd[3 * m + 1]);
+        xrow[3 * m + 2] = to_bf16((z - a.mu[3 * m + 2]) * a.isd[3 * m + 2]);
       });
     }
     __syncthreads();
@@ -542,12 +546,21 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
       if (a.fell_back) a.fell_back[qi] = fb ? 1 : 0;
       if (!fb) a.label[qi] = z >= 0.f ? (int8_t)1 : (int8_t)-1;
     }
+    // fallback list: one atomic per workgroup and tile, then each wave writes
+    // its queries behind those of the lower waves
     const unsigned long long ballot = __ballot(fb);
-    if (ballot) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(a.fb_count, (unsigned long long)__popcll(ballot));
-      base = __shfl(base, 0);
-      if (fb) a.fb_idx[base + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)qi;
+    if (lane == 0) fb_wave[wave] = (unsigned)__popcll(ballot);
+    __syncthreads();
+    if (tid == 0) {
+      unsigned tot = 0;
+      for (int w = 0; w < kInfWaves; ++w) tot += fb_wave[w];
+      fb_base = tot ? atomicAdd(a.fb_count, (unsigned long long)tot) : 0ull;
+    }
+    __syncthreads();
+    if (fb) {
+      unsigned long long off = fb_base;
+      for (int w = 0; w < wave; ++w) off += fb_wave[w];
+      a.fb_idx[off + __popcll(ballot & ((1ull << lane) - 1ull))] = (int32_t)qi;
     }
   }
 }
@@ -575,6 +588,7 @@ struct fastron_mlp {
   uint16_t* w2b = nullptr;  // [H][H]
   uint16_t* w1p = nullptr;  // fused-inference operand order (H == 256, d_in <= 24 only)
   uint16_t* w2p = nullptr;
+  float* isd = nullptr;     // 1 / sd for the fused pass
   int64_t step = 0;
   // activations for a batch of cap_rows
   uint16_t* Xb = nullptr;
@@ -609,7 +623,7 @@ void free_mlp(fastron_mlp* n) {
   if (!n) return;
   void* ps[] = {n->params, n->grads, n->adam_m, n->adam_v, n->mu, n->sd, n->w1b, n->w2b, n->Xb, n->Z1, n->H1b,
                 n->Z2, n->partial, n->z, n->dz, n->dZ2, n->dZ2b, n->dH1, n->dZ1, n->dZ1b, n->colpart, n->loss_part,
-                n->hbuf, n->bad, n->w1p, n->w2p};
+                n->hbuf, n->bad, n->w1p, n->w2p, n->isd};
   for (void* p : ps) (void)hipFree(p);
   delete n;
 }
@@ -711,7 +725,8 @@ fastron_status screen_fused(fastron_mlp* n, const ChainArgs& c, const float* q, 
                             int8_t* label, uint8_t* fell_back, int32_t* fb_idx, unsigned long long* count,
                             hipStream_t s) {
   const int64_t tot = 16 * 64 * 8 + (int64_t)kInfH * kInfH;
-  hipLaunchKernelGGL(k_pack_infer, dim3(nblk(tot)), dim3(256), 0, s, n->w1(), n->w2(), n->d_in, n->w1p, n->w2p);
+  hipLaunchKernelGGL(k_pack_infer, dim3(nblk(tot)), dim3(256), 0, s, n->w1(), n->w2(), n->sd, n->d_in, n->w1p,
+                     n->w2p, n->isd);
   FASTRON_HIP(hipGetLastError());
   InferArgs a;
   a.c = c;
@@ -719,7 +734,7 @@ fastron_status screen_fused(fastron_mlp* n, const ChainArgs& c, const float* q, 
   a.N = N;
   a.ntiles = (N + kInfTile - 1) / kInfTile;
   a.mu = n->mu;
-  a.sd = n->sd;
+  a.isd = n->isd;
   a.w1p = n->w1p;
   a.b1 = n->b1();
   a.w2p = n->w2p;
@@ -732,8 +747,9 @@ fastron_status screen_fused(fastron_mlp* n, const ChainArgs& c, const float* q, 
   a.fell_back = fell_back;
   a.fb_idx = fb_idx;
   a.fb_count = count;
-  const void* kfn = c.n >= kFp64Joints ? reinterpret_cast<const void*>(k_mlp_screen_fused<double>)
-                                       : reinterpret_cast<const void*>(k_mlp_screen_fused<float>);
+  // FP32 chain for the network's features at any n: they are rounded to BF16
+  // (2^-9 relative) right after, far coarser than the FP32 chain's error.
+  const void* kfn = reinterpret_cast<const void*>(k_mlp_screen_fused);
   int dev = 0, ncu = 0, per_cu = 0;
   FASTRON_HIP(hipGetDevice(&dev));
   FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
@@ -797,6 +813,7 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
   if (hidden == kInfH && d_in <= kInfXRow) {
     alloc(&n->w1p, 16 * 64 * 8, 2);
     alloc(&n->w2p, (int64_t)kInfH * kInfH, 2);
+    alloc(&n->isd, d_in, 4);
   }
   if (e == hipSuccess) e = hipMemset(n->adam_m, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->adam_v, 0, n->n_params * 4);
