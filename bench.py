@@ -78,8 +78,8 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
-    ap.add_argument("--legs", default="forms,precision,train,batched,retrain,screen",
-                    help="comma-separated extra legs to run (forms, precision, train, batched, retrain, screen)")
+    ap.add_argument("--legs", default="kernels,forms,precision,train,batched,retrain,screen",
+                    help="comma-separated extra legs (kernels, forms, precision, train, batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=6, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -158,10 +158,13 @@ def main():
 
     extras = {}
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"forms", "precision", "train", "batched", "retrain", "screen"}
+    unknown = legs - {"kernels", "forms", "precision", "train", "batched", "retrain", "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
+    if "kernels" in legs:
+        log("[bench] FK, Gram-column and labeller kernels on 4,194,304 configurations")
+        extras["kernels"] = kernels_run(api, wl, arm, dev)
     if "forms" in legs:
         forms = {}
         for name, flags in (("valu", api.SCORE_VALU), ("bf16_plain", api.SCORE_BF16 | api.BF16_PLAIN),
@@ -226,6 +229,45 @@ def main():
 # grid search over {10, 30, 100} on 5,000 labelled samples (held-out accuracy
 # 0.832 / 0.846 / 0.834), as the paper selects its parameters by grid search.
 GAMMA_TRAIN_7DOF = 30.0
+
+
+def _event_ms(fn, reps):
+    import torch
+
+    fn()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
+    """The HBM-bound kernels of the path against 8 TB/s, and the labeller's rate: batched FK (reads n floats,
+    writes 3M floats per configuration), one Gram-column update over N training points (reads 3M floats and
+    F, writes F), and capsule-box labels against 20 cubes (FP64)."""
+    import torch
+
+    q = torch.from_numpy(wl.configs("kern/q", N, arm.n)).to(dev)
+    P = api.fk_points(arm, q)
+    F = torch.zeros(N, dtype=torch.float32, device=dev)
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    t_fk = _event_ms(lambda: api.fk_points(arm, q), reps)
+    t_gram = _event_ms(lambda: api.gram_update(P, 10.0, 12345, 0.5, F=F, want_kcol=False), reps)
+    t_lab = _event_ms(lambda: api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False), 3)
+    b_fk = N * (arm.n * 4 + arm.M * 12)
+    b_gram = N * (arm.M * 12 + 8)
+    hbm = 8.0e12
+    return {"N": N,
+            "fk_points": {"ms": t_fk, "configs_per_s": N / (t_fk * 1e-3), "bytes": b_fk,
+                          "GB_per_s": b_fk / (t_fk * 1e-3) / 1e9, "frac_hbm": b_fk / (t_fk * 1e-3) / hbm},
+            "gram_update": {"ms": t_gram, "points_per_s": N / (t_gram * 1e-3), "bytes": b_gram,
+                            "GB_per_s": b_gram / (t_gram * 1e-3) / 1e9, "frac_hbm": b_gram / (t_gram * 1e-3) / hbm},
+            "label_capsule_box": {"ms": t_lab, "configs_per_s": N / (t_lab * 1e-3),
+                                  "segment_box_tests_per_s": N * arm.n * 20 / (t_lab * 1e-3)}}
 
 
 def precision_run(api, wl, arm, gamma, dev, S=16_384, N=4_194_304, fp64_sample=262_144, reps=5):

@@ -91,21 +91,35 @@ fastron_status pack_chain(const fastron_chain* chain, const fastron_cpoints* cp,
 // ---------------------------------------------------------------------------
 // a1: one thread per configuration.
 // ---------------------------------------------------------------------------
+// The block's rows of q and of P are contiguous in memory, so both pass
+// through LDS: the block reads its 256 n floats and writes its 256 x 3M
+// floats with consecutive lanes on consecutive words, and each thread works
+// on its own row in LDS. Dynamic LDS: 256 (n + 3M) floats (at most 64 KB).
 template <typename R>
 __global__ void __launch_bounds__(256) k_fk_points(ChainArgs c, const float* __restrict__ q, int64_t N,
                                                     float* __restrict__ P) {
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= N) return;
-  float qv[FASTRON_MAX_JOINTS];
+  extern __shared__ float rows[];
+  const int n = c.n, w = 3 * c.M;
+  float* qs = rows;              // [256][n]
+  float* ps = rows + 256 * n;    // [256][w]
+  const int64_t j0 = (int64_t)blockIdx.x * 256;
+  const int nrow = (int)(N - j0 < 256 ? N - j0 : 256);
+  for (int e = threadIdx.x; e < nrow * n; e += 256) qs[e] = q[j0 * n + e];
+  __syncthreads();
+  if ((int)threadIdx.x < nrow) {
+    float qv[FASTRON_MAX_JOINTS];
 #pragma unroll
-  for (int i = 0; i < FASTRON_MAX_JOINTS; ++i)
-    if (i < c.n) qv[i] = q[j * c.n + i];
-  float* out = P + j * (int64_t)c.M * 3;
-  fk_walk<R>(c, qv, [&](int m, float x, float y, float z) {
-    out[3 * m + 0] = x;
-    out[3 * m + 1] = y;
-    out[3 * m + 2] = z;
-  });
+    for (int i = 0; i < FASTRON_MAX_JOINTS; ++i)
+      if (i < n) qv[i] = qs[threadIdx.x * n + i];
+    float* out = ps + threadIdx.x * w;
+    fk_walk<R>(c, qv, [&](int m, float x, float y, float z) {
+      out[3 * m + 0] = x;
+      out[3 * m + 1] = y;
+      out[3 * m + 2] = z;
+    });
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < nrow * w; e += 256) P[j0 * w + e] = ps[e];
 }
 
 // ---------------------------------------------------------------------------
@@ -340,10 +354,11 @@ fastron_status fastron_fk_points(const fastron_chain* chain, const fastron_cpoin
   FASTRON_CHECK(aligned(q, 4) && aligned(P, 4), "q and P must be 4-byte aligned");
   const int64_t blocks = (N + 255) / 256;
   FASTRON_CHECK(blocks <= INT32_MAX, "N too large");
+  const size_t lds = (size_t)256 * (c.n + 3 * c.M) * sizeof(float);
   if (c.n >= kFp64Joints)
-    hipLaunchKernelGGL(k_fk_points<double>, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), c, q, N, P);
+    hipLaunchKernelGGL(k_fk_points<double>, dim3((unsigned)blocks), dim3(256), lds, as_stream(stream), c, q, N, P);
   else
-    hipLaunchKernelGGL(k_fk_points<float>, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), c, q, N, P);
+    hipLaunchKernelGGL(k_fk_points<float>, dim3((unsigned)blocks), dim3(256), lds, as_stream(stream), c, q, N, P);
   FASTRON_HIP(hipGetLastError());
   return FASTRON_OK;
 }

@@ -181,3 +181,63 @@ def test_score_edge_cases(oracle_mod, dev):
     Ps = oracle_mod.control_points(dh, one.frames, sq.astype(np.float64))
     Pq = oracle_mod.control_points(dh, one.frames, q.cpu().numpy().astype(np.float64))
     check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, error_bound(Ps, alp, gamma, Pq), min_agree=0.99)
+
+
+def _random_chain(name, n, frames, offsets=False, prismatic=()):
+    g = wl.rng(name)
+    a = g.uniform(0.05, 0.2, n)
+    alpha = g.choice(np.array([0.0, np.pi / 2, -np.pi / 2]), size=n)
+    d = g.uniform(-0.1, 0.1, n)
+    jt = np.zeros(n, dtype=np.int32)
+    jt[list(prismatic)] = 1
+    frames = np.asarray(frames, dtype=np.int32)
+    off = g.uniform(-0.05, 0.05, (frames.shape[0], 3)) if offsets else None
+    return wl.Arm(a=a, alpha=alpha, d=d, theta=g.uniform(-0.5, 0.5, n), joint_type=jt, frames=frames, offsets=off)
+
+
+@pytest.mark.parametrize("case", ["n16_M16", "n12_M9_offsets_prismatic", "n2_M3_base", "n5_M13_repeated"])
+def test_score_general_chains(oracle_mod, dev, case):
+    """Largest supported chain (16 joints, 16 moving points), point offsets and prismatic joints, a base-frame
+    point next to moving ones, and control points repeated on the same frame; S and N ragged."""
+    if case == "n16_M16":
+        arm = _random_chain(case, 16, np.arange(1, 17))
+    elif case == "n12_M9_offsets_prismatic":
+        arm = _random_chain(case, 12, [1, 2, 4, 5, 7, 8, 10, 11, 12], offsets=True, prismatic=(2, 9))
+    elif case == "n2_M3_base":
+        arm = _random_chain(case, 2, [0, 1, 2])
+    else:
+        arm = _random_chain(case, 5, [1, 1, 2, 3, 3, 3, 4, 5, 5, 2, 4, 1, 5], offsets=True)
+    gamma, S, N = 10.0, 301, 517
+    sq, al = wl.model(case, S, arm.n)
+    q = wl.configs(case + "/q", N, arm.n)
+    announce(f"fk_score general chain {case}")
+    f, lab = api.fk_score(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma,
+                          torch.from_numpy(q).to(dev))
+    dh = oracle_mod.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64),
+                           offset=arm.offsets)
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64), offset=arm.offsets)
+    Pq = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64), offset=arm.offsets)
+    print(check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, error_bound(Ps, al, gamma, Pq), min_agree=0.995))
+
+
+def test_score_duplicate_supports_and_wide_gamma(oracle_mod, dev):
+    """Degenerate inputs: every support repeated (weights split between the copies give the same f as the
+    merged weight) and kernel widths from 0.01 to 1e4."""
+    arm = wl.arm_7dof()
+    sq, al = wl.model("dup", 200, 7)
+    q = torch.from_numpy(wl.configs("dup/q", 300, 7)).to(dev)
+    sq2 = np.concatenate([sq, sq])
+    al2 = np.concatenate([0.25 * al, 0.75 * al]).astype(np.float32)
+    dh = oracle_dh(oracle_mod, arm)
+    for gamma in (0.01, 10.0, 1e4):
+        announce(f"duplicate supports gamma={gamma}")
+        f1, _ = api.fk_score(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma, q)
+        f2, l2 = api.fk_score(arm, torch.from_numpy(sq2).to(dev), torch.from_numpy(al2).to(dev), gamma, q)
+        ref = oracle_mod.score(dh, arm.frames, sq2.astype(np.float64), al2.astype(np.float64), gamma,
+                               q.cpu().numpy().astype(np.float64))
+        Ps = oracle_mod.control_points(dh, arm.frames, sq2.astype(np.float64))
+        Pq = oracle_mod.control_points(dh, arm.frames, q.cpu().numpy().astype(np.float64))
+        tol = error_bound(Ps, al2, gamma, Pq)
+        check_scores(f2.cpu().numpy(), l2.cpu().numpy(), ref, tol, min_agree=0.99)
+        assert np.all(np.abs(f1.cpu().numpy() - f2.cpu().numpy()) <= 2 * tol)
