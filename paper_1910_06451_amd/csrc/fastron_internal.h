@@ -3,6 +3,8 @@
 // forward kinematics). Not installed; the public ABI is include/fastron_fk.h.
 #pragma once
 
+#include <type_traits>
+
 #include <hip/hip_runtime.h>
 
 #include <cstdarg>
@@ -85,8 +87,28 @@ inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_
 __device__ __forceinline__ void sincos_r(double x, double* s, double* c) { sincos(x, s, c); }
 __device__ __forceinline__ void sincos_r(float x, float* s, float* c) { sincosf(x, s, c); }
 
-template <typename R, typename Emit>
+// Hardware sine / cosine (absolute error about 1e-6 for the joint ranges
+// here): for consumers that round the positions far more coarsely right
+// after, such as the screening network's BF16 features.
+struct FastTrig {};
+__device__ __forceinline__ void sincos_r(float x, float* s, float* c, FastTrig) {
+  *s = __sinf(x);
+  *c = __cosf(x);
+}
+
+// R = double or float; R = FastTrig computes in float with hardware sin/cos.
+template <typename R>
+struct FkReal {
+  typedef R type;
+};
+template <>
+struct FkReal<FastTrig> {
+  typedef float type;
+};
+
+template <typename RT, typename Emit>
 __device__ __forceinline__ void fk_walk(const ChainArgs& c, const float* q, Emit&& emit) {
+  typedef typename FkReal<RT>::type R;
   R xx = (R)c.base_r[0], xy = (R)c.base_r[3], xz = (R)c.base_r[6];
   R yx = (R)c.base_r[1], yy = (R)c.base_r[4], yz = (R)c.base_r[7];
   R zx = (R)c.base_r[2], zy = (R)c.base_r[5], zz = (R)c.base_r[8];
@@ -109,7 +131,10 @@ __device__ __forceinline__ void fk_walk(const ChainArgs& c, const float* q, Emit
     R th = (R)c.th[i], dd = (R)c.d[i];
     if ((c.prismatic >> i) & 1u) dd += qi; else th += qi;
     R st, ct;
-    sincos_r(th, &st, &ct);
+    if constexpr (std::is_same<RT, FastTrig>::value)
+      sincos_r(th, &st, &ct, FastTrig{});
+    else
+      sincos_r(th, &st, &ct);
     R ux = ct * xx + st * yx, uy = ct * xy + st * yy, uz = ct * xz + st * yz;
     R vx = ct * yx - st * xx, vy = ct * yy - st * xy, vz = ct * yz - st * xz;
     R a = (R)c.a[i], cal = (R)c.ca[i], sal = (R)c.sa[i];

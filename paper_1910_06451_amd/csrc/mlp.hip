@@ -383,8 +383,9 @@ __global__ void k_zero_u64(unsigned long long* p) {
 // One persistent workgroup per CU holds W2 (BF16, 128 KB) in LDS for its whole
 // life and walks tiles of 512 queries; each of its 8 waves owns 64 queries
 // (four 16-query blocks). Per tile a wave
-//   1. computes the FK of its 64 queries (one per lane, FP32 chain),
-//      standardises them and stages the BF16 features in LDS;
+//   1. computes the FK of its 64 queries (one per lane, FP32 chain with
+//      hardware sin / cos), standardises them and stages the BF16 features
+//      in LDS;
 //   2. layer 1 on the matrix cores in transposed form, H1^T = W1^T X^T, so
 //      that every lane ends up holding exactly the H1 values it must feed to
 //      layer 2 as an MFMA operand (no trip through LDS): the rows of each W1^T
@@ -482,7 +483,7 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
     if (qi < a.N) {
       float qv[FASTRON_MAX_JOINTS];
       for (int i = 0; i < a.c.n; ++i) qv[i] = a.q[qi * a.c.n + i];
-      fk_walk<float>(a.c, qv, [&](int m, float x, float y, float z) {
+      fk_walk<FastTrig>(a.c, qv, [&](int m, float x, float y, float z) {
         xrow[3 * m + 0] = to_bf16((x - a.mu[3 * m + 0]) * a.isd[3 * m + 0]);
         xrow[3 * m + 1] = to_bf16((y - a.mu[3 * m + 1]) * a.isd[3 * m + 1]);
         xrow[3 * m + 2] = to_bf16((z - a.mu[3 * m + 2]) * a.isd[3 * m + 2]);
@@ -747,8 +748,9 @@ fastron_status screen_fused(fastron_mlp* n, const ChainArgs& c, const float* q, 
   a.fell_back = fell_back;
   a.fb_idx = fb_idx;
   a.fb_count = count;
-  // FP32 chain for the network's features at any n: they are rounded to BF16
-  // (2^-9 relative) right after, far coarser than the FP32 chain's error.
+  // FP32 chain with hardware sin / cos for the network's features at any n:
+  // they are rounded to BF16 (2^-9 relative) right after, far coarser than
+  // the chain's error.
   const void* kfn = reinterpret_cast<const void*>(k_mlp_screen_fused);
   int dev = 0, ncu = 0, per_cu = 0;
   FASTRON_HIP(hipGetDevice(&dev));
