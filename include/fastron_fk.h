@@ -253,8 +253,12 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
 
 /* ---- tuning ----------------------------------------------------------------
  * Process-wide launch parameters (host side):
- *   "train.blocks"  workgroups of the persistent training grid, 0 = automatic
- *   "train.threads" threads per training workgroup: 256, 512 or 1024
+ *   "train.kernel"      1 (default): single-wave workgroups, no workgroup
+ *                       barriers; 0: multi-wave workgroups (also used when
+ *                       the single-wave grid would exceed its limits)
+ *   "train.wave_groups" grid cap of the single-wave kernel, 1..512 (256)
+ *   "train.blocks"      workgroups of the multi-wave grid, 0 = automatic
+ *   "train.threads"     threads per multi-wave workgroup: 256, 512 or 1024
  * fastron_tune_get returns -1 for an unknown key.                         */
 fastron_status fastron_tune_set(const char* key, int64_t value);
 int64_t fastron_tune_get(const char* key);

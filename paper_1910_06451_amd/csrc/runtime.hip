@@ -21,6 +21,8 @@ std::unordered_map<std::string, Knob>& table() {
   static std::unordered_map<std::string, Knob> t = {
       {"train.blocks", {0, 0, 4096, false}},    // 0 = automatic
       {"train.threads", {512, 256, 1024, true}},
+      {"train.kernel", {1, 0, 1, false}},         // 1 = single-wave workgroups, 0 = multi-wave
+      {"train.wave_groups", {256, 1, 512, false}},  // grid cap of the single-wave kernel
   };
   return t;
 }

@@ -442,6 +442,188 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
   }
 }
 
+// Whole-wave reduction of records with butterflies, every lane ends with the
+// result: the (value, index) pairs are compared lexicographically (lowest
+// index on ties) and the count summed; the payloads (weights, label) come
+// from the lane that holds the winning index (indices are unique across the
+// lanes' records).
+template <typename T>
+__device__ __forceinline__ Rec<T> wave_allreduce(const Rec<T>& r) {
+  T mv = r.minval, xv = r.maxval;
+  int mi = r.minidx, xi = r.maxidx, cnt = r.count;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    const T omv = __shfl_xor(mv, off), oxv = __shfl_xor(xv, off);
+    const int omi = __shfl_xor(mi, off), oxi = __shfl_xor(xi, off);
+    cnt += __shfl_xor(cnt, off);
+    const bool tmin = omi >= 0 && (mi < 0 || omv < mv || (omv == mv && omi < mi));
+    const bool tmax = oxi >= 0 && (xi < 0 || oxv > xv || (oxv == xv && oxi < xi));
+    mv = tmin ? omv : mv;
+    mi = tmin ? omi : mi;
+    xv = tmax ? oxv : xv;
+    xi = tmax ? oxi : xi;
+  }
+  Rec<T> o = rec_empty<T>();
+  o.count = cnt;
+  if (mi >= 0) {
+    const int src = __builtin_ctzll(__ballot(r.minidx == mi));
+    o.minval = mv;
+    o.minidx = mi;
+    o.a_at_min = __shfl(r.a_at_min, src);
+    o.ymin = __shfl(r.ymin, src);
+  }
+  if (xi >= 0) {
+    const int src = __builtin_ctzll(__ballot(r.maxidx == xi));
+    o.maxval = xv;
+    o.maxidx = xi;
+    o.a_at_max = __shfl(r.a_at_max, src);
+  }
+  return o;
+}
+
+// Single-wave form of the same algorithm: one wave per workgroup, so no
+// workgroup barrier stands between the column pass, the record exchange and
+// the decision. Each lane reads the records of workgroups lane, lane + 64, ...
+// (at most kWaveChunks x 64 workgroups), issuing the loads of all its records
+// before checking their tags.
+constexpr int kWaveChunks = 8;
+
+template <typename T, int PT>
+__global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
+  constexpr int K = RecWords<T>::K;
+  __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
+  extern __shared__ float pslice[];  // this slice's control points when they fit (st.p_in_lds)
+  const unsigned G = gridDim.x;
+  const int lane = threadIdx.x;
+  const int64_t j0 = (int64_t)blockIdx.x * st.chunk;
+  const int64_t j1 = (j0 + st.chunk < st.N) ? j0 + st.chunk : st.N;
+  const int M = st.M;
+  if (st.p_in_lds)
+    for (int64_t e = lane; e < (j1 - j0) * 3 * M; e += 64) pslice[e] = st.P[j0 * 3 * M + e];
+  __syncthreads();
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(st.rec);  // [2][G][K]
+
+  T y[PT], F[PT], a[PT];
+  int64_t jj[PT];
+  Rec<T> r = rec_empty<T>();
+#pragma unroll
+  for (int k = 0; k < PT; ++k) {
+    jj[k] = j0 + lane + (int64_t)k * 64;
+    if (jj[k] < j1) {
+      y[k] = (T)st.y[jj[k]];
+      F[k] = st.F[jj[k]];
+      a[k] = st.alpha[jj[k]];
+      point_record(r, jj[k], y[k], F[k], a[k]);
+    } else {
+      y[k] = 0;
+      F[k] = 0;
+      a[k] = 0;
+    }
+  }
+  r = wave_allreduce(r);
+
+  int64_t updates = 0;
+  int64_t status = 1;
+  for (int64_t it = 0;; ++it) {
+    const unsigned long long seq = (unsigned long long)(uint32_t)(it + 1) << 32;
+    unsigned long long* slot = words + (size_t)(it & 1) * G * K;
+    if (lane < K)
+      __hip_atomic_store(slot + (size_t)blockIdx.x * K + lane, seq | RecWords<T>::get(r, lane), __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+    uint32_t pay[kWaveChunks][K];
+    bool ready[kWaveChunks];
+#pragma unroll
+    for (int c = 0; c < kWaveChunks; ++c) ready[c] = c * 64 + lane >= (int)G;
+    bool ok = true;
+    const long long t0 = wall_clock64();
+    while (true) {
+      bool all = true;
+#pragma unroll
+      for (int c = 0; c < kWaveChunks; ++c) {
+        if (!ready[c]) {
+          const unsigned long long* rw = slot + (size_t)(c * 64 + lane) * K;
+          bool rd = true;
+#pragma unroll
+          for (int k = 0; k < K; ++k) {
+            const unsigned long long v = __hip_atomic_load(rw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            pay[c][k] = (uint32_t)v;
+            rd = rd && ((v & 0xffffffff00000000ull) == seq);
+          }
+          ready[c] = rd;
+        }
+        all = all && ready[c];
+      }
+      if (__all(all)) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (wall_clock64() - t0 > st.timeout) {
+        ok = false;
+        break;
+      }
+    }
+    Rec<T> gr = rec_empty<T>();
+    if (ok) {
+#pragma unroll
+      for (int c = 0; c < kWaveChunks; ++c)
+        if (c * 64 + lane < (int)G) rec_merge(gr, RecWords<T>::make(pay[c]));
+      gr = wave_allreduce(gr);
+    }
+    Decision<T> d;
+    d.action = 0;
+    d.i = -1;
+    d.dalpha = 0;
+    if (!ok) {
+      d.action = 4;
+    } else if (updates >= st.iter_max) {
+      d.action = 3;
+    } else if (gr.minidx >= 0 && gr.minval <= (T)0 && ((int64_t)gr.count < st.s_max || gr.a_at_min != (T)0)) {
+      d.i = gr.minidx;
+      const T yi = (T)gr.ymin;
+      const T Fi = yi * gr.minval;          // y = +-1: y (y F) = F exactly
+      const T bi = yi > 0 ? st.beta : (T)1;  // b_i = beta^(0.5 (y_i + 1)), Eq. 5
+      d.dalpha = sub_rn(bi * yi, Fi);        // Eq. 6
+      d.action = 1;
+    } else if (gr.maxidx >= 0 && gr.maxval > (T)0) {
+      d.i = gr.maxidx;
+      d.dalpha = -gr.a_at_max;
+      d.action = 2;
+    }
+    if (d.action != 1 && d.action != 2) {
+      status = d.action == 0 ? 0 : (d.action == 3 ? 1 : -5);
+      break;
+    }
+    if (lane < 3 * M) pi_sh[lane] = st.P[d.i * (int64_t)M * 3 + lane];
+    if (blockIdx.x == 0 && lane == 0 && updates < st.trace_cap) {
+      st.trace_act[updates] = d.action;
+      st.trace_idx[updates] = (int32_t)d.i;
+    }
+    __syncthreads();  // one wave: orders the LDS writes of pi_sh before the reads below
+    ++updates;
+    r = rec_empty<T>();
+#pragma unroll
+    for (int k = 0; k < PT; ++k) {
+      if (jj[k] < j1) {
+        const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)M * 3 : st.P + jj[k] * (int64_t)M * 3;
+        const T kv = kfk_pair(pj, pi_sh, M, st.half_g);
+        F[k] = axpy_rn(d.dalpha, kv, F[k]);
+        if (jj[k] == d.i) a[k] = (d.action == 1) ? a[k] + d.dalpha : (T)0;  // Eq. 7 / removal
+        point_record(r, jj[k], y[k], F[k], a[k]);
+      }
+    }
+    r = wave_allreduce(r);
+    __syncthreads();  // pi_sh is rewritten in the next iteration
+  }
+#pragma unroll
+  for (int k = 0; k < PT; ++k)
+    if (jj[k] < j1) {
+      st.F[jj[k]] = F[k];
+      st.alpha[jj[k]] = a[k];
+    }
+  if (blockIdx.x == 0 && lane == 0) {
+    st.out[0] = updates;
+    st.out[1] = status;
+  }
+}
+
 __global__ void k_train_init(unsigned long long* words, int64_t nwords, unsigned* bar, int64_t* out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < nwords) words[i] = 0ull;
@@ -508,35 +690,62 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   FASTRON_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (!coop) return fail(FASTRON_EUNSUPPORTED, "device does not support cooperative launches");
-  // Workgroups: a slice per workgroup, at most one workgroup per CU, each
-  // thread holding PT points in registers (PT in {1, 2, 4, 8, 16}).
-  const int threads = (int)tune_get("train.threads");
-  int64_t G = tune_get("train.blocks");
-  if (G <= 0) G = (N + 2 * threads - 1) / (2 * threads);  // about two points per thread
-  if (G > ncu) G = ncu;
-  if (G < 1) G = 1;
-  int64_t chunk = (N + G - 1) / G;
+  // Launch shape. Default: the single-wave kernel, PT points per lane with PT
+  // the smallest power of two that keeps the grid within "train.wave_groups"
+  // workgroups (at most kWaveChunks x 64 and all co-resident). Otherwise, or
+  // with "train.kernel" = 0: the multi-wave kernel, a slice per workgroup and
+  // at most one workgroup per CU, each thread holding PT points.
+  int threads = 64;
+  int64_t G = 0, chunk = 0;
   int PT = 1;
-  while ((int64_t)PT * threads < chunk) PT *= 2;
-  if (PT > 16)
-    return fail(FASTRON_EUNSUPPORTED, "N = %lld exceeds %lld training points (16 per thread on %d CUs)",
-                (long long)N, (long long)16 * threads * ncu, ncu);
-  G = (N + chunk - 1) / chunk;
   const void* kfn = nullptr;
-  switch (PT) {
-    case 1: kfn = reinterpret_cast<const void*>(k_train<T, 1>); break;
-    case 2: kfn = reinterpret_cast<const void*>(k_train<T, 2>); break;
-    case 4: kfn = reinterpret_cast<const void*>(k_train<T, 4>); break;
-    case 8: kfn = reinterpret_cast<const void*>(k_train<T, 8>); break;
-    default: kfn = reinterpret_cast<const void*>(k_train<T, 16>); break;
-  }
-  // stage each slice's control points in LDS when they fit (48 KB budget)
-  size_t lds_bytes = (size_t)chunk * 3 * M * sizeof(float);
-  if (lds_bytes > 48 * 1024) lds_bytes = 0;
+  size_t lds_bytes = 0;
   int per_cu = 0;
-  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
-  if (per_cu < 1) return fail(FASTRON_EUNSUPPORTED, "training kernel cannot be resident with %d threads", threads);
-
+  if (tune_get("train.kernel") == 1) {
+    const int64_t cap = tune_get("train.wave_groups");
+    while (PT < 16 && (N + 64 * PT - 1) / (64 * PT) > cap) PT *= 2;
+    chunk = 64 * (int64_t)PT;
+    G = (N + chunk - 1) / chunk;
+    if (G <= kWaveChunks * 64) {
+      switch (PT) {
+        case 1: kfn = reinterpret_cast<const void*>(k_train_wave<T, 1>); break;
+        case 2: kfn = reinterpret_cast<const void*>(k_train_wave<T, 2>); break;
+        case 4: kfn = reinterpret_cast<const void*>(k_train_wave<T, 4>); break;
+        case 8: kfn = reinterpret_cast<const void*>(k_train_wave<T, 8>); break;
+        default: kfn = reinterpret_cast<const void*>(k_train_wave<T, 16>); break;
+      }
+      lds_bytes = (size_t)chunk * 3 * M * sizeof(float);
+      if (lds_bytes > 48 * 1024) lds_bytes = 0;
+      FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
+      if (per_cu < 1 || G > (int64_t)per_cu * ncu) kfn = nullptr;
+    }
+  }
+  if (kfn == nullptr) {
+    threads = (int)tune_get("train.threads");
+    G = tune_get("train.blocks");
+    if (G <= 0) G = (N + 2 * threads - 1) / (2 * threads);  // about two points per thread
+    if (G > ncu) G = ncu;
+    if (G < 1) G = 1;
+    chunk = (N + G - 1) / G;
+    PT = 1;
+    while ((int64_t)PT * threads < chunk) PT *= 2;
+    if (PT > 16)
+      return fail(FASTRON_EUNSUPPORTED, "N = %lld exceeds %lld training points (16 per thread on %d CUs)",
+                  (long long)N, (long long)16 * threads * ncu, ncu);
+    G = (N + chunk - 1) / chunk;
+    switch (PT) {
+      case 1: kfn = reinterpret_cast<const void*>(k_train<T, 1>); break;
+      case 2: kfn = reinterpret_cast<const void*>(k_train<T, 2>); break;
+      case 4: kfn = reinterpret_cast<const void*>(k_train<T, 4>); break;
+      case 8: kfn = reinterpret_cast<const void*>(k_train<T, 8>); break;
+      default: kfn = reinterpret_cast<const void*>(k_train<T, 16>); break;
+    }
+    // stage each slice's control points in LDS when they fit (48 KB budget)
+    lds_bytes = (size_t)chunk * 3 * M * sizeof(float);
+    if (lds_bytes > 48 * 1024) lds_bytes = 0;
+    FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
+    if (per_cu < 1) return fail(FASTRON_EUNSUPPORTED, "training kernel cannot be resident with %d threads", threads);
+  }
   const size_t rec_bytes = ((sizeof(unsigned long long) * 2 * (size_t)G * RecWords<T>::K + 255) / 256) * 256;
   char* ws = nullptr;
   FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), rec_bytes + 256 + 256, s));
