@@ -143,6 +143,39 @@ __device__ __forceinline__ double kfk_pair(const float* __restrict__ pj, const f
   return s / (double)M;
 }
 
+// The same K_FK with both points' coordinates in registers (MM points,
+// compile-time), evaluated in the same order as kfk_pair.
+template <int MM>
+__device__ __forceinline__ float kfk_regs(const float* pj, const float* pi, float half_g) {
+  float s = 0.f;
+#pragma unroll
+  for (int m = 0; m < MM; ++m) {
+    const float dx = pj[3 * m] - pi[3 * m], dy = pj[3 * m + 1] - pi[3 * m + 1], dz = pj[3 * m + 2] - pi[3 * m + 2];
+    const float t = 1.0f + half_g * (dx * dx + dy * dy + dz * dz);
+    const float r = __builtin_amdgcn_rcpf(t);
+    s = fmaf(r, r, s);
+  }
+  return s / (float)MM;
+}
+
+template <int MM>
+__device__ __forceinline__ double kfk_regs(const float* pj, const float* pi, double half_g) {
+#pragma clang fp contract(off)
+  double s = 0.0;
+#pragma unroll
+  for (int m = 0; m < MM; ++m) {
+    double d2 = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double diff = (double)pj[3 * m + k] - (double)pi[3 * m + k];
+      d2 += diff * diff;
+    }
+    const double t = 1.0 + half_g * d2;
+    s += 1.0 / (t * t);
+  }
+  return s / (double)MM;
+}
+
 __device__ __forceinline__ float axpy_rn(float a, float x, float y) { return y + a * x; }
 
 // ---------------------------------------------------------------------------
@@ -488,7 +521,10 @@ __device__ __forceinline__ Rec<T> wave_allreduce(const Rec<T>& r) {
 // before checking their tags.
 constexpr int kWaveChunks = 8;
 
-template <typename T, int PT>
+// MM > 0: the chain has exactly MM control points and every lane keeps its
+// points' coordinates in registers for the whole run; MM = 0: any M, the
+// coordinates come from LDS (or global memory) in each column pass.
+template <typename T, int PT, int MM>
 __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
   constexpr int K = RecWords<T>::K;
   __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
@@ -505,14 +541,22 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
 
   T y[PT], F[PT], a[PT];
   int64_t jj[PT];
+  constexpr int kReg = MM > 0 ? 3 * MM : 1;
+  float pjr[PT][kReg];
   Rec<T> r = rec_empty<T>();
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
     jj[k] = j0 + lane + (int64_t)k * 64;
+#pragma unroll
+    for (int e = 0; e < kReg; ++e) pjr[k][e] = 0.f;
     if (jj[k] < j1) {
       y[k] = (T)st.y[jj[k]];
       F[k] = st.F[jj[k]];
       a[k] = st.alpha[jj[k]];
+      if constexpr (MM > 0) {
+#pragma unroll
+        for (int e = 0; e < kReg; ++e) pjr[k][e] = st.P[jj[k] * kReg + e];
+      }
       point_record(r, jj[k], y[k], F[k], a[k]);
     } else {
       y[k] = 0;
@@ -599,11 +643,21 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
     __syncthreads();  // one wave: orders the LDS writes of pi_sh before the reads below
     ++updates;
     r = rec_empty<T>();
+    float pir[kReg];
+    if constexpr (MM > 0) {
+#pragma unroll
+      for (int e = 0; e < kReg; ++e) pir[e] = pi_sh[e];
+    }
 #pragma unroll
     for (int k = 0; k < PT; ++k) {
       if (jj[k] < j1) {
-        const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)M * 3 : st.P + jj[k] * (int64_t)M * 3;
-        const T kv = kfk_pair(pj, pi_sh, M, st.half_g);
+        T kv;
+        if constexpr (MM > 0) {
+          kv = kfk_regs<MM>(pjr[k], pir, st.half_g);
+        } else {
+          const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)M * 3 : st.P + jj[k] * (int64_t)M * 3;
+          kv = kfk_pair(pj, pi_sh, M, st.half_g);
+        }
         F[k] = axpy_rn(d.dalpha, kv, F[k]);
         if (jj[k] == d.i) a[k] = (d.action == 1) ? a[k] + d.dalpha : (T)0;  // Eq. 7 / removal
         point_record(r, jj[k], y[k], F[k], a[k]);
@@ -667,6 +721,24 @@ __global__ void __launch_bounds__(1024) k_compact(const T* __restrict__ alpha, i
   if (threadIdx.x == 0) *count = base;
 }
 
+template <typename T, int MM>
+static const void* wave_kernel_mm(int PT) {
+  switch (PT) {
+    case 1: return reinterpret_cast<const void*>(k_train_wave<T, 1, MM>);
+    case 2: return reinterpret_cast<const void*>(k_train_wave<T, 2, MM>);
+    case 4: return reinterpret_cast<const void*>(k_train_wave<T, 4, MM>);
+    case 8: return reinterpret_cast<const void*>(k_train_wave<T, 8, MM>);
+    default: return reinterpret_cast<const void*>(k_train_wave<T, 16, MM>);
+  }
+}
+
+template <typename T>
+static const void* wave_kernel(int PT, int mm) {
+  if (mm == 4) return wave_kernel_mm<T, 4>(PT);
+  if (mm == 8) return wave_kernel_mm<T, 8>(PT);
+  return wave_kernel_mm<T, 0>(PT);
+}
+
 template <typename T>
 static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int32_t M, T gamma, T beta,
                                  int64_t iter_max, int64_t s_max, T* alpha, T* F, int32_t* support_idx,
@@ -707,14 +779,11 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     chunk = 64 * (int64_t)PT;
     G = (N + chunk - 1) / chunk;
     if (G <= kWaveChunks * 64) {
-      switch (PT) {
-        case 1: kfn = reinterpret_cast<const void*>(k_train_wave<T, 1>); break;
-        case 2: kfn = reinterpret_cast<const void*>(k_train_wave<T, 2>); break;
-        case 4: kfn = reinterpret_cast<const void*>(k_train_wave<T, 4>); break;
-        case 8: kfn = reinterpret_cast<const void*>(k_train_wave<T, 8>); break;
-        default: kfn = reinterpret_cast<const void*>(k_train_wave<T, 16>); break;
-      }
-      lds_bytes = (size_t)chunk * 3 * M * sizeof(float);
+      // chains with 4 or 8 control points keep each lane's coordinates in
+      // registers (up to 4 points per lane)
+      const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
+      kfn = wave_kernel<T>(PT, mm);
+      lds_bytes = mm ? 0 : (size_t)chunk * 3 * M * sizeof(float);
       if (lds_bytes > 48 * 1024) lds_bytes = 0;
       FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
       if (per_cu < 1 || G > (int64_t)per_cu * ncu) kfn = nullptr;
