@@ -106,7 +106,7 @@ def test_batch_autotune_and_graph_replay(dev):
     b.close()
 
 
-def test_batch_full_scale(dev):
+def test_batch_full_scale(oracle_mod, dev):
     """256 environments, lognormal support sets over [200, 8000], 1,000-100,000 queries each."""
     arm = wl.arm_7dof()
     gamma = 10.0
@@ -123,4 +123,15 @@ def test_batch_full_scale(dev):
         assert torch.equal(f[qo[e]:qo[e + 1]], fr), e
         assert torch.equal(lab[qo[e]:qo[e + 1]], lr), e
     assert torch.isfinite(f).all()
+    # the oracle on a sample of the largest and the smallest environment
+    dh = oracle_dh(oracle_mod, arm)
+    fn, ln = f.cpu().numpy(), lab.cpu().numpy()
+    for e in pick[1:3]:
+        s64 = sq[so[e]:so[e + 1]].astype(np.float64)
+        idx = np.arange(qo[e], qo[e + 1])[::max(1, int(envs.query_counts[e]) // 200)]
+        r = oracle_mod.score(dh, arm.frames, s64, al[so[e]:so[e + 1]].astype(np.float64), gamma,
+                             q[idx].astype(np.float64))
+        tol = error_bound(oracle_mod.control_points(dh, arm.frames, s64), al[so[e]:so[e + 1]], gamma,
+                          oracle_mod.control_points(dh, arm.frames, q[idx].astype(np.float64)))
+        check_scores(fn[idx], ln[idx], r, tol, min_agree=0.99)
     b.close()

@@ -209,3 +209,38 @@ def test_train_epoch_rejects_bad_order(dev):
         net.train_epoch(P, y, order, batch=128)
     assert ei.value.status == _native.FASTRON_EINVAL
     net.close()
+
+
+def test_screen_full_size_sampled(oracle_mod, dev):
+    """The screening form's launch at full size (4,194,304 queries through the fused kernel, tau = 1 so that
+    a fallback list forms): sampled logits against the FP64 oracle forward pass, labels of confident queries
+    = sign(logit), labels of fallback queries = the Fastron label, fallback count = |logit| < tau."""
+    arm = wl.arm_7dof()
+    dh = oracle_dh(oracle_mod, arm)
+    N = 4_194_304
+    q = wl.configs("bench7/screen_q", N, arm.n)
+    q_d = torch.from_numpy(q).to(dev)
+    params = wl.mlp_init(24, 256, name="screen_full_init")
+    net = api.MLP(24, 256, max_rows=8192)
+    net.set_params(torch.from_numpy(params).to(dev))
+    net.fit_standardisation(api.fk_points(arm, q_d[:65536].contiguous()))
+    sq, al = wl.model("screen_full_model", 500, 7)
+    model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), 10.0)
+    announce("screen full size N=4194304 tau=1")
+    lab, z, fb, nf = net.screen(arm, model, q_d, 1.0)
+    zc = z.cpu().numpy()
+    fbc = fb.cpu().numpy().astype(bool)
+    assert nf == int(fbc.sum()) and np.array_equal(fbc, np.abs(zc) < 1.0)
+    labc = lab.cpu().numpy()
+    assert np.array_equal(labc[~fbc], np.where(zc[~fbc] >= 0, 1, -1).astype(np.int8))
+    _, plain = api.fk_score_prepared(arm, model, q_d, want_f=False)
+    assert np.array_equal(labc[fbc], plain.cpu().numpy()[fbc])
+    idx = np.unique(np.concatenate([wl.rng("screen_full/sample").choice(N, 2000, replace=False), [0, N - 1]]))
+    _, _, mu, sd = net.get_params(dev)
+    ps = [p_.astype(np.float64) for p_ in wl.split_mlp_params(params, 24)]
+    X = oracle_mod.control_points(dh, arm.frames, q[idx].astype(np.float64)).reshape(idx.size, 24)
+    z_ref, _ = mo.forward(ps, X, mu.cpu().numpy().astype(np.float64), sd.cpu().numpy().astype(np.float64))
+    rel = np.linalg.norm(zc[idx] - z_ref) / np.linalg.norm(z_ref)
+    print(dict(fallback=nf / N, rel_vs_oracle=float(rel)))
+    assert rel < 2e-2
+    net.close()

@@ -241,3 +241,33 @@ def test_score_duplicate_supports_and_wide_gamma(oracle_mod, dev):
         tol = error_bound(Ps, al2, gamma, Pq)
         check_scores(f2.cpu().numpy(), l2.cpu().numpy(), ref, tol, min_agree=0.99)
         assert np.all(np.abs(f1.cpu().numpy() - f2.cpu().numpy()) <= 2 * tol)
+
+
+def test_precision_form_full_size_sampled(oracle_mod, dev):
+    """The precision form's workload in one launch per form: 7-DOF arm, S = 16,384, N = 4,194,304. FP32 and
+    BF16 split3 must meet the FP32 bound on sampled queries; plain and split2 are held to sign agreement."""
+    arm = wl.arm_7dof()
+    gamma, S, N = 10.0, 16_384, 4_194_304
+    sq, al = wl.model("prec7", S, arm.n)
+    q = wl.configs("prec7/q", N, arm.n)
+    model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma)
+    q_d = torch.from_numpy(q).to(dev)
+    idx = np.unique(np.concatenate([wl.rng("prec7/sample").choice(N, 1000, replace=False), [0, N - 1]]))
+    dh = oracle_dh(oracle_mod, arm)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q[idx].astype(np.float64))
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, arm.frames, q[idx].astype(np.float64))
+    tol = error_bound(Ps, al, gamma, Pq)
+    for name, flags in (("fp32", api.SCORE_FP32), ("split3", api.SCORE_BF16 | api.BF16_SPLIT3),
+                        ("split2", api.SCORE_BF16 | api.BF16_SPLIT2), ("plain", api.SCORE_BF16 | api.BF16_PLAIN)):
+        announce(f"precision form full size {name}")
+        f, lab = api.fk_score_prepared(arm, model, q_d, flags=flags)
+        fs, ls = f.cpu().numpy()[idx], lab.cpu().numpy()[idx]
+        assert bool(torch.isfinite(f).all())
+        if name in ("fp32", "split3"):
+            print(name, check_scores(fs, ls, ref, tol))
+        else:
+            agree = float(np.mean(ls == _sign(ref)))
+            print(name, dict(max_abs_df=float(np.abs(fs - ref).max()), sign_agreement=agree))
+            assert agree >= (0.9999 if name == "split2" else 0.995)
+        del f, lab

@@ -170,3 +170,32 @@ def test_three_dof_end_to_end(oracle_mod, dev):
     print({"support": int(sup.size), **stats, "gpu": m_gpu, "oracle": m_ref})
     assert abs(m_gpu["accuracy"] - m_ref["accuracy"]) * yq.size <= stats["ambiguous"]
     assert m_gpu["accuracy"] >= 0.95
+
+
+def test_train_full_size_claim2(oracle_mod, dev):
+    """The benchmark's training run at full size: 50,000 labelled 7-DOF configurations (20 cubes), gamma = 30.
+    The model must converge, its F must agree with F = K alpha recomputed in FP64 by the oracle, and that FP64
+    F must give a positive margin to (nearly) every training point (Claim 2)."""
+    arm = wl.arm_7dof()
+    dh = oracle_dh(oracle_mod, arm)
+    q = wl.configs("bench7/train", 50_000, arm.n)
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+    y = y.astype(np.int8)
+    P32 = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
+    announce("train fp32 7dof N=50000 gamma=30")
+    out = api.train(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 30.0)
+    assert out["converged"]
+    alpha = out["alpha"].cpu().numpy()
+    sup = out["support"].cpu().numpy()
+    np.testing.assert_array_equal(sup, np.flatnonzero(alpha))
+    assert np.all(y[sup] * alpha[sup] > 0)
+    P64 = P32.astype(np.float64)
+    F_oracle = oracle_mod.score_points(P64[sup], alpha[sup].astype(np.float64), 30.0, P64)
+    F_gpu = out["F"].cpu().numpy()
+    margins = y * F_oracle
+    print(dict(support=int(sup.size), updates=out["updates"], max_dF=float(np.abs(F_gpu - F_oracle).max()),
+               frac_positive=float(np.mean(margins > 0)), min_margin=float(margins.min())))
+    assert np.all(y * F_gpu > 0)
+    assert np.abs(F_gpu - F_oracle).max() < 1e-2
+    assert np.mean(margins > 0) >= 0.999
