@@ -78,8 +78,8 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
-    ap.add_argument("--legs", default="kernels,forms,precision,train,batched,retrain,screen",
-                    help="comma-separated extra legs (kernels, forms, precision, train, batched, retrain, screen)")
+    ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,batched,retrain,screen",
+                    help="comma-separated extra legs (kernels, forms, precision, dof3, train, batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=6, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -157,8 +157,9 @@ def main():
     f_np = f_gpu.cpu().numpy()
 
     extras = {}
+    checks = []  # GPU results queued for the FP64 comparison of the CPU leg
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"kernels", "forms", "precision", "train", "batched", "retrain", "screen"}
+    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "batched", "retrain", "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -176,13 +177,16 @@ def main():
         extras["forms"] = forms
     if "precision" in legs:
         log("[bench] precision form: S=16,384, N=4,194,304")
-        extras["precision"] = precision_run(api, wl, arm, gamma, dev, fp64_sample=0 if args.no_cpu_baseline else 262_144)
+        extras["precision"] = precision_run(api, wl, arm, gamma, dev, checks)
+    if "dof3" in legs:
+        log("[bench] 3-DOF workload: FP64 training on 2,000 labelled samples, scoring")
+        extras["dof3"] = dof3_run(api, wl, dev, checks)
     if "train" in legs:
         log("[bench] training run on 50,000 labelled samples")
         extras["train"] = train_run(api, wl, arm, dev)
     if "batched" in legs:
         log("[bench] batched form: 256 environments")
-        extras["batched"] = batched_run(api, wl, arm, gamma, dev)
+        extras["batched"] = batched_run(api, wl, arm, gamma, dev, checks)
     if "retrain" in legs:
         log("[bench] re-training 16 environments after their cubes move")
         extras["retrain16"] = retrain_run(api, wl, arm, dev)
@@ -193,7 +197,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (FP64 oracle)")
-        cpu, agree = cpu_baseline(arm, sq_np, al_np, q_np, gamma, f_np, lab_gpu, args.cpu_seconds, extras)
+        cpu, agree = cpu_baseline(arm, sq_np, al_np, q_np, gamma, f_np, lab_gpu, args.cpu_seconds, extras, checks)
     else:
         agree = {}
 
@@ -231,18 +235,24 @@ def main():
 GAMMA_TRAIN_7DOF = 30.0
 
 
-def _event_ms(fn, reps):
+def _event_ms(fn, reps, rounds=3):
+    """Milliseconds per call of fn from HIP events on the current stream: three warm-up calls, then the
+    median over `rounds` rounds of `reps` back-to-back calls."""
     import torch
 
-    fn()
-    stream = torch.cuda.current_stream()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
+    for _ in range(3):
         fn()
-    e1.record(stream)
-    e1.synchronize()
-    return e0.elapsed_time(e1) / reps
+    stream = torch.cuda.current_stream()
+    per = []
+    for _ in range(rounds):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        per.append(e0.elapsed_time(e1) / reps)
+    return float(np.median(per))
 
 
 def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
@@ -270,59 +280,82 @@ def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
                                   "segment_box_tests_per_s": N * arm.n * 20 / (t_lab * 1e-3)}}
 
 
-def precision_run(api, wl, arm, gamma, dev, S=16_384, N=4_194_304, fp64_sample=262_144, reps=5):
+def precision_run(api, wl, arm, gamma, dev, checks, S=16_384, N=4_194_304, fp64_sample=262_144, reps=5):
     """FP32 score versus the BF16 cross-term forms on S = 16,384 supports and N = 4,194,304 queries: kernel time
-    of each form, max |df| and sign agreement against the FP32 path (all queries) and against the FP64 oracle
-    (an evenly spaced sample of fp64_sample queries; the queries whose |f_fp64| is below a form's max |df| are
-    counted as inherently ambiguous for that form)."""
+    of each form, max |df| and sign agreement against the FP32 path (all queries); an evenly spaced sample of
+    fp64_sample queries of every form is queued for the FP64 comparison of the CPU leg."""
     import torch
 
     sq_np, al_np = wl.model("prec7", S, arm.n)
     q_np = wl.configs("prec7/q", N, arm.n)
     sq, al, q = (torch.from_numpy(x).to(dev) for x in (sq_np, al_np, q_np))
     model = api.support_prep(arm, sq, al, gamma)
-    stream = torch.cuda.current_stream()
     forms = {"fp32": api.SCORE_FP32, "bf16_plain": api.SCORE_BF16 | api.BF16_PLAIN,
              "bf16_split2": api.SCORE_BF16 | api.BF16_SPLIT2, "bf16_split3": api.SCORE_BF16 | api.BF16_SPLIT3}
     res, outs = {}, {}
     for name, flags in forms.items():
         f = torch.empty(N, dtype=torch.float32, device=dev)
         lab = torch.empty(N, dtype=torch.int8, device=dev)
-        api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        for _ in range(reps):
-            api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
-        e1.record(stream)
-        e1.synchronize()
-        t = e0.elapsed_time(e1) / reps
+        t = _event_ms(lambda: api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab)), reps)
         outs[name] = (f, lab)
         res[name] = {"kernel_ms": t, "checks_per_s": N / (t * 1e-3),
                      "cp_evals_per_s": N * S * int(np.sum(arm.frames > 0)) / (t * 1e-3)}
     f32, l32 = outs["fp32"]
+    idx = np.linspace(0, N - 1, fp64_sample).astype(np.int64)
     for name, (f, lab) in outs.items():
         res[name]["vs_fp32"] = {"max_abs_df": float((f - f32).abs().max()),
                                 "sign_agreement": float((lab == l32).float().mean())}
         res[name]["speed_vs_fp32"] = res["fp32"]["kernel_ms"] / res[name]["kernel_ms"]
-    out = {"S": S, "N": N, "forms": res}
-    if fp64_sample:
-        import oracle
+        checks.append({"arm": arm, "sq": sq_np, "al": al_np, "gamma": gamma, "q": q_np[idx],
+                       "f": f.cpu().numpy()[idx], "lab": lab.cpu().numpy()[idx], "into": res[name]})
+    return {"S": S, "N": N, "fp64_sample": fp64_sample, "forms": res}
 
-        dh = oracle.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
-        idx = np.linspace(0, N - 1, fp64_sample).astype(np.int64)
-        t0 = time.perf_counter()
-        ref = oracle.score(dh, arm.frames, sq_np.astype(np.float64), al_np.astype(np.float64), gamma,
-                           q_np[idx].astype(np.float64))
-        sign_ref = np.where(ref < 0, -1, 1)
-        out["fp64_sample"] = int(fp64_sample)
-        out["fp64_seconds"] = time.perf_counter() - t0
-        for name, (f, lab) in outs.items():
-            fs = f.cpu().numpy()[idx].astype(np.float64)
-            ls = lab.cpu().numpy()[idx]
-            df = float(np.max(np.abs(fs - ref)))
-            res[name]["vs_fp64"] = {"max_abs_df": df, "sign_agreement": float(np.mean(ls == sign_ref)),
-                                    "ambiguous": int(np.sum(np.abs(ref) < df))}
-    return out
+
+def dof3_run(api, wl, dev, checks, reps=20):
+    """The 3-DOF workload: 2,000 configurations labelled against 5 cubes of side 0.15 (the first seed whose labels
+    are 10-90 % in collision), Algorithm 1 in FP64 on the device (gamma = 10), then the model scores 10,000 fresh
+    queries (accuracy / TPR / TNR against their geometric labels) and, for throughput, 1,000,000 queries."""
+    import torch
+
+    arm = wl.arm_3dof()
+    for seed in range(wl.MASTER_SEED, wl.MASTER_SEED + 200):
+        q = torch.from_numpy(wl.configs("train3", 2000, arm.n, seed=seed)).to(dev)
+        lo, hi = wl.cubes("train3/cubes", 5, 0.15, None, seed=seed)
+        y, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
+        frac = float((y == 1).float().mean())
+        if 0.1 <= frac <= 0.9:
+            break
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = api.train(api.fk_points(arm, q), y, 10.0, fp64=True)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sup = out["support"].long()
+    al = out["alpha"][sup].float().contiguous()
+    model = api.support_prep(arm, q[sup].contiguous(), al, 10.0)
+    qq = torch.from_numpy(wl.configs("train3/queries", 10_000, arm.n, seed=seed)).to(dev)
+    yq, _ = api.label_capsule_box(arm, qq, arm.radius, lo, hi, want_clearance=False)
+    f = torch.empty(10_000, dtype=torch.float32, device=dev)
+    lab = torch.empty(10_000, dtype=torch.int8, device=dev)
+    t_q = _event_ms(lambda: api.fk_score_prepared(arm, model, qq, out=(f, lab)), reps)
+    tp = int(((lab == 1) & (yq == 1)).sum()); tn = int(((lab == -1) & (yq == -1)).sum())
+    pos = int((yq == 1).sum()); neg = int((yq == -1).sum())
+    N = 1_000_000
+    qb = torch.from_numpy(wl.configs("dof3/q", N, arm.n)).to(dev)
+    fb = torch.empty(N, dtype=torch.float32, device=dev)
+    lb = torch.empty(N, dtype=torch.int8, device=dev)
+    t_b = _event_ms(lambda: api.fk_score_prepared(arm, model, qb, out=(fb, lb)), reps)
+    S = int(sup.numel())
+    Mm = int(np.sum(arm.frames > 0))
+    res = {"seed": seed, "train_collision_rate": frac, "train_ms_fp64": t_train * 1e3, "updates": out["updates"],
+           "support": S, "converged": bool(out["converged"]),
+           "queries_10k": {"ms": t_q, "accuracy": (tp + tn) / 10_000, "tpr": tp / max(pos, 1), "tnr": tn / max(neg, 1)},
+           "throughput_1M": {"ms": t_b, "checks_per_s": N / (t_b * 1e-3), "kernel_evals_per_s": N * S / (t_b * 1e-3),
+                             "cp_evals_per_s": N * S * Mm / (t_b * 1e-3),
+                             "frac_alu": N * S * Mm / (t_b * 1e-3) / ALU_PEAK_CP_PER_S}}
+    checks.append({"arm": arm, "sq": q[sup].cpu().numpy(), "al": al.cpu().numpy(), "gamma": 10.0,
+                   "q": qq.cpu().numpy(), "f": f.cpu().numpy(), "lab": lab.cpu().numpy(), "into": res["queries_10k"]})
+    return res
 
 
 def train_run(api, wl, arm, dev):
@@ -347,7 +380,7 @@ def train_run(api, wl, arm, dev):
             "collision_rate": float((y == 1).float().mean().item())}
 
 
-def batched_run(api, wl, arm, gamma, dev, reps=5):
+def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
     """256 environments with lognormal support sets and uniform query batches: one persistent graph-replayed
     launch versus one plain launch per environment."""
     import torch
@@ -394,11 +427,21 @@ def batched_run(api, wl, arm, gamma, dev, reps=5):
     ms_plain = e0.elapsed_time(e1) / reps
     same = bool(torch.equal(f, fp) and torch.equal(lab, lp))
     kevals = float(np.sum(envs.support_counts.astype(np.float64) * envs.query_counts))
+    Mm = int(np.sum(arm.frames > 0))
+    res = {"E": envs.E, "queries": N_tot, "supports": S_tot, "tile_queries": tq, "ms_graph_replay": ms_batch,
+           "checks_per_s": N_tot / (ms_batch * 1e-3), "kernel_evals_per_s": kevals / (ms_batch * 1e-3),
+           "frac_alu": kevals * Mm / (ms_batch * 1e-3) / ALU_PEAK_CP_PER_S,
+           "ms_plain_per_env_launches": ms_plain, "speedup_vs_plain": ms_plain / ms_batch,
+           "identical_to_plain": same, "fp64_sample": {}}
+    # FP64 comparison (CPU leg) on 2,000 evenly spaced queries of the largest and of the smallest environment
+    for tag, e in (("largest_S", int(np.argmax(envs.support_counts))), ("smallest_S", int(np.argmin(envs.support_counts)))):
+        idx = np.linspace(qo[e], qo[e + 1] - 1, 2000).astype(np.int64)
+        res["fp64_sample"][tag] = {"env": e, "S": int(envs.support_counts[e])}
+        checks.append({"arm": arm, "sq": sq[so[e]:so[e + 1]].cpu().numpy(), "al": al[so[e]:so[e + 1]].cpu().numpy(),
+                       "gamma": gamma, "q": q[idx].cpu().numpy(), "f": f.cpu().numpy()[idx],
+                       "lab": lab.cpu().numpy()[idx], "into": res["fp64_sample"][tag]})
     b.close()
-    return {"E": envs.E, "queries": N_tot, "supports": S_tot, "tile_queries": tq, "ms_graph_replay": ms_batch,
-            "checks_per_s": N_tot / (ms_batch * 1e-3), "kernel_evals_per_s": kevals / (ms_batch * 1e-3),
-            "ms_plain_per_env_launches": ms_plain, "speedup_vs_plain": ms_plain / ms_batch,
-            "identical_to_plain": same}
+    return res
 
 
 def retrain_run(api, wl, arm, dev, n_env=16, N=20_000):
@@ -495,9 +538,21 @@ def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304
             "plain": {"checks_per_s": n_query / t_plain, "accuracy": acc_plain}, "screened": rows}
 
 
-def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras):
-    """FP64 oracle on a bounded, evenly spaced sample of the queries (all host threads)."""
+def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras, checks):
+    """FP64 oracle on a bounded, evenly spaced sample of the queries (all host threads); also the FP64
+    comparisons queued by the other legs (max |df|, sign agreement, queries inherently ambiguous at that
+    error: |f_fp64| < max |df|)."""
     import oracle
+
+    for c in checks:
+        a = c["arm"]
+        dh_c = oracle.dh_table(a.a, a.alpha, a.d, a.theta, a.joint_type)
+        ref = oracle.score(dh_c, a.frames, c["sq"].astype(np.float64), c["al"].astype(np.float64), c["gamma"],
+                           c["q"].astype(np.float64), offset=a.offsets)
+        df = float(np.max(np.abs(c["f"].astype(np.float64) - ref)))
+        c["into"]["vs_fp64"] = {"queries": int(ref.size), "max_abs_df": df,
+                                "sign_agreement": float(np.mean(c["lab"] == np.where(ref < 0, -1, 1))),
+                                "ambiguous": int(np.sum(np.abs(ref) < df))}
 
     dh = oracle.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
     sq64, al64 = sq.astype(np.float64), al.astype(np.float64)
@@ -517,8 +572,30 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras):
     for name, form in extras.get("forms", {}).items():
         form["sign_agreement_vs_fp64"] = float(np.mean(form["labels"][idx] == sign_ref))
     cpu = {"value": n / dt, "unit": "checks/s", "cores": oracle.num_threads(), "kind": "oracle",
-           "sample": f"{n} evenly spaced queries of the same workload (S={sq.shape[0]}), {dt:.1f} s"}
+           "sample": f"{n} evenly spaced queries of the same workload (S={sq.shape[0]}), {dt:.1f} s",
+           "logical_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+    # one thread on a 10,000-query subset (the paper's thread count is not stated)
+    threads = oracle.num_threads()
+    oracle.set_num_threads(1)
+    sub = np.linspace(0, q.shape[0] - 1, 10_000).astype(np.int64)
+    t0 = time.perf_counter()
+    oracle.score(dh, arm.frames, sq64, al64, gamma, q[sub].astype(np.float64))
+    dt1 = time.perf_counter() - t0
+    oracle.set_num_threads(threads)
+    cpu["single_thread"] = {"value": sub.size / dt1, "unit": "checks/s", "us_per_check": dt1 * 1e6 / sub.size,
+                            "sample": "10,000 evenly spaced queries"}
     return cpu, agree
+
+
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
 
 
 if __name__ == "__main__":

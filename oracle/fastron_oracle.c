@@ -423,3 +423,12 @@ int oracle_num_threads(void) {
   return 1;
 #endif
 }
+
+/* Sets the thread count of later OpenMP loops (no effect without OpenMP). */
+void oracle_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
