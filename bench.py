@@ -81,7 +81,7 @@ def main():
     ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,batched,retrain,screen",
                     help="comma-separated extra legs (kernels, forms, precision, dof3, train, batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
-    ap.add_argument("--mlp-epochs", type=int, default=6, help="epochs of the screening network in the extras")
+    ap.add_argument("--mlp-epochs", type=int, default=10, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()

@@ -68,6 +68,8 @@ struct GemmArgs {
   float* partial;    // [ceil(N / 64)][M] when head is set
   int relu;
   int M, N, K;
+  int kchunk;        // K range per blockIdx.z (a multiple of the K chunk)
+  float* split;      // split-K: raw partial products [gridDim.z][M][N], no epilogue
 };
 
 constexpr int kGT = 64;   // output tile edge
@@ -80,17 +82,19 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
   __shared__ float hsum[4][kGT];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.x * kGT, n0 = (int64_t)blockIdx.y * kGT;
+  const int64_t kb = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t ke = kb + g.kchunk < g.K ? kb + g.kchunk : g.K;
   f4m acc[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) acc[t] = (f4m){0.f, 0.f, 0.f, 0.f};
-  for (int64_t k0 = 0; k0 < g.K; k0 += kGK) {
+  for (int64_t k0 = kb; k0 < ke; k0 += kGK) {
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
       const int e = tid * 8 + i;  // 2048 elements per operand chunk
       const int r = e / kGK, kk = e % kGK;
       const int64_t gm = m0 + r, gk = k0 + kk, gn = n0 + r;
-      As[r][kk] = (gm < g.M && gk < g.K) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
-      Bs[r][kk] = (gn < g.N && gk < g.K) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
+      As[r][kk] = (gm < g.M && gk < ke) ? g.A[gm * g.sam + gk * g.sak] : (uint16_t)0;
+      Bs[r][kk] = (gn < g.N && gk < ke) ? g.B[gk * g.sbk + gn * g.sbn] : (uint16_t)0;
     }
     __syncthreads();
     const int row = 16 * wave + (lane & 15), kq = 8 * (lane >> 4);
@@ -103,6 +107,19 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
     __syncthreads();
   }
   // epilogue: lane holds rows 16 wave + 4 (lane / 16) + r, column 16 t + lane % 16
+  if (g.split) {
+    float* out = g.split + (int64_t)blockIdx.z * g.M * g.N;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      const int64_t n = n0 + 16 * t + (lane & 15);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t m = m0 + 16 * wave + 4 * (lane >> 4) + r;
+        if (m < g.M && n < g.N) out[m * g.N + n] = acc[t][r];
+      }
+    }
+    return;
+  }
   float hpart[4] = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
@@ -138,6 +155,24 @@ __global__ void __launch_bounds__(256) k_gemm_bf16(GemmArgs g) {
       if (m < g.M) g.partial[(int64_t)blockIdx.y * g.M + m] = hsum[w][rr];
     }
   }
+}
+
+// Split-K: sums the partial products in split order (deterministic) and
+// applies the epilogue (bias, ReLU, FP32 / BF16 output).
+__global__ void __launch_bounds__(256) k_splitk_reduce(const float* __restrict__ split, int splits, int M, int N,
+                                                        const float* __restrict__ bias, int relu,
+                                                        float* __restrict__ C, int64_t ldc, uint16_t* __restrict__ Cb,
+                                                        int64_t ldcb) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t MN = (int64_t)M * N;
+  if (e >= MN) return;
+  const int64_t m = e / N, n = e % N;
+  float v = 0.f;
+  for (int z = 0; z < splits; ++z) v += split[z * MN + e];
+  if (bias) v += bias[n];
+  if (relu) v = fmaxf(v, 0.f);
+  if (C) C[m * ldc + n] = v;
+  if (Cb) Cb[m * ldcb + n] = to_bf16(v);
 }
 
 // ---------------------------------------------------------------------------
@@ -590,6 +625,7 @@ struct fastron_mlp {
   uint16_t* w1p = nullptr;  // fused-inference operand order (H == 256, d_in <= 24 only)
   uint16_t* w2p = nullptr;
   float* isd = nullptr;     // 1 / sd for the fused pass
+  float* splitbuf = nullptr;  // split-K partial products of the weight-gradient GEMMs
   int64_t step = 0;
   // activations for a batch of cap_rows
   uint16_t* Xb = nullptr;
@@ -624,18 +660,45 @@ void free_mlp(fastron_mlp* n) {
   if (!n) return;
   void* ps[] = {n->params, n->grads, n->adam_m, n->adam_v, n->mu, n->sd, n->w1b, n->w2b, n->Xb, n->Z1, n->H1b,
                 n->Z2, n->partial, n->z, n->dz, n->dZ2, n->dZ2b, n->dH1, n->dZ1, n->dZ1b, n->colpart, n->loss_part,
-                n->hbuf, n->bad, n->w1p, n->w2p, n->isd};
+                n->hbuf, n->bad, n->w1p, n->w2p, n->isd, n->splitbuf};
   for (void* p : ps) (void)hipFree(p);
   delete n;
 }
 
+constexpr int64_t kSplitFloats = 4 << 20;  // split-K workspace (16 MB)
+
+// C = act(A B + bias). Output grids too small to fill the device (the weight
+// gradients: a few 64 x 64 tiles, K = batch rows) split K across blockIdx.z
+// into `split` (kSplitFloats floats) and reduce in a second kernel.
 fastron_status gemm(hipStream_t s, const uint16_t* A, int64_t sam, int64_t sak, const uint16_t* B, int64_t sbk,
                     int64_t sbn, int M, int N, int K, float* C, int64_t ldc, uint16_t* Cb, int64_t ldcb,
-                    const float* bias, int relu, const float* head = nullptr, float* partial = nullptr) {
-  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, Cb, ldcb, bias, head, partial, relu, M, N, K};
-  dim3 grid((unsigned)((M + kGT - 1) / kGT), (unsigned)((N + kGT - 1) / kGT));
+                    const float* bias, int relu, const float* head = nullptr, float* partial = nullptr,
+                    float* split = nullptr) {
+  const int64_t tiles = (int64_t)((M + kGT - 1) / kGT) * ((N + kGT - 1) / kGT);
+  int64_t splits = 1;
+  if (split && !head && tiles < 128 && K >= 4 * 128) {
+    splits = (512 + tiles - 1) / tiles;
+    const int64_t by_k = K / 128;  // at least 128 rows of K per split
+    const int64_t by_mem = kSplitFloats / ((int64_t)M * N);
+    if (splits > by_k) splits = by_k;
+    if (splits > by_mem) splits = by_mem;
+    if (splits < 1) splits = 1;
+  }
+  int64_t kchunk = (K + splits - 1) / splits;
+  kchunk = (kchunk + kGK - 1) / kGK * kGK;
+  if (kchunk < kGK) kchunk = kGK;
+  splits = (K + kchunk - 1) / kchunk;
+  if (splits < 1) splits = 1;
+  GemmArgs g{A, sam, sak, B, sbk, sbn, C, ldc, Cb, ldcb, bias, head, partial, relu, M, N, K, (int)kchunk,
+             splits > 1 ? split : nullptr};
+  dim3 grid((unsigned)((M + kGT - 1) / kGT), (unsigned)((N + kGT - 1) / kGT), (unsigned)splits);
   hipLaunchKernelGGL(k_gemm_bf16, grid, dim3(256), 0, s, g);
   FASTRON_HIP(hipGetLastError());
+  if (splits > 1) {
+    hipLaunchKernelGGL(k_splitk_reduce, dim3((unsigned)(((int64_t)M * N + 255) / 256)), dim3(256), 0, s, split,
+                       (int)splits, M, N, bias, relu, C, ldc, Cb, ldcb);
+    FASTRON_HIP(hipGetLastError());
+  }
   return FASTRON_OK;
 }
 
@@ -693,13 +756,15 @@ fastron_status backward(fastron_mlp* n, int64_t rows, const int8_t* y, const int
   hipLaunchKernelGGL(k_head_back, dim3(nblk(rows * H)), dim3(256), 0, s, n->dz, n->w3(), n->Z2, rows, H, n->dZ2,
                      n->dZ2b);
   FASTRON_HIP(hipGetLastError());
-  TRY(gemm(s, n->H1b, 1, H, n->dZ2b, H, 1, H, H, (int)rows, gw2, H, nullptr, 0, nullptr, 0));
+  TRY(gemm(s, n->H1b, 1, H, n->dZ2b, H, 1, H, H, (int)rows, gw2, H, nullptr, 0, nullptr, 0, nullptr, nullptr,
+           n->splitbuf));
   TRY(colsum(s, n, n->dZ2, rows, H, H, nullptr, gb2));
   // layer 1: dH1 = dZ2 W2^T; dZ1 = dH1 [Z1 > 0]; gW1 = X^T dZ1; gb1 = sum dZ1
   TRY(gemm(s, n->dZ2b, H, 1, n->w2b, 1, H, (int)rows, H, H, n->dH1, H, nullptr, 0, nullptr, 0));
   hipLaunchKernelGGL(k_relu_back, dim3(nblk(rows * H)), dim3(256), 0, s, n->dH1, n->Z1, rows * H, n->dZ1, n->dZ1b);
   FASTRON_HIP(hipGetLastError());
-  TRY(gemm(s, n->Xb, 1, n->kin_pad, n->dZ1b, H, 1, n->d_in, H, (int)rows, gw1, H, nullptr, 0, nullptr, 0));
+  TRY(gemm(s, n->Xb, 1, n->kin_pad, n->dZ1b, H, 1, n->d_in, H, (int)rows, gw1, H, nullptr, 0, nullptr, 0, nullptr,
+           nullptr, n->splitbuf));
   TRY(colsum(s, n, n->dZ1, rows, H, H, nullptr, gb1));
   return FASTRON_OK;
 }
@@ -812,6 +877,7 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
   alloc(&n->loss_part, (R + 255) / 256, 4);
   alloc(&n->hbuf, R * H, 4);
   alloc(&n->bad, 1, 4);
+  alloc(&n->splitbuf, kSplitFloats, 4);
   if (hidden == kInfH && d_in <= kInfXRow) {
     alloc(&n->w1p, 16 * 64 * 8, 2);
     alloc(&n->w2p, (int64_t)kInfH * kInfH, 2);
