@@ -584,7 +584,56 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras, checks)
     oracle.set_num_threads(threads)
     cpu["single_thread"] = {"value": sub.size / dt1, "unit": "checks/s", "us_per_check": dt1 * 1e6 / sub.size,
                             "sample": "10,000 evenly spaced queries"}
+    cpu["rows"] = cpu_rows(oracle, arm, dh, extras)
     return cpu, agree
+
+
+def cpu_rows(oracle, arm, dh, extras):
+    """The oracle timed on the other steps of the path, each beside the GPU figure of the same step when the
+    corresponding leg ran: FK (a1), Gram column (a4), Algorithm 1 (a5, 3-DOF workload), labels (a9) and the
+    screening network's forward pass (a8)."""
+    from oracle import mlp_oracle
+    from paper_1910_06451_amd import workloads as wl
+
+    rows = {}
+    kern = extras.get("kernels", {})
+
+    def timed(fn):
+        t0 = time.perf_counter()
+        out = fn()
+        return out, time.perf_counter() - t0
+
+    qs = wl.configs("kern/q", 262_144, arm.n).astype(np.float64)
+    P, t = timed(lambda: oracle.control_points(dh, arm.frames, qs))
+    rows["fk_points"] = {"oracle_configs_per_s": qs.shape[0] / t, "sample": "262,144 configurations",
+                         "gpu_configs_per_s": kern.get("fk_points", {}).get("configs_per_s")}
+    _, t = timed(lambda: oracle.score_points(P[:1], np.ones(1), 10.0, P))
+    rows["gram_column"] = {"oracle_points_per_s": P.shape[0] / t, "sample": "one column over 262,144 points",
+                           "gpu_points_per_s": kern.get("gram_update", {}).get("points_per_s")}
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    _, t = timed(lambda: oracle.capsule_box_labels(dh, qs[:65_536], arm.radius, lo, hi))
+    rows["labels"] = {"oracle_configs_per_s": 65_536 / t, "sample": "65,536 configurations, 20 cubes",
+                      "gpu_configs_per_s": kern.get("label_capsule_box", {}).get("configs_per_s")}
+    d3 = extras.get("dof3")
+    if d3:
+        a3 = wl.arm_3dof()
+        dh3 = oracle.dh_table(a3.a, a3.alpha, a3.d, a3.theta, a3.joint_type)
+        q3 = wl.configs("train3", 2000, a3.n, seed=d3["seed"]).astype(np.float64)
+        lo3, hi3 = wl.cubes("train3/cubes", 5, 0.15, None, seed=d3["seed"])
+        y3, _ = oracle.capsule_box_labels(dh3, q3, a3.radius, lo3, hi3)
+        P3 = oracle.control_points(dh3, a3.frames, q3).astype(np.float32).astype(np.float64)
+        r3, t = timed(lambda: oracle.fastron_update(P3, y3, 10.0))
+        rows["train_3dof"] = {"oracle_ms": t * 1e3, "oracle_updates": r3["updates"],
+                              "gpu_ms_fp64": d3["train_ms_fp64"], "gpu_updates": d3["updates"],
+                              "sample": "2,000 labelled 3-DOF configurations, gamma = 10"}
+    params = [p.astype(np.float64) for p in wl.split_mlp_params(wl.mlp_init(24, 256, name="cpu_rows"), 24)]
+    X = P[:65_536].reshape(-1, 24)
+    _, t = timed(lambda: mlp_oracle.forward(params, X, X.mean(axis=0), X.std(axis=0) + 1e-9))
+    scr = extras.get("screen", {})
+    tau0 = next((r for r in scr.get("screened", []) if r["tau"] == 0.0), {})
+    rows["mlp_forward"] = {"oracle_queries_per_s": X.shape[0] / t, "sample": "65,536 queries (NumPy FP64)",
+                           "gpu_screen_tau0_checks_per_s": tau0.get("checks_per_s")}
+    return rows
 
 
 def _cpu_model():
