@@ -86,8 +86,13 @@ def main():
                     help="also run a plain 256 MiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); got --gpus {args.gpus}",
+        print(f"bench.py measures one GPU only (there is no multi-GPU path); got --gpus {args.gpus}",
               file=sys.stderr)
+        sys.exit(2)
+    legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
+    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "batched", "retrain", "screen"}
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -158,11 +163,6 @@ def main():
 
     extras = {}
     checks = []  # GPU results queued for the FP64 comparison of the CPU leg
-    legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "batched", "retrain", "screen"}
-    if unknown:
-        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
-        sys.exit(2)
     if "kernels" in legs:
         log("[bench] FK, Gram-column and labeller kernels on 4,194,304 configurations")
         extras["kernels"] = kernels_run(api, wl, arm, dev)
