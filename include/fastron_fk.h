@@ -98,7 +98,12 @@ fastron_status fastron_fk_points(const fastron_chain* chain, const fastron_cpoin
  * weights alpha_i) converted once into the operand layout the scoring kernels
  * stream: per-point scaled control points, their squared norms and alpha/M.
  * `data` is caller-owned device memory of at least fastron_model_bytes(S, M)
- * bytes, 256-byte aligned; its contents are private to the library.         */
+ * bytes, 256-byte aligned; its contents are private to the library. The
+ * blob holds the supports' control points, so a model must be scored with
+ * the chain and control points it was prepared with. support_q is [S][n]
+ * float, alpha [S] float (device). fastron_model_bytes returns -1 for S < 0
+ * or M outside [1, 16]; fastron_support_prep returns FASTRON_EINVAL for a
+ * blob that is too small or misaligned, gamma <= 0 or a bad chain.          */
 typedef struct {
   int64_t S;        /* support-set size (0 allowed: f == 0 everywhere) */
   int32_t M;        /* control points per configuration */
