@@ -124,3 +124,25 @@ def test_control_point_frames_match_oracle(lib, oracle_mod):
         for inc in (False, True):
             ref = oracle_mod.control_point_frames(oracle_mod.dh_table(a, np.zeros(n), d, None, types), inc)
             assert _frames_lib(lib, a, d, types, inc) == list(ref)
+
+
+def test_constructor_validation(lib):
+    """Batch and network constructors reject bad arguments before touching a device."""
+    arm = wl.arm_7dof()
+    hc = nat.HostChain(arm)
+    h = ctypes.c_void_p()
+    so = (ctypes.c_int64 * 3)(0, 10, 5)  # decreasing
+    qo = (ctypes.c_int64 * 3)(0, 4, 8)
+    assert lib.fastron_batch_create(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), 2, so, qo, 10.0,
+                                    ctypes.byref(h)) == nat.FASTRON_EINVAL
+    assert "decreases" in nat.last_error()
+    so_ok = (ctypes.c_int64 * 3)(0, 10, 15)
+    assert lib.fastron_batch_create(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), 2, so_ok, qo, -1.0,
+                                    ctypes.byref(h)) == nat.FASTRON_EINVAL
+    assert lib.fastron_batch_create(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), 0, so_ok, qo, 10.0,
+                                    ctypes.byref(h)) == nat.FASTRON_EINVAL
+    assert not h.value
+    for d_in, hidden, rows in ((0, 256, 16), (24, 17, 16), (24, 256, 0), (49, 256, 16)):
+        assert lib.fastron_mlp_create(d_in, hidden, rows, ctypes.byref(h)) == nat.FASTRON_EINVAL, (d_in, hidden, rows)
+    assert lib.fastron_mlp_screen_workspace_bytes(-1, 7) == -1
+    assert lib.fastron_mlp_param_count(None) == -1
