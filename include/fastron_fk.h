@@ -46,7 +46,7 @@ typedef enum {
   FASTRON_EUNSUPPORTED = -2,  /* valid but unsupported request (e.g. no gfx950 device) */
   FASTRON_EHIP = -3,          /* a HIP runtime call failed; see fastron_last_error() */
   FASTRON_ENOMEM = -4,        /* a device allocation failed */
-  FASTRON_EDEVICE = -5        /* a device-side safety limit fired (e.g. a grid barrier timed out) */
+  FASTRON_EDEVICE = -5        /* a device-side safety limit fired (the training record exchange timed out) */
 } fastron_status;
 
 #define FASTRON_MAX_JOINTS 16

@@ -863,7 +863,8 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   if (e != hipSuccess) return fail(FASTRON_EHIP, "training launch failed: %s", hipGetErrorString(e));
   *updates = host[0];
   *n_support = host[2];
-  if (host[1] == -5) return fail(FASTRON_EDEVICE, "grid barrier timed out after %lld updates", (long long)host[0]);
+  if (host[1] == -5)
+    return fail(FASTRON_EDEVICE, "record exchange timed out after %lld updates", (long long)host[0]);
   rs = host[1] == 0 ? FASTRON_OK : FASTRON_NOT_CONVERGED;
   return rs;
 }
