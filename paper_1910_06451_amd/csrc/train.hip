@@ -53,9 +53,8 @@ struct TrainState {
   const int8_t* y;
   T* alpha;
   T* F;
-  Rec<T>* rec;         // [2][G]
-  unsigned* bar;       // [0] arrivals, [1] generation
-  int64_t* out;        // [0] updates, [1] status (0 break, 1 iter_max, -5 barrier timeout)
+  Rec<T>* rec;         // record words [2][G][K]
+  int64_t* out;        // [0] updates, [1] status (0 break, 1 iter_max, -5 exchange timeout)
   int32_t* trace_act;
   int32_t* trace_idx;
   int64_t trace_cap;
@@ -208,7 +207,7 @@ template <typename T>
 struct Decision {
   T dalpha;
   int64_t i;
-  int action;  // 1 add, 2 remove, 0 break (converged), 3 stop (iter_max), 4 stop (barrier timeout)
+  int action;  // 1 add, 2 remove, 0 break (converged), 3 stop (iter_max), 4 stop (exchange timeout)
 };
 
 template <typename T>
@@ -678,13 +677,10 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
   }
 }
 
-__global__ void k_train_init(unsigned long long* words, int64_t nwords, unsigned* bar, int64_t* out) {
+__global__ void k_train_init(unsigned long long* words, int64_t nwords, int64_t* out) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i < nwords) words[i] = 0ull;
-  if (blockIdx.x == 0 && threadIdx.x < 2) {
-    bar[threadIdx.x] = 0u;
-    out[threadIdx.x] = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x < 2) out[threadIdx.x] = 0;
 }
 
 // removeNonsupportPoints: stable compaction of the indices with alpha != 0.
@@ -817,13 +813,12 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   }
   const size_t rec_bytes = ((sizeof(unsigned long long) * 2 * (size_t)G * RecWords<T>::K + 255) / 256) * 256;
   char* ws = nullptr;
-  FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), rec_bytes + 256 + 256, s));
+  FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), rec_bytes + 256, s));
   Rec<T>* rec = reinterpret_cast<Rec<T>*>(ws);  // reinterpreted as record words by the kernel
-  unsigned* bar = reinterpret_cast<unsigned*>(ws + rec_bytes);
-  int64_t* out = reinterpret_cast<int64_t*>(ws + rec_bytes + 64);
-  int64_t* cnt = reinterpret_cast<int64_t*>(ws + rec_bytes + 128);
+  int64_t* out = reinterpret_cast<int64_t*>(ws + rec_bytes);
+  int64_t* cnt = reinterpret_cast<int64_t*>(ws + rec_bytes + 64);
   hipLaunchKernelGGL(k_train_init, dim3((unsigned)((rec_bytes / 8 + 255) / 256)), dim3(256), 0, s,
-                     reinterpret_cast<unsigned long long*>(ws), (int64_t)(rec_bytes / 8), bar, out);
+                     reinterpret_cast<unsigned long long*>(ws), (int64_t)(rec_bytes / 8), out);
   fastron_status rs = FASTRON_OK;
   hipError_t e = hipGetLastError();
   if (e == hipSuccess) {
@@ -833,7 +828,6 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     st.alpha = alpha;
     st.F = F;
     st.rec = rec;
-    st.bar = bar;
     st.out = out;
     st.trace_act = trace_action;
     st.trace_idx = trace_index;
