@@ -280,7 +280,7 @@ def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
                                   "segment_box_tests_per_s": N * arm.n * 20 / (t_lab * 1e-3)}}
 
 
-def precision_run(api, wl, arm, gamma, dev, checks, S=16_384, N=4_194_304, fp64_sample=262_144, reps=5):
+def precision_run(api, wl, arm, gamma, dev, checks, S=16_384, N=4_194_304, fp64_sample=1_048_576, reps=5):
     """FP32 score versus the BF16 cross-term forms on S = 16,384 supports and N = 4,194,304 queries: kernel time
     of each form, max |df| and sign agreement against the FP32 path (all queries); an evenly spaced sample of
     fp64_sample queries of every form is queued for the FP64 comparison of the CPU leg."""
