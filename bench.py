@@ -445,35 +445,57 @@ def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
 
 
 def retrain_run(api, wl, arm, dev, n_env=16, N=20_000):
-    """Per environment: label, train, shift every cube by 0.05 m in a random direction, relabel, warm-start."""
+    """16 environments: label, train, shift every cube by 0.05 m in a random direction, relabel, warm-start.
+    Once one environment after the other (fastron_train), once all 16 in one launch (fastron_train_batch), whose
+    results must be identical."""
     import torch
 
     envs = wl.batched_envs()
-    rows = []
-    torch.cuda.synchronize()
-    t_all = time.perf_counter()
+    qs, y0s, y1s = [], [], []
     for e in range(n_env):
         q = torch.from_numpy(wl.configs(f"retrain/{e}/q", N, arm.n)).to(dev)
         lo, hi = wl.cubes(f"retrain/{e}/cubes", int(envs.cube_counts[e]), 0.1, 0.25)
         y0, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
-        P = api.fk_points(arm, q)
-        first = api.train(P, y0, GAMMA_TRAIN_7DOF)
         shift = 0.05 * wl.unit_directions(f"retrain/{e}/shift", lo.shape[0])
         y1, _ = api.label_capsule_box(arm, q, arm.radius, lo + shift, hi + shift, want_clearance=False)
+        qs.append(q)
+        y0s.append(y0)
+        y1s.append(y1)
+    P = api.fk_points(arm, torch.cat(qs))
+    Y0, Y1 = torch.cat(y0s), torch.cat(y1s)
+    off = np.arange(n_env + 1, dtype=np.int64) * N
+    rows = []
+    torch.cuda.synchronize()
+    t_all = time.perf_counter()
+    seq = []
+    for e in range(n_env):
+        sl = slice(e * N, (e + 1) * N)
+        first = api.train(P[sl].contiguous(), Y0[sl].contiguous(), GAMMA_TRAIN_7DOF)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        second = api.train(P, y1, GAMMA_TRAIN_7DOF, alpha=first["alpha"], F=first["F"])
+        second = api.train(P[sl].contiguous(), Y1[sl].contiguous(), GAMMA_TRAIN_7DOF, alpha=first["alpha"],
+                           F=first["F"])
         torch.cuda.synchronize()
-        rows.append({"cubes": int(envs.cube_counts[e]), "relabelled": int((y0 != y1).sum().item()),
-                     "updates_first": first["updates"], "updates_warm": second["updates"],
-                     "support_first": int(first["support"].numel()), "support_warm": int(second["support"].numel()),
+        seq.append(second)
+        rows.append({"updates_first": first["updates"], "updates_warm": second["updates"],
                      "warm_ms": (time.perf_counter() - t0) * 1e3, "converged": bool(second["converged"])})
+    t_seq = time.perf_counter() - t_all
+    t0 = time.perf_counter()
+    b0 = api.train_batch(P, Y0, off, GAMMA_TRAIN_7DOF)
     torch.cuda.synchronize()
-    return {"envs": n_env, "N_per_env": N, "total_ms": (time.perf_counter() - t_all) * 1e3,
+    t1 = time.perf_counter()
+    b1 = api.train_batch(P, Y1, off, GAMMA_TRAIN_7DOF, alpha=b0["alpha"], F=b0["F"])
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    same = all(torch.equal(b1["alpha"][e * N:(e + 1) * N], seq[e]["alpha"]) for e in range(n_env))
+    return {"envs": n_env, "N_per_env": N, "total_ms_one_after_another": t_seq * 1e3,
             "warm_ms_mean": float(np.mean([r["warm_ms"] for r in rows])),
             "updates_warm_mean": float(np.mean([r["updates_warm"] for r in rows])),
             "updates_first_mean": float(np.mean([r["updates_first"] for r in rows])),
-            "all_converged": all(r["converged"] for r in rows)}
+            "all_converged": all(r["converged"] for r in rows),
+            "one_launch": {"first_ms": (t1 - t0) * 1e3, "warm_ms": (t2 - t1) * 1e3,
+                           "warm_speedup_vs_one_after_another": sum(r["warm_ms"] for r in rows) / ((t2 - t1) * 1e3),
+                           "converged": bool(b0["converged"] and b1["converged"]), "identical": bool(same)}}
 
 
 def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304, taus=(0.0, 0.5, 1.0, 2.0, 4.0)):

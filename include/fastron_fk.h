@@ -177,6 +177,19 @@ fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int
                                  int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
                                  int64_t trace_cap, void* stream);
 
+/* Several independent training sets (Algorithm 1 each, FP32) in one launch,
+ * e.g. the environments of the batched form after their obstacles moved:
+ * set e is rows offsets[e] .. offsets[e+1] - 1 of P, y, alpha and F
+ * (offsets: HOST array of E + 1 int64, strictly increasing from 0). The sets
+ * advance concurrently, each with its own exchange, and each ends exactly as
+ * fastron_train on that set alone would. support_idx [N_total] receives set
+ * e's ascending support indices (relative to offsets[e]) at
+ * support_idx[offsets[e]]; n_support and updates are HOST arrays [E]. The
+ * call synchronises `stream`; FASTRON_NOT_CONVERGED if any set hit iter_max.*/
+fastron_status fastron_train_batch(const float* P, const int8_t* y, int32_t E, const int64_t* offsets, int32_t M,
+                                   float gamma, float beta, int64_t iter_max, int64_t s_max, float* alpha, float* F,
+                                   int32_t* support_idx, int64_t* n_support, int64_t* updates, void* stream);
+
 /* ---- a7: batched form ----------------------------------------------------
  * E environments share one arm (chain + control points); environment e has
  * its own Fastron model (supports support_off[e] .. support_off[e+1] - 1 of

@@ -15,7 +15,7 @@ from . import _native as nat
 from ._native import HostChain, check
 
 __all__ = [
-    "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train",
+    "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train", "train_batch",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
@@ -189,6 +189,42 @@ def train(P: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, ite
         out["trace_action"] = tr_a[:k]
         out["trace_index"] = tr_i[:k]
     return out
+
+
+def train_batch(P: torch.Tensor, y: torch.Tensor, offsets, gamma: float, beta: float = 1.0,
+                iter_max: int | None = None, s_max: int | None = None, alpha: torch.Tensor | None = None,
+                F: torch.Tensor | None = None):
+    """Algorithm 1 on several independent training sets at once (rows offsets[e] .. offsets[e+1] - 1 of P and y
+    form set e). iter_max / s_max default to 20 N_e / N_e of the largest set. Returns dict(alpha, F,
+    supports (list of index tensors relative to each set), converged (all sets), updates (list))."""
+    _dev(P, torch.float32, "P")
+    _dev(y, torch.int8, "y")
+    N, M = P.shape[0], P.shape[1]
+    if P.dim() != 3 or P.shape[2] != 3 or y.shape != (N,):
+        raise ValueError("P must be (N, M, 3) and y (N,)")
+    off = np.ascontiguousarray(np.asarray(offsets, dtype=np.int64))
+    E = off.shape[0] - 1
+    if E < 1 or off[0] != 0 or off[-1] != N or np.any(np.diff(off) <= 0):
+        raise ValueError("offsets must increase strictly from 0 to N")
+    largest = int(np.max(np.diff(off)))
+    alpha = torch.zeros(N, dtype=torch.float32, device=P.device) if alpha is None else alpha.clone()
+    F = torch.zeros(N, dtype=torch.float32, device=P.device) if F is None else F.clone()
+    _dev(alpha, torch.float32, "alpha")
+    _dev(F, torch.float32, "F")
+    if alpha.shape != (N,) or F.shape != (N,):
+        raise ValueError("alpha and F must be (N,)")
+    iter_max = 20 * largest if iter_max is None else int(iter_max)
+    s_max = largest if s_max is None else int(s_max)
+    support = torch.empty(N, dtype=torch.int32, device=P.device)
+    ns = np.zeros(E, dtype=np.int64)
+    upd = np.zeros(E, dtype=np.int64)
+    p64 = ctypes.POINTER(ctypes.c_int64)
+    st = nat.lib().fastron_train_batch(_ptr(P), _ptr(y), E, off.ctypes.data_as(p64), M, float(gamma), float(beta),
+                                       iter_max, s_max, _ptr(alpha), _ptr(F), _ptr(support), ns.ctypes.data_as(p64),
+                                       upd.ctypes.data_as(p64), _stream())
+    check(st, allow=(nat.FASTRON_OK, nat.FASTRON_NOT_CONVERGED))
+    supports = [support[off[e]:off[e] + ns[e]] for e in range(E)]
+    return dict(alpha=alpha, F=F, supports=supports, converged=(st == nat.FASTRON_OK), updates=upd.tolist())
 
 
 def label_capsule_box(arm, q: torch.Tensor, radius: float, boxes_lo, boxes_hi, want_clearance=True):

@@ -24,6 +24,7 @@
 // Records are double-buffered by iteration parity. The wait is bounded by a
 // constant-clock budget and reports FASTRON_EDEVICE instead of hanging.
 #include <cmath>
+#include <vector>
 
 #include "fastron_internal.h"
 
@@ -67,6 +68,13 @@ struct TrainState {
   int chunk;           // training points per workgroup
   long long timeout;    // wait limit for the record exchange, in constant-clock ticks
   int p_in_lds;         // the slice's control points are staged in LDS
+  // several independent training sets in one launch (single-wave kernel only):
+  // workgroup w trains set env_of[w], whose workgroups are env_wg0[e] ..
+  // env_wg0[e + 1] - 1, whose points are env_off[e] .. env_off[e + 1] - 1, and
+  // whose (updates, status) go to out[2 e], out[2 e + 1]. NULL: one set.
+  const int32_t* env_of;
+  const int32_t* env_wg0;
+  const int64_t* env_off;
 };
 
 template <typename T>
@@ -528,15 +536,28 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
   constexpr int K = RecWords<T>::K;
   __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
   extern __shared__ float pslice[];  // this slice's control points when they fit (st.p_in_lds)
-  const unsigned G = gridDim.x;
   const int lane = threadIdx.x;
-  const int64_t j0 = (int64_t)blockIdx.x * st.chunk;
-  const int64_t j1 = (j0 + st.chunk < st.N) ? j0 + st.chunk : st.N;
+  // this workgroup's training set: its workgroups (G, own index me), points and records
+  unsigned G = gridDim.x, me = blockIdx.x;
+  int64_t set_lo = 0, set_hi = st.N;
+  unsigned long long* words = reinterpret_cast<unsigned long long*>(st.rec);  // [2][G][K] per set
+  int64_t* out = st.out;
+  if (st.env_of) {
+    const int e = st.env_of[blockIdx.x];
+    const int w0 = st.env_wg0[e];
+    G = (unsigned)(st.env_wg0[e + 1] - w0);
+    me = blockIdx.x - (unsigned)w0;
+    set_lo = st.env_off[e];
+    set_hi = st.env_off[e + 1];
+    words += (size_t)2 * K * w0;
+    out += 2 * e;
+  }
+  const int64_t j0 = set_lo + (int64_t)me * st.chunk;
+  const int64_t j1 = (j0 + st.chunk < set_hi) ? j0 + st.chunk : set_hi;
   const int M = st.M;
   if (st.p_in_lds)
     for (int64_t e = lane; e < (j1 - j0) * 3 * M; e += 64) pslice[e] = st.P[j0 * 3 * M + e];
   __syncthreads();
-  unsigned long long* words = reinterpret_cast<unsigned long long*>(st.rec);  // [2][G][K]
 
   T y[PT], F[PT], a[PT];
   int64_t jj[PT];
@@ -571,7 +592,7 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
     const unsigned long long seq = (unsigned long long)(uint32_t)(it + 1) << 32;
     unsigned long long* slot = words + (size_t)(it & 1) * G * K;
     if (lane < K)
-      __hip_atomic_store(slot + (size_t)blockIdx.x * K + lane, seq | RecWords<T>::get(r, lane), __ATOMIC_RELAXED,
+      __hip_atomic_store(slot + (size_t)me * K + lane, seq | RecWords<T>::get(r, lane), __ATOMIC_RELAXED,
                          __HIP_MEMORY_SCOPE_AGENT);
     uint32_t pay[kWaveChunks][K];
     bool ready[kWaveChunks];
@@ -635,7 +656,7 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
       break;
     }
     if (lane < 3 * M) pi_sh[lane] = st.P[d.i * (int64_t)M * 3 + lane];
-    if (blockIdx.x == 0 && lane == 0 && updates < st.trace_cap) {
+    if (me == 0 && lane == 0 && updates < st.trace_cap) {
       st.trace_act[updates] = d.action;
       st.trace_idx[updates] = (int32_t)d.i;
     }
@@ -671,9 +692,9 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
       st.F[jj[k]] = F[k];
       st.alpha[jj[k]] = a[k];
     }
-  if (blockIdx.x == 0 && lane == 0) {
-    st.out[0] = updates;
-    st.out[1] = status;
+  if (me == 0 && lane == 0) {
+    out[0] = updates;
+    out[1] = status;
   }
 }
 
@@ -841,6 +862,9 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     st.chunk = (int)chunk;
     st.timeout = 400000000ll;  // 4 s at 100 MHz
     st.p_in_lds = lds_bytes > 0 ? 1 : 0;
+    st.env_of = nullptr;
+    st.env_wg0 = nullptr;
+    st.env_off = nullptr;
     void* args[] = {&st};
     e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3((unsigned)threads), args, lds_bytes, s);
   }
@@ -861,6 +885,137 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     return fail(FASTRON_EDEVICE, "record exchange timed out after %lld updates", (long long)host[0]);
   rs = host[1] == 0 ? FASTRON_OK : FASTRON_NOT_CONVERGED;
   return rs;
+}
+
+// Several independent training sets in one cooperative launch of the
+// single-wave kernel: set e gets ceil(N_e / (64 PT)) workgroups, its own
+// records and its own exchange, so the sets advance concurrently.
+static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t E, const int64_t* offsets, int32_t M,
+                                       float gamma, float beta, int64_t iter_max, int64_t s_max, float* alpha, float* F,
+                                       int32_t* support_idx, int64_t* n_support, int64_t* updates, void* stream) {
+  clear_error();
+  FASTRON_CHECK(E >= 1 && E <= 4096, "E = %d outside [1, 4096]", E);
+  FASTRON_CHECK(offsets != nullptr, "offsets must be a non-NULL host array");
+  FASTRON_CHECK(offsets[0] == 0, "offsets must start at 0");
+  for (int e = 0; e < E; ++e)
+    FASTRON_CHECK(offsets[e + 1] > offsets[e], "training set %d is empty or offsets decrease", e);
+  const int64_t N = offsets[E];
+  FASTRON_CHECK(N < INT32_MAX, "N = %lld outside [1, 2^31)", (long long)N);
+  FASTRON_CHECK(M >= 1 && M <= FASTRON_MAX_POINTS, "M = %d outside [1, %d]", M, FASTRON_MAX_POINTS);
+  FASTRON_CHECK(P && y && alpha && F && support_idx, "P, y, alpha, F and support_idx must be non-NULL");
+  FASTRON_CHECK(n_support && updates, "n_support and updates must be non-NULL host arrays");
+  FASTRON_CHECK(std::isfinite(gamma) && gamma > 0.f, "gamma must be finite and > 0");
+  FASTRON_CHECK(std::isfinite(beta) && beta >= 1.f, "beta must be >= 1 (Eq. 5)");
+  FASTRON_CHECK(iter_max >= 0, "iter_max < 0");
+  FASTRON_CHECK(s_max >= 1, "s_max must be >= 1");
+  hipStream_t s = as_stream(stream);
+  int dev = 0, ncu = 0, coop = 0;
+  FASTRON_HIP(hipGetDevice(&dev));
+  FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+  FASTRON_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
+  if (!coop) return fail(FASTRON_EUNSUPPORTED, "device does not support cooperative launches");
+  // smallest PT whose grid fits the cap per set and the resident capacity in total
+  const int64_t cap = tune_get("train.wave_groups");
+  int PT = 1;
+  const void* kfn = nullptr;
+  int64_t G = 0;
+  size_t lds_bytes = 0;
+  for (;; PT *= 2) {
+    if (PT > 16) return fail(FASTRON_EUNSUPPORTED, "training sets too large for one resident launch");
+    int64_t total = 0, largest = 0;
+    for (int e = 0; e < E; ++e) {
+      const int64_t ge = (offsets[e + 1] - offsets[e] + 64 * PT - 1) / (64 * PT);
+      total += ge;
+      largest = ge > largest ? ge : largest;
+    }
+    if (largest > cap && PT < 16) continue;
+    if (largest > kWaveChunks * 64) continue;
+    const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
+    kfn = wave_kernel<float>(PT, mm);
+    lds_bytes = mm ? 0 : (size_t)64 * PT * 3 * M * sizeof(float);
+    if (lds_bytes > 48 * 1024) lds_bytes = 0;
+    int per_cu = 0;
+    FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 64, lds_bytes));
+    if (per_cu >= 1 && total <= (int64_t)per_cu * ncu) {
+      G = total;
+      break;
+    }
+  }
+  const int64_t chunk = 64 * (int64_t)PT;
+  std::vector<int32_t> env_of((size_t)G), env_wg0((size_t)E + 1);
+  env_wg0[0] = 0;
+  for (int e = 0; e < E; ++e) {
+    const int64_t ge = (offsets[e + 1] - offsets[e] + chunk - 1) / chunk;
+    env_wg0[e + 1] = env_wg0[e] + (int32_t)ge;
+    for (int64_t w = env_wg0[e]; w < env_wg0[e + 1]; ++w) env_of[(size_t)w] = e;
+  }
+  constexpr int K = RecWords<float>::K;
+  const size_t rec_bytes = ((sizeof(unsigned long long) * 2 * (size_t)G * K + 255) / 256) * 256;
+  const size_t tab_bytes = ((sizeof(int32_t) * ((size_t)G + E + 1) + sizeof(int64_t) * (E + 1) + 255) / 256) * 256;
+  const size_t out_bytes = ((sizeof(int64_t) * 3 * (size_t)E + 255) / 256) * 256;
+  char* ws = nullptr;
+  FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&ws), rec_bytes + tab_bytes + out_bytes, s));
+  int32_t* d_env_of = reinterpret_cast<int32_t*>(ws + rec_bytes);
+  int32_t* d_env_wg0 = d_env_of + G;
+  int64_t* d_env_off = reinterpret_cast<int64_t*>(ws + rec_bytes + tab_bytes - sizeof(int64_t) * (E + 1));
+  int64_t* out = reinterpret_cast<int64_t*>(ws + rec_bytes + tab_bytes);  // [E][2], then counts [E]
+  int64_t* cnt = out + 2 * E;
+  hipError_t e = hipMemcpyAsync(d_env_of, env_of.data(), sizeof(int32_t) * G, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(d_env_wg0, env_wg0.data(), sizeof(int32_t) * (E + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d_env_off, offsets, sizeof(int64_t) * (E + 1), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_train_init, dim3((unsigned)((rec_bytes / 8 + 255) / 256)), dim3(256), 0, s,
+                       reinterpret_cast<unsigned long long*>(ws), (int64_t)(rec_bytes / 8), out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) {
+    TrainState<float> st;
+    st.P = P;
+    st.y = y;
+    st.alpha = alpha;
+    st.F = F;
+    st.rec = reinterpret_cast<Rec<float>*>(ws);
+    st.out = out;
+    st.trace_act = nullptr;
+    st.trace_idx = nullptr;
+    st.trace_cap = 0;
+    st.N = N;
+    st.iter_max = iter_max;
+    st.s_max = s_max;
+    st.half_g = gamma / 2.0f;
+    st.beta = beta;
+    st.M = M;
+    st.chunk = (int)chunk;
+    st.timeout = 400000000ll;  // 4 s at 100 MHz
+    st.p_in_lds = lds_bytes > 0 ? 1 : 0;
+    st.env_of = d_env_of;
+    st.env_wg0 = d_env_wg0;
+    st.env_off = d_env_off;
+    void* args[] = {&st};
+    e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3(64), args, lds_bytes, s);
+  }
+  for (int k = 0; k < E && e == hipSuccess; ++k) {
+    hipLaunchKernelGGL(k_compact<float>, dim3(1), dim3(1024), 0, s, alpha + offsets[k], offsets[k + 1] - offsets[k],
+                       support_idx + offsets[k], cnt + k);
+    e = hipGetLastError();
+  }
+  std::vector<int64_t> host((size_t)3 * E, 0);
+  if (e == hipSuccess) e = hipMemcpyAsync(host.data(), out, sizeof(int64_t) * 3 * E, hipMemcpyDeviceToHost, s);
+  const hipError_t ef = hipFreeAsync(ws, s);
+  if (e == hipSuccess) e = ef;
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(FASTRON_EHIP, "batched training failed: %s", hipGetErrorString(e));
+  bool all_converged = true;
+  for (int k = 0; k < E; ++k) {
+    updates[k] = host[2 * k];
+    n_support[k] = host[2 * E + k];
+    if (host[2 * k + 1] == -5)
+      return fail(FASTRON_EDEVICE, "record exchange of training set %d timed out after %lld updates", k,
+                  (long long)host[2 * k]);
+    if (host[2 * k + 1] != 0) all_converged = false;
+  }
+  return all_converged ? FASTRON_OK : FASTRON_NOT_CONVERGED;
 }
 
 }  // namespace fastron
@@ -893,6 +1048,13 @@ fastron_status fastron_train(const float* P, const int8_t* y, int64_t N, int32_t
                              int64_t trace_cap, void* stream) {
   return train_impl<float>(P, y, N, M, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
                            trace_action, trace_index, trace_cap, stream);
+}
+
+fastron_status fastron_train_batch(const float* P, const int8_t* y, int32_t E, const int64_t* offsets, int32_t M,
+                                   float gamma, float beta, int64_t iter_max, int64_t s_max, float* alpha, float* F,
+                                   int32_t* support_idx, int64_t* n_support, int64_t* updates, void* stream) {
+  return train_batch_impl(P, y, E, offsets, M, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                          stream);
 }
 
 fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma, double beta,

@@ -199,3 +199,37 @@ def test_train_full_size_claim2(oracle_mod, dev):
     assert np.all(y * F_gpu > 0)
     assert np.abs(F_gpu - F_oracle).max() < 1e-2
     assert np.mean(margins > 0) >= 0.999
+
+
+def test_train_batch_matches_single_sets(oracle_mod, dev):
+    """Several training sets in one launch (ragged sizes, one set of a single point) end exactly as each set
+    trained alone: same weights, F, support and update count; also from a warm start after relabelling."""
+    arm = wl.arm_7dof()
+    dh = oracle_dh(oracle_mod, arm)
+    sizes = [1, 777, 2048, 3001, 64]
+    off = np.concatenate([[0], np.cumsum(sizes)])
+    q = wl.configs("train_batch/q", int(off[-1]), arm.n)
+    lo, hi = wl.cubes("train_batch/cubes", 20, 0.1, 0.25)
+    y0, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+    shift = 0.05 * wl.unit_directions("train_batch/shift", lo.shape[0])
+    y1, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo + shift, hi + shift)
+    P = torch.from_numpy(oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)).to(dev)
+    Y0 = torch.from_numpy(y0.astype(np.int8)).to(dev)
+    Y1 = torch.from_numpy(y1.astype(np.int8)).to(dev)
+    iters = 200_000
+    announce("train_batch: 5 sets, fresh")
+    b0 = api.train_batch(P, Y0, off, 30.0, iter_max=iters, s_max=4000)
+    announce("train_batch: 5 sets, warm start after relabelling")
+    b1 = api.train_batch(P, Y1, off, 30.0, iter_max=iters, s_max=4000, alpha=b0["alpha"], F=b0["F"])
+    for e in range(len(sizes)):
+        sl = slice(int(off[e]), int(off[e + 1]))
+        announce(f"train single set {e} (N={sizes[e]})")
+        s0 = api.train(P[sl].contiguous(), Y0[sl].contiguous(), 30.0, iter_max=iters, s_max=4000)
+        s1 = api.train(P[sl].contiguous(), Y1[sl].contiguous(), 30.0, iter_max=iters, s_max=4000,
+                       alpha=s0["alpha"], F=s0["F"])
+        for b, s_ in ((b0, s0), (b1, s1)):
+            assert torch.equal(b["alpha"][sl], s_["alpha"]), e
+            assert torch.equal(b["F"][sl], s_["F"]), e
+            assert torch.equal(b["supports"][e], s_["support"]), e
+        assert b0["updates"][e] == s0["updates"] and b1["updates"][e] == s1["updates"], e
+    assert b0["converged"] and b1["converged"]
