@@ -27,13 +27,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # Derived ALU ceiling of the FP32 fused score, in control-point kernel
-# evaluations (cp-evals) per second. One cp-eval needs the 4-deep cross term
-# with the norms (4 FMA-equivalents; FP32 MFMA runs on the same ALUs as the
-# vector FMAs and does not overlap with them), one reciprocal (quarter-rate
-# transcendental) and one FMA. With 128 FP32 lanes/clk/CU (the 157.3 TFLOP/s
-# figure) and 32 transcendental lanes/clk/CU:
-#   256 CU * 2.4e9 Hz / (5/128 + 1/32) = 8.74e12 cp-evals/s.
-ALU_PEAK_CP_PER_S = 256 * 2.4e9 / (5.0 / 128 + 1.0 / 32)
+# evaluations (cp-evals) per second: the instructions one (support, query) pair
+# with Mm moving points needs, priced at the published rates (FP32 MFMA and
+# vector FMA 128 lanes/clk/CU, the 157.3 TFLOP/s figure; transcendentals 32
+# lanes/clk/CU) with the matrix and vector units not overlapping. In units of
+# 1/128 CU clock per pair:
+#   cross term with the norms on the matrix unit        4 Mm
+#   saturated-reciprocal sum: Mm reciprocals (4 each) + Mm FMAs + 1 weighting FMA
+#                                                      -> 9 Mm + 1 in all
+#   running-fraction sum: Mm squares + 2 (Mm - 1) for numerator and
+#   denominator + one reciprocal (4) + the quotient + 1 weighting FMA
+#                                                      -> 7 Mm + 4 in all
+# e.g. Mm = 7: 8.60e12 (saturated) and 10.39e12 (fraction) cp-evals/s.
+def alu_peak(Mm, rational):
+    return 256 * 2.4e9 * 128 * Mm / ((7 * Mm + 4) if rational else (9 * Mm + 1))
 
 # HBM bytes per launch of the FP32 score kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled
@@ -150,8 +157,11 @@ def main():
         del src, dst
     cp_per_launch = N * S * Mm
     achieved = cp_per_launch / (k_ms * 1e-3)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": ALU_PEAK_CP_PER_S / 1e12,
-                "unit": "Tcp-eval/s", "frac": achieved / ALU_PEAK_CP_PER_S, "traffic": score_traffic(Mm, S, N),
+    rational = api.score_rational(arm, gamma)
+    peak = alu_peak(Mm, rational)
+    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
+                "unit": "Tcp-eval/s", "frac": achieved / peak, "traffic": score_traffic(Mm, S, N),
+                "sum_form": "running fraction" if rational else "saturated reciprocal",
                 "traffic_unit": "HBM bytes per launch",
                 # queries (n floats each) + the FP32 part of the packed support set (256 B header,
                 # 16-support tiles of 80 * Mp + 16 floats) + outputs (float score + int8 label)
@@ -352,7 +362,7 @@ def dof3_run(api, wl, dev, checks, reps=20):
            "queries_10k": {"ms": t_q, "accuracy": (tp + tn) / 10_000, "tpr": tp / max(pos, 1), "tnr": tn / max(neg, 1)},
            "throughput_1M": {"ms": t_b, "checks_per_s": N / (t_b * 1e-3), "kernel_evals_per_s": N * S / (t_b * 1e-3),
                              "cp_evals_per_s": N * S * Mm / (t_b * 1e-3),
-                             "frac_alu": N * S * Mm / (t_b * 1e-3) / ALU_PEAK_CP_PER_S}}
+                             "frac_alu": N * S * Mm / (t_b * 1e-3) / alu_peak(Mm, api.score_rational(arm, 10.0))}}
     checks.append({"arm": arm, "sq": q[sup].cpu().numpy(), "al": al.cpu().numpy(), "gamma": 10.0,
                    "q": qq.cpu().numpy(), "f": f.cpu().numpy(), "lab": lab.cpu().numpy(), "into": res["queries_10k"]})
     return res
@@ -430,7 +440,7 @@ def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
     Mm = int(np.sum(arm.frames > 0))
     res = {"E": envs.E, "queries": N_tot, "supports": S_tot, "tile_queries": tq, "ms_graph_replay": ms_batch,
            "checks_per_s": N_tot / (ms_batch * 1e-3), "kernel_evals_per_s": kevals / (ms_batch * 1e-3),
-           "frac_alu": kevals * Mm / (ms_batch * 1e-3) / ALU_PEAK_CP_PER_S,
+           "frac_alu": kevals * Mm / (ms_batch * 1e-3) / alu_peak(Mm, api.score_rational(arm, gamma)),
            "ms_plain_per_env_launches": ms_plain, "speedup_vs_plain": ms_plain / ms_batch,
            "identical_to_plain": same, "fp64_sample": {}}
     # FP64 comparison (CPU leg) on 2,000 evenly spaced queries of the largest and of the smallest environment

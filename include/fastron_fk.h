@@ -138,6 +138,19 @@ fastron_status fastron_fk_score_prepared(const fastron_chain* chain, const fastr
                                          const fastron_model* model, const float* q, int64_t N, float* f,
                                          int8_t* label, uint32_t flags, void* stream);
 
+/* Which of two equivalent ways the scoring kernels (single-model, batched and
+ * the screening fallback) use to sum K_RQ = 1/t^2 over the control points of
+ * one (support, query) pair, for this chain, control points, gamma and flags
+ * (host only, no device work): 1 = one running fraction n/e per pair with a
+ * single reciprocal (taken when a bound R on the distance of every moving
+ * point from the base -- finite unless a prismatic joint precedes one --
+ * keeps T = 1.01 (1 + 2 gamma R^2), an upper bound on t, within
+ * T^(2 Mm) <= 2^120 and T <= 2^16, or T <= 2^8 for FASTRON_BF16_PLAIN, and
+ * the tuning key "score.rational" is 1); 0 = one saturated reciprocal per
+ * value (always for FASTRON_SCORE_VALU). Negative: FASTRON_EINVAL for a bad
+ * chain, gamma <= 0 or unknown flags.                                       */
+int32_t fastron_score_rational(const fastron_chain* chain, const fastron_cpoints* cp, float gamma, uint32_t flags);
+
 /* Convenience form: prepares the support set (a2) into stream-ordered scratch
  * memory and scores (a3) in one call.                                       */
 fastron_status fastron_fk_score(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,
@@ -277,7 +290,16 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *   "train.wave_groups" grid cap of the single-wave kernel, 1..512 (256)
  *   "train.blocks"      workgroups of the multi-wave grid, 0 = automatic
  *   "train.threads"     threads per multi-wave workgroup: 256, 512 or 1024
- * fastron_tune_get returns -1 for an unknown key.                         */
+ *   "score.rational"    1 (default): the FP32 scoring kernels sum a pair's
+ *                       1/t^2 terms as one running fraction (one reciprocal
+ *                       per pair) when a bound on the chain's reach keeps the
+ *                       fraction in range (revolute joints up to the last
+ *                       moving point, T = 1.01 (1 + 2 gamma R^2) <= 2^16 and
+ *                       T^(2 Mm) <= 2^120); 0: one saturated reciprocal per
+ *                       value always. The two agree to FP32 rounding.
+ * Keys take effect at the next launch (a captured batch graph keeps the
+ * kernel it was captured with). fastron_tune_get returns -1 for an unknown
+ * key.                                                                      */
 fastron_status fastron_tune_set(const char* key, int64_t value);
 int64_t fastron_tune_get(const char* key);
 

@@ -48,6 +48,16 @@ def _chain(arm):
     return arm if isinstance(arm, HostChain) else HostChain(arm)
 
 
+def tune_get(key: str) -> int:
+    """Current value of a launch/tuning knob (-1 for an unknown key)."""
+    return int(nat.lib().fastron_tune_get(key.encode()))
+
+
+def tune_set(key: str, value: int) -> None:
+    """Sets a launch/tuning knob; raises on an unknown key or a value out of range."""
+    check(nat.lib().fastron_tune_set(key.encode(), int(value)))
+
+
 def control_point_frames(arm, include_base: bool = False) -> np.ndarray:
     """Frame indices of the control points placed by the library's Section III-A rule (frame origins,
     none for a revolute joint with a_i = d_i = 0; frame 0 first when include_base)."""
@@ -120,6 +130,14 @@ def fk_score_prepared(arm, model: PreparedModel, q: torch.Tensor, flags: int = S
                                               ctypes.byref(model.desc), _ptr(q), q.shape[0], _ptr(f), _ptr(lab),
                                               int(flags), _stream()))
     return f, lab
+
+
+def score_rational(arm, gamma: float, flags: int = SCORE_FP32) -> bool:
+    """True when scoring with this arm, gamma and flags sums each pair's 1/t^2 terms as one running fraction."""
+    hc = _chain(arm)
+    r = nat.lib().fastron_score_rational(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), float(gamma), int(flags))
+    check(min(r, 0))
+    return r == 1
 
 
 def fk_score(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, q: torch.Tensor,

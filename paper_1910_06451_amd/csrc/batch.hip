@@ -35,7 +35,7 @@ __global__ void k_reset_counter(unsigned long long* counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
-template <int MM, typename R, int QB>
+template <int MM, typename R, int QB, bool RAT>
 __global__ void __launch_bounds__(256) k_score_batched(ChainArgs c, const float* __restrict__ q,
                                                         const BatchItem* __restrict__ items, int64_t n_items,
                                                         unsigned long long* __restrict__ counter,
@@ -61,24 +61,29 @@ __global__ void __launch_bounds__(256) k_score_batched(ChainArgs c, const float*
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int64_t t0 = tile_off[it.env];
     const int64_t nt = tile_off[it.env + 1] - t0;
-    wave_score_fp32<MM, QB>(lds[wave], tiles + t0 * tile_floats(Mp), nt, Mp, f_const[it.env], it.q0, qend, f,
+    wave_score_fp32<MM, QB, RAT, false>(lds[wave], tiles + t0 * tile_floats(Mp), nt, Mp, f_const[it.env], it.q0, qend, f,
                             label);
   }
 }
 
-template <int MM, typename R>
-static const void* batched_kernel_r(int qb) {
+template <int MM, typename R, bool RAT>
+static const void* batched_kernel_q(int qb) {
   switch (qb) {
-    case 1: return reinterpret_cast<const void*>(k_score_batched<MM, R, 1>);
-    case 2: return reinterpret_cast<const void*>(k_score_batched<MM, R, 2>);
-    default: return reinterpret_cast<const void*>(k_score_batched<MM, R, 4>);
+    case 1: return reinterpret_cast<const void*>(k_score_batched<MM, R, 1, RAT>);
+    case 2: return reinterpret_cast<const void*>(k_score_batched<MM, R, 2, RAT>);
+    default: return reinterpret_cast<const void*>(k_score_batched<MM, R, 4, RAT>);
   }
 }
 
+template <int MM, typename R>
+static const void* batched_kernel_r(int qb, bool rat) {
+  return rat ? batched_kernel_q<MM, R, true>(qb) : batched_kernel_q<MM, R, false>(qb);
+}
+
 template <typename R>
-static const void* batched_kernel_m(int mm, int qb) {
+static const void* batched_kernel_m(int mm, int qb, bool rat) {
 #define FASTRON_BMM(K) \
-  case K: return batched_kernel_r<K, R>(qb);
+  case K: return batched_kernel_r<K, R>(qb, rat);
   switch (mm) {
     FASTRON_BMM(1) FASTRON_BMM(2) FASTRON_BMM(3) FASTRON_BMM(4) FASTRON_BMM(5) FASTRON_BMM(6) FASTRON_BMM(7)
     FASTRON_BMM(8) FASTRON_BMM(9) FASTRON_BMM(10) FASTRON_BMM(11) FASTRON_BMM(12) FASTRON_BMM(13)
@@ -156,7 +161,9 @@ fastron_status launch_batch(fastron_batch* b, const float* q, float* f, int8_t* 
   hipLaunchKernelGGL(k_reset_counter, dim3(1), dim3(64), 0, s, b->d_counter);
   FASTRON_HIP(hipGetLastError());
   if (b->n_items == 0) return FASTRON_OK;
-  const void* kfn = c.n >= kFp64Joints ? batched_kernel_m<double>(c.Mm, b->qb) : batched_kernel_m<float>(c.Mm, b->qb);
+  const bool rat = rational_sum_ok(c, b->gamma);
+  const void* kfn = c.n >= kFp64Joints ? batched_kernel_m<double>(c.Mm, b->qb, rat)
+                                       : batched_kernel_m<float>(c.Mm, b->qb, rat);
   if (!kfn) return fail(FASTRON_EUNSUPPORTED, "batched scoring needs 1..16 moving control points");
   int ncu = 0, per_cu = 0;
   FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device));

@@ -56,11 +56,23 @@ struct ChainArgs {
   uint32_t on_frame[FASTRON_MAX_JOINTS + 1];  // bit m set: control point m sits on frame i
   int32_t moving[FASTRON_MAX_POINTS];         // indices of the moving control points, in order
   int32_t slot[FASTRON_MAX_POINTS];           // rank of point m among the moving points, -1 if fixed
+  double reach;  // upper bound on |p| over the moving points and all joint values (inf past a prismatic joint)
 };
 
 // Validates chain and control points and packs them. `need_points` = false
 // for entry points that only use the chain (the labeller).
 fastron_status pack_chain(const fastron_chain* chain, const fastron_cpoints* cp, ChainArgs* out, bool need_points);
+
+// Whether the scoring kernels may sum 1/t^2 over a pair's control points as
+// one running fraction (no per-value reciprocal, no saturation): true when
+// the chain's reach bound R caps t = 1 + gamma/2 ||p - p'||^2 at
+// T = 1 + 2 gamma R^2 (with 1 % slack) such that T^(2 Mm) <= 2^120, so the
+// fraction's denominator and numerator stay finite and normal, and
+// T <= t_limit, so that t's own rounding error keeps it far from 0 without
+// the saturation: 2^16 where t is formed to FP32 accuracy (error a few units
+// of 2^-24 times T), 2^8 for one bf16 product per coordinate (error about
+// 2^-8 gamma R^2). The tuning key score.rational = 0 switches the form off.
+bool rational_sum_ok(const ChainArgs& c, float gamma, double t_limit = 65536.0);
 
 // Tuning table lookup (-1 for an unknown key).
 int64_t tune_get(const char* key);

@@ -1,5 +1,6 @@
 // Forward kinematics (Section II-A, Eq. 1-2), the prepared support set and the
 // library's shared host utilities (errors, argument packing).
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <mutex>
@@ -85,7 +86,41 @@ fastron_status pack_chain(const fastron_chain* chain, const fastron_cpoints* cp,
     }
   }
   out->Mm = mm;
+  // Reach bound: a revolute D-H link moves the next origin by sqrt(a^2 + d^2)
+  // whatever its angle; a prismatic one by an unbounded amount. The base
+  // matrix B scales lengths by at most sqrt(lambda_max(B^T B)), bounded by the
+  // largest absolute row sum of B^T B (Gershgorin; exactly 1 for a rotation).
+  double link[FASTRON_MAX_JOINTS + 1];
+  link[0] = 0.0;
+  for (int i = 0; i < n; ++i)
+    link[i + 1] = (out->prismatic >> i & 1u) ? HUGE_VAL : link[i] + std::hypot(out->a[i], out->d[i]);
+  double rn = 0.0;
+  for (int i = 0; i < 3; ++i) {
+    double row = 0.0;
+    for (int j = 0; j < 3; ++j) {
+      double btb = 0.0;
+      for (int k = 0; k < 3; ++k) btb += out->base_r[3 * k + i] * out->base_r[3 * k + j];
+      row += std::fabs(btb);
+    }
+    rn = std::max(rn, row);
+  }
+  rn = std::sqrt(rn) * (1.0 + 1e-12);
+  const double bp = std::sqrt(out->base_p[0] * out->base_p[0] + out->base_p[1] * out->base_p[1] +
+                              out->base_p[2] * out->base_p[2]);
+  out->reach = 0.0;
+  for (int k = 0; k < mm; ++k) {
+    const int m = out->moving[k];
+    const double off = std::sqrt(out->off[m][0] * out->off[m][0] + out->off[m][1] * out->off[m][1] +
+                                 out->off[m][2] * out->off[m][2]);
+    out->reach = std::max(out->reach, bp + rn * (link[cp->frame[m]] + off));
+  }
   return FASTRON_OK;
+}
+
+bool rational_sum_ok(const ChainArgs& c, float gamma, double t_limit) {
+  if (c.Mm < 1 || tune_get("score.rational") != 1 || !std::isfinite(c.reach)) return false;
+  const double T = 1.01 * (1.0 + 2.0 * (double)gamma * c.reach * c.reach);
+  return T <= t_limit && 2.0 * c.Mm * std::log2(T) <= 120.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -190,8 +225,9 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
     }
     if (B16) {
       // bf16 cross-term operand: -gamma p' split into hi + mid + lo bf16 terms, laid out so that the query
-      // side selects the precision: k0-2 hi, k3-5 hi, k6-8 mid, k9-11 hi, k12-14 lo, k15-17 mid, k18-20 = 1
-      // (the query side puts hi/mid/lo of p against them, and the three bf16 parts of c_q against the ones).
+      // side selects the precision: k0-2 hi, k3-5 hi, k6-8 mid, k9-11 hi, k12-14 lo, k15-17 mid, k18-20 = 1,
+      // k21-23 the hi/mid/lo bf16 parts of c_s (the query side puts hi/mid/lo of p against the first six
+      // groups, the three bf16 parts of c_q against the ones and ones against the parts of c_s).
       uint16_t sx[3], sy[3], sz[3];
       bf16_split(ax, 3, sx);
       bf16_split(ay, 3, sy);
@@ -202,6 +238,9 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
       put3(0, 0); put3(3, 0); put3(6, 1); put3(9, 0); put3(12, 2); put3(15, 1);
       const uint16_t one = 0x3f80;
       put(18, one); put(19, one); put(20, one);
+      uint16_t sc[3];
+      bf16_split(cs, 3, sc);
+      put(21, sc[0]); put(22, sc[1]); put(23, sc[2]);
     }
   });
   W[sl] = alpha_s / (float)c.M;

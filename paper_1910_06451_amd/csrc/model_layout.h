@@ -31,8 +31,8 @@ __host__ __device__ constexpr int64_t tile_floats(int Mp) { return 64 * Mp + 16 
 __host__ __device__ constexpr int64_t tile_c_offset(int Mp) { return 64 * Mp; }
 __host__ __device__ constexpr int64_t tile_w_offset(int Mp) { return 80 * Mp; }
 
-// BF16 tile: per m, an A operand of 16 supports x 32 k (bf16) = 1 KB, then the
-// FP32 C block and W are read from the fp32 tile.
+// BF16 tile: per m, an A operand of 16 supports x 32 k (bf16) = 1 KB that also
+// carries c_s (three bf16 parts); W is read from the fp32 tile.
 __host__ __device__ constexpr int64_t tile_bf16_bytes(int Mp) { return (int64_t)Mp * 16 * 32 * 2; }
 
 inline int64_t fp32_tiles_offset() { return kHeaderBytes; }

@@ -23,6 +23,8 @@ std::unordered_map<std::string, Knob>& table() {
       {"train.threads", {512, 256, 1024, true}},
       {"train.kernel", {1, 0, 1, false}},         // 1 = single-wave workgroups, 0 = multi-wave
       {"train.wave_groups", {256, 1, 512, false}},  // grid cap of the single-wave kernel
+      {"score.rational", {1, 0, 1, false}},        // 1 = running-fraction sum where the reach bound allows it
+      {"score.bf16_blocks", {4, 2, 4, true}},      // query blocks resident per pass of the BF16 score kernel
   };
   return t;
 }

@@ -11,11 +11,11 @@
 //   A[s] = (-gamma x', -gamma y', -gamma z', 1)   (prepared support operand)
 //   B[q] = (x, y, z, c_q)                        (query FK, computed here)
 //   C[s][q] = c_s                                (per-row constant)
-// Each lane then turns its 4 outputs into 1/t^2 with one reciprocal (its
-// clamp modifier saturates at 1, i.e. t >= 1, which guards against
-// cancellation) and one FMA, accumulating over m; alpha_s / M weights the sum
-// once per (s, q) and the four lane groups are reduced with shuffles at the
-// end. Points fixed to the base contribute exactly 1 per pair and arrive as
+// Each lane then sums 1/t^2 over m for its 4 (s, q) pairs, either with one
+// saturated reciprocal and one FMA per value or, where the chain's reach
+// bound allows it, as one running fraction with a single reciprocal per pair
+// (wave_score_fp32); alpha_s / M weights the sum once per (s, q) and the four
+// lane groups are reduced with shuffles at the end. Points fixed to the base contribute exactly 1 per pair and arrive as
 // the constant f_const.
 #include <cmath>
 
@@ -26,7 +26,7 @@ namespace fastron {
 // ---------------------------------------------------------------------------
 // FP32 MFMA form (default): one wave per 64 queries.
 // ---------------------------------------------------------------------------
-template <int MM, typename R>
+template <int MM, typename R, bool RAT>
 __global__ void __launch_bounds__(256) k_score_mfma(ChainArgs c, const float* __restrict__ q, int64_t N,
                                                      const char* __restrict__ blob, int64_t ntiles, int Mp,
                                                      float gamma, float* __restrict__ f,
@@ -38,120 +38,7 @@ __global__ void __launch_bounds__(256) k_score_mfma(ChainArgs c, const float* __
   __syncthreads();
   const float f_const = reinterpret_cast<const float*>(blob)[0];
   const float* tiles = reinterpret_cast<const float*>(blob + kHeaderBytes);
-  wave_score_fp32<MM, 4>(lds[wave], tiles, ntiles, Mp, f_const, qbase, N, f, label);
-}
-
-// ---------------------------------------------------------------------------
-// BF16 MFMA form: the cross term -gamma p.p' as bf16 products on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation. The support operand holds
-// -gamma p' as hi + mid + lo bf16 parts (prepare kernel); the query side
-// chooses the precision by which parts of p it pairs with them:
-//   variant 0 (plain) : hi(p).hi(p')
-//   variant 1 (split2): + mid(p).hi(p') + hi(p).mid(p')
-//   variant 2 (split3): + lo(p).hi(p') + hi(p).lo(p') + mid(p).mid(p')
-// c_q enters through three bf16 parts against unit entries (exact to FP32
-// rounding), c_s through the FP32 accumulator input.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ unsigned short bf16_rne_d(float x) {
-  uint32_t u = __float_as_uint(x);
-  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
-  return (unsigned short)(r >> 16);
-}
-__device__ __forceinline__ float bf16_f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
-
-struct Split3 {
-  unsigned short h, m, l;
-};
-__device__ __forceinline__ Split3 split3(float v) {
-  Split3 s;
-  s.h = bf16_rne_d(v);
-  float r = v - bf16_f(s.h);
-  s.m = bf16_rne_d(r);
-  r -= bf16_f(s.m);
-  s.l = bf16_rne_d(r);
-  return s;
-}
-
-// Query-side value of k slot `k` (layout mirrors the prepared support operand).
-__device__ __forceinline__ unsigned short query_slot(int k, int variant, const Split3& x, const Split3& y,
-                                                     const Split3& z, const Split3& cq) {
-  const int grp = k / 3, comp = k % 3;
-  const Split3& v = comp == 0 ? x : (comp == 1 ? y : z);
-  switch (grp) {
-    case 0: return v.h;                          // against hi(p')
-    case 1: return variant >= 1 ? v.m : 0;       // against hi(p')
-    case 2: return variant >= 1 ? v.h : 0;       // against mid(p')
-    case 3: return variant >= 2 ? v.l : 0;       // against hi(p')
-    case 4: return variant >= 2 ? v.h : 0;       // against lo(p')
-    case 5: return variant >= 2 ? v.m : 0;       // against mid(p')
-    case 6: return comp == 0 ? cq.h : (comp == 1 ? cq.m : cq.l);  // against 1
-    default: return 0;
-  }
-}
-
-template <int MM, typename R>
-__global__ void __launch_bounds__(256) k_score_bf16(ChainArgs c, const float* __restrict__ q, int64_t N,
-                                                     const char* __restrict__ blob, int64_t ntiles, int Mp,
-                                                     float gamma, int variant, float* __restrict__ f,
-                                                     int8_t* __restrict__ label) {
-  __shared__ f4 lds[kWavesPerBlock][64][MM];
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t qbase = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * 64;
-  stage_queries<MM, R>(c, q, N, gamma, qbase + lane, lds[wave]);
-  __syncthreads();
-  const int g = lane >> 4, col = lane & 15;
-  bf8 B[4][MM];
-#pragma unroll
-  for (int b = 0; b < 4; ++b)
-#pragma unroll
-    for (int m = 0; m < MM; ++m) {
-      const f4 p = lds[wave][16 * b + col][m];
-      const Split3 sx = split3(p[0]), sy = split3(p[1]), sz = split3(p[2]), sc = split3(p[3]);
-      u16x8 u;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) u[e] = query_slot(8 * g + e, variant, sx, sy, sz, sc);
-      B[b][m] = __builtin_bit_cast(bf8, u);
-    }
-
-  const float f_const = reinterpret_cast<const float*>(blob)[0];
-  const float* tiles = reinterpret_cast<const float*>(blob + kHeaderBytes);
-  const int64_t tstride = tile_floats(Mp);
-  const int64_t coff = tile_c_offset(Mp), woff = tile_w_offset(Mp);
-  const int64_t S_pad = ntiles * kTile;
-  const u16x8* A16 = reinterpret_cast<const u16x8*>(blob + kHeaderBytes + ntiles * tstride * 4 +
-                                                    S_pad * (int64_t)Mp * 16);
-  float fpart[4] = {0.f, 0.f, 0.f, 0.f};
-  for (int64_t t = 0; t < ntiles; ++t) {
-    const float* T = tiles + t * tstride;
-    bf8 Av[MM];
-#pragma unroll
-    for (int m = 0; m < MM; ++m) Av[m] = __builtin_bit_cast(bf8, A16[(t * Mp + m) * 64 + lane]);
-    f4 Cv[MM];
-#pragma unroll
-    for (int m = 0; m < MM; ++m) Cv[m] = *reinterpret_cast<const f4*>(T + coff + (g * Mp + m) * 4);
-    const f4 W = *reinterpret_cast<const f4*>(T + woff + 4 * g);
-#pragma unroll
-    for (int b = 0; b < 4; ++b) {
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
-#pragma unroll
-      for (int m = 0; m < MM; ++m) {
-        const f4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(Av[m], B[b][m], Cv[m], 0, 0, 0);
-        const float r0 = rcp_sat(d[0]), r1 = rcp_sat(d[1]), r2 = rcp_sat(d[2]), r3 = rcp_sat(d[3]);
-        a0 = fmaf(r0, r0, a0);
-        a1 = fmaf(r1, r1, a1);
-        a2 = fmaf(r2, r2, a2);
-        a3 = fmaf(r3, r3, a3);
-      }
-      fpart[b] = fmaf(W[0], a0, fmaf(W[1], a1, fmaf(W[2], a2, fmaf(W[3], a3, fpart[b]))));
-    }
-  }
-#pragma unroll
-  for (int b = 0; b < 4; ++b) {
-    float v = fpart[b];
-    v += __shfl_xor(v, 16);
-    v += __shfl_xor(v, 32);
-    if (g == 0) write_result(qbase + 16 * b + col, N, v + f_const, f, label);
-  }
+  wave_score_fp32<MM, 4, RAT, true>(lds[wave], tiles, ntiles, Mp, f_const, qbase, N, f, label);
 }
 
 // ---------------------------------------------------------------------------
@@ -205,22 +92,21 @@ __global__ void __launch_bounds__(256) k_score_const(const char* __restrict__ bl
 // Host dispatch over the number of moving points and the FK precision.
 // ---------------------------------------------------------------------------
 template <int MM, typename R>
-static void launch_one(uint32_t kind, int variant, dim3 grid, hipStream_t s, const ChainArgs& c, const float* q,
+static void launch_one(uint32_t kind, bool rat, dim3 grid, hipStream_t s, const ChainArgs& c, const float* q,
                        int64_t N, const char* blob, int64_t nt, int Mp, float gamma, float* f, int8_t* label) {
-  if (kind == FASTRON_SCORE_BF16)
-    hipLaunchKernelGGL((k_score_bf16<MM, R>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma, variant, f, label);
-  else if (kind == FASTRON_SCORE_VALU)
+  if (kind == FASTRON_SCORE_VALU)
     hipLaunchKernelGGL((k_score_valu<MM, R>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma, f, label);
+  else if (rat)
+    hipLaunchKernelGGL((k_score_mfma<MM, R, true>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma, f, label);
   else
-    hipLaunchKernelGGL((k_score_mfma<MM, R>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma, f, label);
+    hipLaunchKernelGGL((k_score_mfma<MM, R, false>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma, f, label);
 }
 
 template <typename R>
-static void launch_mm(int Mm, uint32_t kind, int variant, dim3 grid, hipStream_t s, const ChainArgs& c,
-                      const float* q, int64_t N, const char* blob, int64_t nt, int Mp, float gamma, float* f,
-                      int8_t* label) {
+static void launch_mm(int Mm, uint32_t kind, bool rat, dim3 grid, hipStream_t s, const ChainArgs& c, const float* q,
+                      int64_t N, const char* blob, int64_t nt, int Mp, float gamma, float* f, int8_t* label) {
 #define FASTRON_MM_CASE(K) \
-  case K: launch_one<K, R>(kind, variant, grid, s, c, q, N, blob, nt, Mp, gamma, f, label); break;
+  case K: launch_one<K, R>(kind, rat, grid, s, c, q, N, blob, nt, Mp, gamma, f, label); break;
   switch (Mm) {
     FASTRON_MM_CASE(1) FASTRON_MM_CASE(2) FASTRON_MM_CASE(3) FASTRON_MM_CASE(4)
     FASTRON_MM_CASE(5) FASTRON_MM_CASE(6) FASTRON_MM_CASE(7) FASTRON_MM_CASE(8)
@@ -243,10 +129,14 @@ fastron_status score_launch(const ChainArgs& c, const fastron_model* model, cons
   const char* blob = static_cast<const char*>(model->data);
   if (c.Mm == 0) {
     hipLaunchKernelGGL(k_score_const, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, blob, N, f, label);
-  } else if (c.n >= kFp64Joints) {
-    launch_mm<double>(c.Mm, kind, variant, dim3((unsigned)blocks), s, c, q, N, blob, nt, Mp, model->gamma, f, label);
   } else {
-    launch_mm<float>(c.Mm, kind, variant, dim3((unsigned)blocks), s, c, q, N, blob, nt, Mp, model->gamma, f, label);
+    const bool rat = rational_sum_ok(c, model->gamma, kind == FASTRON_SCORE_BF16 && variant == 0 ? 256.0 : 65536.0);
+    if (kind == FASTRON_SCORE_BF16)
+      launch_score_bf16(c, variant, rat, dim3((unsigned)blocks), s, q, N, blob, nt, Mp, model->gamma, f, label);
+    else if (c.n >= kFp64Joints)
+      launch_mm<double>(c.Mm, kind, rat, dim3((unsigned)blocks), s, c, q, N, blob, nt, Mp, model->gamma, f, label);
+    else
+      launch_mm<float>(c.Mm, kind, rat, dim3((unsigned)blocks), s, c, q, N, blob, nt, Mp, model->gamma, f, label);
   }
   FASTRON_HIP(hipGetLastError());
   return FASTRON_OK;
@@ -286,6 +176,20 @@ fastron_status fastron_fk_score_prepared(const fastron_chain* chain, const fastr
   if (st != FASTRON_OK) return st;
   if (N == 0) return FASTRON_OK;
   return score_launch(c, model, q, N, f, label, flags, as_stream(stream));
+}
+
+int32_t fastron_score_rational(const fastron_chain* chain, const fastron_cpoints* cp, float gamma, uint32_t flags) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(std::isfinite(gamma) && gamma > 0.f, "gamma must be finite and > 0");
+  FASTRON_CHECK((flags & ~0x33u) == 0 && (flags & 3u) != 3u, "unknown flags 0x%x", flags);
+  FASTRON_CHECK(((flags >> 4) & 3u) <= 2u, "unknown BF16 variant");
+  const uint32_t kind = flags & 3u;
+  if (kind == FASTRON_SCORE_VALU) return 0;
+  const bool plain = kind == FASTRON_SCORE_BF16 && ((flags >> 4) & 3u) == 0u;
+  return rational_sum_ok(c, gamma, plain ? 256.0 : 65536.0) ? 1 : 0;
 }
 
 fastron_status fastron_fk_score(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,

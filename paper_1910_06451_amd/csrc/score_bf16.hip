@@ -1,0 +1,158 @@
+// BF16 precision form of the fused score (Section III-B model, Section III-A
+// Eq. 4, Section II-B Eq. 3): the same kernel as the FP32 form with the cross
+// term on the BF16 matrix instructions. Launched by score_launch.
+#include "score_device.h"
+
+namespace fastron {
+
+// ---------------------------------------------------------------------------
+// BF16 MFMA form: the cross term -gamma p.p' as bf16 products on
+// v_mfma_f32_16x16x32_bf16 with FP32 accumulation. The support operand holds
+// -gamma p' as hi + mid + lo bf16 parts (prepare kernel); the query side
+// chooses the precision by which parts of p it pairs with them:
+//   variant 0 (plain) : hi(p).hi(p')
+//   variant 1 (split2): + mid(p).hi(p') + hi(p).mid(p')
+//   variant 2 (split3): + lo(p).hi(p') + hi(p).lo(p') + mid(p).mid(p')
+// c_q and c_s enter as three bf16 parts each against unit entries (exact to
+// FP32 rounding), so the accumulator input is zero and no FP32 operand block
+// has to be streamed besides the weights.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned short bf16_rne_d(float x) {
+  uint32_t u = __float_as_uint(x);
+  uint32_t r = u + 0x7fffu + ((u >> 16) & 1u);
+  return (unsigned short)(r >> 16);
+}
+__device__ __forceinline__ float bf16_f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+
+struct Split3 {
+  unsigned short h, m, l;
+};
+__device__ __forceinline__ Split3 split3(float v) {
+  Split3 s;
+  s.h = bf16_rne_d(v);
+  float r = v - bf16_f(s.h);
+  s.m = bf16_rne_d(r);
+  r -= bf16_f(s.m);
+  s.l = bf16_rne_d(r);
+  return s;
+}
+
+// Query-side value of k slot `k` (layout mirrors the prepared support operand).
+__device__ __forceinline__ unsigned short query_slot(int k, int variant, const Split3& x, const Split3& y,
+                                                     const Split3& z, const Split3& cq) {
+  const int grp = k / 3, comp = k % 3;
+  const Split3& v = comp == 0 ? x : (comp == 1 ? y : z);
+  switch (grp) {
+    case 0: return v.h;                          // against hi(p')
+    case 1: return variant >= 1 ? v.m : 0;       // against hi(p')
+    case 2: return variant >= 1 ? v.h : 0;       // against mid(p')
+    case 3: return variant >= 2 ? v.l : 0;       // against hi(p')
+    case 4: return variant >= 2 ? v.h : 0;       // against lo(p')
+    case 5: return variant >= 2 ? v.m : 0;       // against mid(p')
+    case 6: return comp == 0 ? cq.h : (comp == 1 ? cq.m : cq.l);  // against 1
+    case 7: return 0x3f80;                       // 1 against the three bf16 parts of c_s
+    default: return 0;
+  }
+}
+
+// One wave stages 64 queries and scores them in 4 / QB passes of QB query
+// blocks, so that only QB blocks' query operands (MM bf8 registers each) are
+// resident while the support tiles stream.
+template <int MM, typename R, bool RAT, int QB>
+__global__ void __launch_bounds__(256) k_score_bf16(ChainArgs c, const float* __restrict__ q, int64_t N,
+                                                     const char* __restrict__ blob, int64_t ntiles, int Mp,
+                                                     float gamma, int variant, float* __restrict__ f,
+                                                     int8_t* __restrict__ label) {
+  __shared__ f4 lds[kWavesPerBlock][64][MM];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int64_t qbase = ((int64_t)blockIdx.x * kWavesPerBlock + wave) * 64;
+  stage_queries<MM, R>(c, q, N, gamma, qbase + lane, lds[wave]);
+  __syncthreads();
+  const int g = lane >> 4, col = lane & 15;
+  const float f_const = reinterpret_cast<const float*>(blob)[0];
+  const float* tiles = reinterpret_cast<const float*>(blob + kHeaderBytes);
+  const int64_t tstride = tile_floats(Mp);
+  const int64_t woff = tile_w_offset(Mp);
+  const int64_t S_pad = ntiles * kTile;
+  const u16x8* A16 = reinterpret_cast<const u16x8*>(blob + kHeaderBytes + ntiles * tstride * 4 +
+                                                    S_pad * (int64_t)Mp * 16);
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};  // c_s arrives through the operands
+#pragma unroll 1
+  for (int h = 0; h < 4; h += QB) {
+    bf8 B[QB][MM];
+#pragma unroll
+    for (int b = 0; b < QB; ++b)
+#pragma unroll
+      for (int m = 0; m < MM; ++m) {
+        const f4 p = lds[wave][16 * (h + b) + col][m];
+        const Split3 sx = split3(p[0]), sy = split3(p[1]), sz = split3(p[2]), sc = split3(p[3]);
+        u16x8 u;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) u[e] = query_slot(8 * g + e, variant, sx, sy, sz, sc);
+        B[b][m] = __builtin_bit_cast(bf8, u);
+      }
+    float fpart[QB];
+#pragma unroll
+    for (int b = 0; b < QB; ++b) fpart[b] = 0.f;
+    for (int64_t t = 0; t < ntiles; ++t) {
+      const float* T = tiles + t * tstride;
+      bf8 Av[MM];
+#pragma unroll
+      for (int m = 0; m < MM; ++m) Av[m] = __builtin_bit_cast(bf8, A16[(t * Mp + m) * 64 + lane]);
+      const f4 W = *reinterpret_cast<const f4*>(T + woff + 4 * g);
+#pragma unroll
+      for (int b = 0; b < QB; ++b) {
+        PairSum<RAT> ps;
+#pragma unroll
+        for (int m = 0; m < MM; ++m) ps.add(m, __builtin_amdgcn_mfma_f32_16x16x32_bf16(Av[m], B[b][m], zero, 0, 0, 0));
+        fpart[b] = ps.finish(W, fpart[b]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
+      float v = fpart[b];
+      v += __shfl_xor(v, 16);
+      v += __shfl_xor(v, 32);
+      if (g == 0) write_result(qbase + 16 * (h + b) + col, N, v + f_const, f, label);
+    }
+  }
+}
+
+template <typename R>
+static void launch_bf16_mm(const ChainArgs& c, int variant, bool rat, dim3 grid, hipStream_t s, const float* q,
+                           int64_t N, const char* blob, int64_t nt, int Mp, float gamma, float* f, int8_t* label) {
+#define FASTRON_BF_CASE(K)                                                                                      \
+  case K:                                                                                                       \
+    if (rat && qb == 2)                                                                                         \
+      hipLaunchKernelGGL((k_score_bf16<K, R, true, 2>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma,    \
+                         variant, f, label);                                                                    \
+    else if (rat)                                                                                               \
+      hipLaunchKernelGGL((k_score_bf16<K, R, true, 4>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma,    \
+                         variant, f, label);                                                                    \
+    else if (qb == 2)                                                                                           \
+      hipLaunchKernelGGL((k_score_bf16<K, R, false, 2>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma,   \
+                         variant, f, label);                                                                    \
+    else                                                                                                        \
+      hipLaunchKernelGGL((k_score_bf16<K, R, false, 4>), grid, dim3(256), 0, s, c, q, N, blob, nt, Mp, gamma,   \
+                         variant, f, label);                                                                    \
+    break;
+  const int qb = (int)tune_get("score.bf16_blocks");
+  switch (c.Mm) {
+    FASTRON_BF_CASE(1) FASTRON_BF_CASE(2) FASTRON_BF_CASE(3) FASTRON_BF_CASE(4)
+    FASTRON_BF_CASE(5) FASTRON_BF_CASE(6) FASTRON_BF_CASE(7) FASTRON_BF_CASE(8)
+    FASTRON_BF_CASE(9) FASTRON_BF_CASE(10) FASTRON_BF_CASE(11) FASTRON_BF_CASE(12)
+    FASTRON_BF_CASE(13) FASTRON_BF_CASE(14) FASTRON_BF_CASE(15) FASTRON_BF_CASE(16)
+    default: break;
+  }
+#undef FASTRON_BF_CASE
+}
+
+void launch_score_bf16(const ChainArgs& c, int variant, bool rat, dim3 grid, hipStream_t s, const float* q,
+                       int64_t N, const char* blob, int64_t nt, int Mp, float gamma, float* f, int8_t* label) {
+  if (c.n >= kFp64Joints)
+    launch_bf16_mm<double>(c, variant, rat, grid, s, q, N, blob, nt, Mp, gamma, f, label);
+  else
+    launch_bf16_mm<float>(c, variant, rat, grid, s, q, N, blob, nt, Mp, gamma, f, label);
+}
+
+}  // namespace fastron

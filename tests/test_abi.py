@@ -146,3 +146,47 @@ def test_constructor_validation(lib):
         assert lib.fastron_mlp_create(d_in, hidden, rows, ctypes.byref(h)) == nat.FASTRON_EINVAL, (d_in, hidden, rows)
     assert lib.fastron_mlp_screen_workspace_bytes(-1, 7) == -1
     assert lib.fastron_mlp_param_count(None) == -1
+
+
+def test_score_form_choice(lib):
+    """Host-side choice between the running-fraction and the saturated-reciprocal sums. For the 7-DOF arm
+    (revolute, d = 0) the reach bound is R = sum_i a_i, so T = 1.01 (1 + 2 gamma R^2) can be worked out by
+    hand: the fraction is taken iff T <= 2^16 (2^8 for plain BF16) and 2 Mm log2(T) <= 120 with Mm = 7."""
+    from paper_1910_06451_amd import api
+
+    arm = wl.arm_7dof()
+    R = float(np.sum(np.hypot(arm.a, arm.d)))
+
+    def expect(gamma, t_limit):
+        T = 1.01 * (1.0 + 2.0 * gamma * R * R)
+        return T <= t_limit and 2 * 7 * np.log2(T) <= 120.0
+
+    for gamma in (0.01, 1.0, 10.0, 40.0, 100.0, 1e4):
+        assert api.score_rational(arm, gamma) == expect(gamma, 65536.0), gamma
+        assert api.score_rational(arm, gamma, api.SCORE_BF16 | api.BF16_SPLIT3) == expect(gamma, 65536.0), gamma
+        assert api.score_rational(arm, gamma, api.SCORE_BF16) == expect(gamma, 256.0), gamma
+        assert not api.score_rational(arm, gamma, api.SCORE_VALU)
+    # the cases that separate the limits
+    assert api.score_rational(arm, 10.0) and api.score_rational(arm, 10.0, api.SCORE_BF16)
+    assert api.score_rational(arm, 40.0) and not api.score_rational(arm, 40.0, api.SCORE_BF16)
+    assert not api.score_rational(arm, 100.0)
+    # a prismatic joint before a moving point: no finite reach bound
+    pr = wl.Arm(a=arm.a, alpha=arm.alpha, d=arm.d, theta=arm.theta,
+                joint_type=np.array([0, 0, 1, 0, 0, 0, 0], dtype=np.int32), frames=arm.frames)
+    assert not api.score_rational(pr, 10.0)
+    # ... but one after the last moving point does not matter
+    pr_tail = wl.Arm(a=arm.a, alpha=arm.alpha, d=arm.d, theta=arm.theta,
+                     joint_type=np.array([0, 0, 0, 0, 0, 0, 1], dtype=np.int32),
+                     frames=np.arange(7, dtype=np.int32))
+    assert api.score_rational(pr_tail, 10.0)
+    # the tuning key switches the form off
+    try:
+        api.tune_set("score.rational", 0)
+        assert not api.score_rational(arm, 10.0)
+    finally:
+        api.tune_set("score.rational", 1)
+    assert lib.fastron_score_rational(None, None, ctypes.c_float(10.0), 0) == nat.FASTRON_EINVAL
+    with pytest.raises(Exception):
+        api.score_rational(arm, -1.0)
+    with pytest.raises(Exception):
+        api.score_rational(arm, 10.0, 0x40)

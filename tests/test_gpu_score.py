@@ -5,9 +5,13 @@ Tolerance (derived from the arithmetic, per query): the kernel forms
 t = c_q + c_s - gamma p.p' in float32 from float32 control points, so each
 t carries an absolute error of at most a few units of 2^-24 times the size of
 the terms it adds, |c_q| + |c_s| + gamma |p||p'|; K_RQ = t^-2 turns an error
-dt into 2 dt / t^3, and the reciprocal adds one float32 ulp. Summed over the
-model with |alpha_s| / M weights this gives the bound used below (with a
-factor-of-8 safety margin on the unit roundoff). Queries whose oracle score
+dt into 2 dt / t^3. Turning the t of one pair into sum_m 1/t_m^2 adds a
+relative rounding error of one ulp per value (saturated reciprocal, then an
+FMA) or, in the running-fraction form (n/e with e = prod t_m^2 and all terms
+positive), at most about 3 Mm + 2 units over the pair, Mm being the number of
+moving points; the bound takes the larger. Summed over the model with
+|alpha_s| / M weights this gives the bound used below (with a factor-of-8
+safety margin on the unit roundoff). Queries whose oracle score
 is smaller than their bound are inherently ambiguous for the sign test and
 are reported, not asserted."""
 import numpy as np
@@ -34,7 +38,7 @@ def error_bound(Ps, alpha, gamma, Pq, safety=8.0):
         nq = np.linalg.norm(Pq[j], axis=1)[None, :]
         terms = 1.0 + 0.5 * gamma * (nq ** 2 + ns ** 2) + gamma * nq * ns
         dt = safety * U32 * terms
-        dk = 2.0 * dt / t ** 3 + safety * U32 / t ** 2
+        dk = 2.0 * dt / t ** 3 + safety * (3 * Ps.shape[1] + 2) * U32 / t ** 2
         out[j] = np.sum(aw[:, None] * dk)
     return out
 
@@ -77,6 +81,39 @@ def test_score_parity(oracle_mod, dev, arm_name, S, N):
     tol = error_bound(Ps, al, gamma, Pq)
     stats = check_scores(f, lab, ref, tol)
     print(stats)
+
+
+@pytest.mark.parametrize("arm_name", ["3dof", "7dof"])
+def test_rational_and_saturated_sums(oracle_mod, dev, arm_name):
+    """Both ways of summing 1/t^2 over a pair's control points (running fraction with one reciprocal per
+    pair; saturated reciprocal per value) meet the bound against the oracle on the same inputs, single-model
+    and batched, and agree with each other to within the bound."""
+    arm = wl.arm_3dof() if arm_name == "3dof" else wl.arm_7dof()
+    gamma, S, N = 10.0, 517, 1999
+    sq, al, q = _case(arm, S, N, gamma, f"rat_{arm_name}")
+    sq_d, al_d, q_d = (torch.from_numpy(x).to(dev) for x in (sq, al, q))
+    dh = oracle_dh(oracle_mod, arm)
+    ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64))
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64))
+    tol = error_bound(Ps, al, gamma, Pq)
+    model = api.support_prep(arm, sq_d, al_d, gamma)
+    out = {}
+    try:
+        for rat in (1, 0):
+            api.tune_set("score.rational", rat)
+            announce(f"fk_score {arm_name} score.rational={rat}")
+            f, lab = api.fk_score_prepared(arm, model, q_d)
+            out[rat] = f.cpu().numpy()
+            print(rat, check_scores(out[rat], lab.cpu().numpy(), ref, tol))
+            b = api.Batch(arm, [S], [N], gamma)
+            b.prepare(sq_d, al_d)
+            fb, lb = b.score(q_d)
+            assert np.all(np.abs(fb.cpu().numpy().astype(np.float64) - out[rat]) <= tol)
+            check_scores(fb.cpu().numpy(), lb.cpu().numpy(), ref, tol)
+    finally:
+        api.tune_set("score.rational", 1)
+    assert np.all(np.abs(out[1].astype(np.float64) - out[0]) <= tol)
 
 
 def test_score_full_size_sampled(oracle_mod, dev):
