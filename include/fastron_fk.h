@@ -290,13 +290,15 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *   "train.wave_groups" grid cap of the single-wave kernel, 1..512 (256)
  *   "train.blocks"      workgroups of the multi-wave grid, 0 = automatic
  *   "train.threads"     threads per multi-wave workgroup: 256, 512 or 1024
- *   "score.rational"    1 (default): the FP32 scoring kernels sum a pair's
- *                       1/t^2 terms as one running fraction (one reciprocal
- *                       per pair) when a bound on the chain's reach keeps the
- *                       fraction in range (revolute joints up to the last
- *                       moving point, T = 1.01 (1 + 2 gamma R^2) <= 2^16 and
- *                       T^(2 Mm) <= 2^120); 0: one saturated reciprocal per
- *                       value always. The two agree to FP32 rounding.
+ *   "score.rational"    1 (default): the MFMA scoring kernels (FP32, BF16,
+ *                       batched) sum a pair's 1/t^2 terms as one running
+ *                       fraction (one reciprocal per pair) when a bound on
+ *                       the chain's reach keeps the fraction in range (see
+ *                       fastron_score_rational); 0: one saturated reciprocal
+ *                       per value always. The two agree to FP32 rounding.
+ *   "score.bf16_blocks" query blocks of 16 whose BF16 operands the BF16 score
+ *                       kernel keeps resident per pass: 4 (default) or 2
+ *                       (fewer registers, more waves; same results)
  * Keys take effect at the next launch (a captured batch graph keeps the
  * kernel it was captured with). fastron_tune_get returns -1 for an unknown
  * key.                                                                      */

@@ -200,9 +200,12 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
     if (V) {
       V[m * 4 + 0] = 0.f; V[m * 4 + 1] = 0.f; V[m * 4 + 2] = 0.f; V[m * 4 + 3] = 0.f;
     }
-    // bf16 A operand: row sl, k = 0..31, stored as [g][s][8] per m
+    // bf16 A operand: row sl, k = 0..31, stored as [g][s][8] per m; the unit
+    // entries k18-20 (against the parts of c_q) are set for padding too, so
+    // that a padded row's t is c_q >= 1 as in the FP32 layout, never 0
     if (B16)
-      for (int k = 0; k < 32; ++k) B16[(int64_t)m * 512 + ((k >> 3) * 16 + sl) * 8 + (k & 7)] = 0;
+      for (int k = 0; k < 32; ++k)
+        B16[(int64_t)m * 512 + ((k >> 3) * 16 + sl) * 8 + (k & 7)] = (k >= 18 && k <= 20) ? 0x3f80 : 0;
   }
   W[sl] = 0.f;
   if (!sq_row) return;

@@ -161,16 +161,23 @@ def test_prepared_matches_convenience_and_valu(oracle_mod, dev):
     assert torch.equal(lab_only, l1)
 
 
+@pytest.mark.parametrize("rational", [1, 0])
 @pytest.mark.parametrize("variant", [api.BF16_PLAIN, api.BF16_SPLIT2, api.BF16_SPLIT3])
-def test_bf16_forms(oracle_mod, dev, variant):
-    """Precision form: BF16 cross term with FP32 norms / accumulation. split3 must meet the FP32 bound;
-    the cheaper variants are measured against the oracle and must stay finite and ordered by accuracy."""
+def test_bf16_forms(oracle_mod, dev, variant, rational):
+    """Precision form: BF16 cross term with FP32 norms / accumulation, with either summation of a pair's
+    K_RQ terms. split3 must meet the FP32 bound; the cheaper variants are measured against the oracle and
+    must stay finite and ordered by accuracy."""
     arm = wl.arm_7dof()
     gamma = 10.0
-    sq, al, q = _case(arm, 2048, 2000, gamma, "bf16_forms")
-    announce(f"bf16 variant {variant}")
+    sq, al, q = _case(arm, 2043, 2000, gamma, "bf16_forms")  # ragged: the last tile has padded rows
+    announce(f"bf16 variant {variant} score.rational={rational}")
     model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma)
-    f, lab = api.fk_score_prepared(arm, model, torch.from_numpy(q).to(dev), flags=api.SCORE_BF16 | variant)
+    assert api.score_rational(arm, gamma, api.SCORE_BF16 | variant)  # the bound admits the fraction here
+    try:
+        api.tune_set("score.rational", rational)
+        f, lab = api.fk_score_prepared(arm, model, torch.from_numpy(q).to(dev), flags=api.SCORE_BF16 | variant)
+    finally:
+        api.tune_set("score.rational", 1)
     f, lab = f.cpu().numpy(), lab.cpu().numpy()
     dh = oracle_dh(oracle_mod, arm)
     ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64))
@@ -187,6 +194,25 @@ def test_bf16_forms(oracle_mod, dev, variant):
         assert err.max() < 0.05 and agree > 0.99
     else:
         assert agree > 0.8
+
+
+def test_bf16_resident_blocks_setting(dev):
+    """The BF16 kernel's query blocks per pass (score.bf16_blocks = 2 or 4) changes only which operands are
+    resident, not any query's arithmetic: results are bit-identical, including a ragged last workgroup."""
+    arm = wl.arm_7dof()
+    gamma = 10.0
+    sq, al, q = _case(arm, 333, 1234, gamma, "bf16_blocks")
+    model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma)
+    q_d = torch.from_numpy(q).to(dev)
+    out = {}
+    try:
+        for qb in (4, 2):
+            api.tune_set("score.bf16_blocks", qb)
+            announce(f"bf16 split3 score.bf16_blocks={qb}")
+            out[qb] = api.fk_score_prepared(arm, model, q_d, flags=api.SCORE_BF16 | api.BF16_SPLIT3)
+    finally:
+        api.tune_set("score.bf16_blocks", 4)
+    assert torch.equal(out[2][0], out[4][0]) and torch.equal(out[2][1], out[4][1])
 
 
 def test_score_edge_cases(oracle_mod, dev):
