@@ -179,6 +179,30 @@ def test_score_form_choice(lib):
                      joint_type=np.array([0, 0, 0, 0, 0, 0, 1], dtype=np.int32),
                      frames=np.arange(7, dtype=np.int32))
     assert api.score_rational(pr_tail, 10.0)
+    # a base transform adds its translation to the reach and scales it by the norm of its matrix (a
+    # rotation: exactly 1): with R = |p_base| + s sum_i a_i, gamma = 28 separates the cases
+    import types
+
+    def with_base(Bm, p):
+        T4 = np.eye(4)
+        T4[:3, :3], T4[:3, 3] = Bm, p
+        return types.SimpleNamespace(a=arm.a, alpha=arm.alpha, d=arm.d, theta=arm.theta, joint_type=arm.joint_type,
+                                     frames=arm.frames, offsets=None, base=T4)
+
+    def t_ok(Rr, gamma):
+        T = 1.01 * (1.0 + 2.0 * gamma * Rr * Rr)
+        return T <= 65536.0 and 14 * np.log2(T) <= 120.0
+
+    cz, sz, cx, sx = np.cos(0.7), np.sin(0.7), np.cos(0.3), np.sin(0.3)
+    rot = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]]) @ np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    p = np.array([0.3, -0.2, 0.5])
+    assert t_ok(R, 28.0) and not t_ok(np.linalg.norm(p) + R, 28.0) and t_ok(np.linalg.norm(p) + R, 25.0)
+    assert api.score_rational(arm, 28.0)
+    assert not api.score_rational(with_base(rot, p), 28.0)
+    assert api.score_rational(with_base(rot, p), 25.0)
+    assert api.score_rational(with_base(rot, np.zeros(3)), 28.0)  # a pure rotation leaves the bound alone
+    assert not t_ok(np.linalg.norm(p) + 2 * R, 10.0)
+    assert not api.score_rational(with_base(2 * np.eye(3), p), 10.0)  # a scaling base matrix counts
     # the tuning key switches the form off
     try:
         api.tune_set("score.rational", 0)
