@@ -19,6 +19,9 @@ for Improved Proxy Collision Checking"):
 * ``control_point_frames`` -- Section III-A, placement of control points at frame origins
 * ``k_rq``             -- Section II-B, Eq. 3 (second-order rational quadratic)
 * ``k_fk``, ``gram``   -- Section III-A, Eq. 4 (FK kernel) and the kernel matrix
+* ``k_pts``            -- Eq. 4 on M points of D coordinates; M = 1 on the joint
+  vector (D = n) is Eq. 3 on configurations, the baseline of Section IV
+* ``rbf_score``        -- Section III-B model with that configuration-space kernel
 * ``score``            -- Section III-B, model f(x) = sum_i K(S_i, x) alpha_i
 * ``fastron_update``   -- Section III-B, Eq. 5-9 and Algorithm 1
 * ``loss``             -- Section III-B, Eq. 5
@@ -76,6 +79,17 @@ def _load():
     lib.oracle_score_points.argtypes = [ctypes.c_int, i64, dp, dp, ctypes.c_double, i64, dp, dp]
     lib.oracle_score.argtypes = [ctypes.c_int, dp, dp, ctypes.c_int, ip, dp, i64, dp, dp, ctypes.c_double,
                                  i64, dp, dp]
+    lib.oracle_k_pts.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double]
+    lib.oracle_k_pts.restype = ctypes.c_double
+    lib.oracle_gram_pts.argtypes = [i64, ctypes.c_int, ctypes.c_int, dp, ctypes.c_double, dp]
+    lib.oracle_score_pts.argtypes = [ctypes.c_int, ctypes.c_int, i64, dp, dp, ctypes.c_double, i64, dp, dp]
+    lib.oracle_loss_pts.argtypes = [i64, ctypes.c_int, ctypes.c_int, dp, ip, ctypes.c_double, ctypes.c_double, dp]
+    lib.oracle_loss_pts.restype = ctypes.c_double
+    lib.oracle_fastron_update_pts.argtypes = [i64, ctypes.c_int, ctypes.c_int, dp, ip, ctypes.c_double,
+                                              ctypes.c_double, i64, i64, dp, dp, ctypes.POINTER(ctypes.c_int64),
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), i64,
+                                              ip, ctypes.POINTER(ctypes.c_int64), dp]
+    lib.oracle_fastron_update_pts.restype = ctypes.c_int
     lib.oracle_loss.argtypes = [i64, ctypes.c_int, dp, ip, ctypes.c_double, ctypes.c_double, dp]
     lib.oracle_loss.restype = ctypes.c_double
     lib.oracle_fastron_update.argtypes = [i64, ctypes.c_int, dp, ip, ctypes.c_double, ctypes.c_double, i64, i64,
@@ -186,11 +200,19 @@ def k_fk(Px, Pxp, gamma) -> float:
     return float(_load().oracle_k_fk(Px.shape[0], _ptr(Px), _ptr(Pxp), float(gamma)))
 
 
+def k_pts(Px, Pxp, gamma) -> float:
+    """Section III-A Eq. 4 on M points of D coordinates, (M, D) arrays: D = 3 with control points is K_FK;
+    M = 1 with the joint vector (D = n) is the rational quadratic kernel on configurations."""
+    Px, Pxp = _d(Px), _d(Pxp)
+    return float(_load().oracle_k_pts(Px.shape[0], Px.shape[1], _ptr(Px), _ptr(Pxp), float(gamma)))
+
+
 def gram(P, gamma) -> np.ndarray:
+    """Kernel matrix over N points sets P (N, M, D); D = 3 is the FK kernel."""
     P = _d(P)
-    N, M = P.shape[0], P.shape[1]
+    N, M, D = P.shape
     K = np.zeros((N, N))
-    _load().oracle_gram(N, M, _ptr(P), float(gamma), _ptr(K))
+    _load().oracle_gram_pts(N, M, D, _ptr(P), float(gamma), _ptr(K))
     return K
 
 
@@ -203,12 +225,19 @@ def gram_summand(P, gamma, m) -> np.ndarray:
 
 
 def score_points(Ps, alpha, gamma, Pq) -> np.ndarray:
+    """f(q) = sum_s alpha_s K(S_s, q) on point sets Ps (S, M, D) and Pq (N, M, D)."""
     Ps, Pq, alpha = _d(Ps), _d(Pq), _d(alpha)
-    S, M = Ps.shape[0], Ps.shape[1]
+    S, M, D = Ps.shape
     N = Pq.shape[0]
     f = np.zeros(N)
-    _load().oracle_score_points(M, S, _ptr(Ps), _ptr(alpha), float(gamma), N, _ptr(Pq), _ptr(f))
+    _load().oracle_score_pts(M, D, S, _ptr(Ps), _ptr(alpha), float(gamma), N, _ptr(Pq), _ptr(f))
     return f
+
+
+def rbf_score(support_x, alpha, gamma, x) -> np.ndarray:
+    """The baseline model on configurations: f(x) = sum_s alpha_s K_RQ(x_s, x) (Eq. 3 on joint vectors)."""
+    sx, x = _d(support_x), _d(x)
+    return score_points(sx.reshape(sx.shape[0], 1, -1), alpha, gamma, x.reshape(x.shape[0], 1, -1))
 
 
 def score(dh, frame, support_q, alpha, gamma, q, offset=None, base=None) -> np.ndarray:
@@ -235,8 +264,8 @@ def loss(P, y, gamma, beta, alpha) -> float:
     P = _d(P)
     y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
     alpha = _d(alpha)
-    return float(_load().oracle_loss(P.shape[0], P.shape[1], _ptr(P), _ptr(y, ctypes.c_int), float(gamma),
-                                     float(beta), _ptr(alpha)))
+    return float(_load().oracle_loss_pts(P.shape[0], P.shape[1], P.shape[2], _ptr(P), _ptr(y, ctypes.c_int),
+                                         float(gamma), float(beta), _ptr(alpha)))
 
 
 ACT_ADD = 1
@@ -244,13 +273,14 @@ ACT_REMOVE = 2
 
 
 def fastron_update(P, y, gamma, beta=1.0, iter_max=None, s_max=None, alpha=None, F=None, trace=False):
-    """Algorithm 1 on the control points P (N, M, 3) and labels y (+1 / -1).
+    """Algorithm 1 on the point sets P (N, M, D) -- control points (D = 3) for the FK kernel, or the joint
+    vectors as (N, 1, n) for the kernel on configurations -- and labels y (+1 / -1).
 
     Returns a dict with alpha, F (N,), support (ascending indices), converged,
     updates and, with ``trace=True``, per-update (action, index, dalpha).
     """
     P = _d(P)
-    N, M = P.shape[0], P.shape[1]
+    N, M, D = P.shape
     y = np.ascontiguousarray(np.asarray(y, dtype=np.int32))
     if iter_max is None:
         iter_max = 20 * max(N, 1)
@@ -266,7 +296,7 @@ def fastron_update(P, y, gamma, beta=1.0, iter_max=None, s_max=None, alpha=None,
     t_act = np.zeros(max(cap, 1), dtype=np.int32)
     t_idx = np.zeros(max(cap, 1), dtype=np.int64)
     t_da = np.zeros(max(cap, 1))
-    rc = _load().oracle_fastron_update(N, M, _ptr(P), _ptr(y, ctypes.c_int), float(gamma), float(beta),
+    rc = _load().oracle_fastron_update_pts(N, M, D, _ptr(P), _ptr(y, ctypes.c_int), float(gamma), float(beta),
                                        int(iter_max), int(s_max), _ptr(alpha), _ptr(F),
                                        ctypes.byref(upd), _ptr(support, ctypes.c_int64), ctypes.byref(ns), cap,
                                        _ptr(t_act, ctypes.c_int), _ptr(t_idx, ctypes.c_int64), _ptr(t_da))

@@ -133,22 +133,31 @@ double oracle_k_rq(const double* x, const double* xp, int dim, double gamma) {
   return 1.0 / (base * base);
 }
 
-/* Section III-A, Eq. 4: K_FK(x, x') = (1/M) sum_m K_RQ(FK_m(x), FK_m(x')),
- * given the two M x 3 control-point sets.                                    */
-double oracle_k_fk(int M, const double* Px, const double* Pxp, double gamma) {
+/* Section III-A, Eq. 4: K(x, x') = (1/M) sum_m K_RQ(p_m(x), p_m(x')) over M
+ * points of D coordinates each. D = 3 with the control points FK_m is the FK
+ * kernel; M = 1 with the joint vector itself (D = n) is the rational
+ * quadratic kernel on configurations, the baseline the paper compares with
+ * (Section II-B, Eq. 3).                                                     */
+double oracle_k_pts(int M, int D, const double* Px, const double* Pxp, double gamma) {
   double s = 0.0;
-  for (int m = 0; m < M; ++m) s += oracle_k_rq(Px + 3 * m, Pxp + 3 * m, 3, gamma);
+  for (int m = 0; m < M; ++m) s += oracle_k_rq(Px + (size_t)D * m, Pxp + (size_t)D * m, D, gamma);
   return s / (double)M;
+}
+
+/* The FK kernel of Eq. 4 on two M x 3 control-point sets. */
+double oracle_k_fk(int M, const double* Px, const double* Pxp, double gamma) {
+  return oracle_k_pts(M, 3, Px, Pxp, gamma);
 }
 
 /* Kernel matrix K_ij = K_FK(X_i, X_j) over N configurations given as control
  * points (Section II-B, kernel matrix definition). K is N x N row-major.      */
-void oracle_gram(int64_t N, int M, const double* P, double gamma, double* K) {
+void oracle_gram_pts(int64_t N, int M, int D, const double* P, double gamma, double* K) {
+  const size_t w = (size_t)D * M;
 #pragma omp parallel for schedule(static)
   for (int64_t i = 0; i < N; ++i)
-    for (int64_t j = 0; j < N; ++j)
-      K[i * N + j] = oracle_k_fk(M, P + (size_t)3 * M * i, P + (size_t)3 * M * j, gamma);
+    for (int64_t j = 0; j < N; ++j) K[i * N + j] = oracle_k_pts(M, D, P + w * i, P + w * j, gamma);
 }
+void oracle_gram(int64_t N, int M, const double* P, double gamma, double* K) { oracle_gram_pts(N, M, 3, P, gamma, K); }
 
 /* Summand matrix K_m (the RQ matrix of control point m alone), Section III-A. */
 void oracle_gram_summand(int64_t N, int M, const double* P, double gamma, int m, double* K) {
@@ -160,15 +169,19 @@ void oracle_gram_summand(int64_t N, int M, const double* P, double gamma, int m,
 /* Section III-B: Fastron model f(x) = sum_i K(S_i, x) alpha_i over the support
  * set, summed in support-index order. Support and query control points are
  * given (S x M x 3 and N x M x 3).                                           */
-void oracle_score_points(int M, int64_t S, const double* Ps, const double* alpha, double gamma,
-                         int64_t N, const double* Pq, double* f) {
+void oracle_score_pts(int M, int D, int64_t S, const double* Ps, const double* alpha, double gamma,
+                      int64_t N, const double* Pq, double* f) {
+  const size_t w = (size_t)D * M;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t j = 0; j < N; ++j) {
     double acc = 0.0;
-    for (int64_t i = 0; i < S; ++i)
-      acc += oracle_k_fk(M, Ps + (size_t)3 * M * i, Pq + (size_t)3 * M * j, gamma) * alpha[i];
+    for (int64_t i = 0; i < S; ++i) acc += oracle_k_pts(M, D, Ps + w * i, Pq + w * j, gamma) * alpha[i];
     f[j] = acc;
   }
+}
+void oracle_score_points(int M, int64_t S, const double* Ps, const double* alpha, double gamma,
+                         int64_t N, const double* Pq, double* f) {
+  oracle_score_pts(M, 3, S, Ps, alpha, gamma, N, Pq, f);
 }
 
 /* Score from joint configurations: FK of supports and queries (Eq. 2), then
@@ -192,26 +205,31 @@ void oracle_score(int n, const double* dh, const double* base, int M, const int*
 
 /* Section III-B, Eq. 5: L(alpha) = 1/2 alpha^T K alpha - y^T B alpha with
  * b_i = beta^(0.5 (y_i + 1)). Used only by invariant tests.                  */
-double oracle_loss(int64_t N, int M, const double* P, const int* y, double gamma, double beta,
-                   const double* alpha) {
+double oracle_loss_pts(int64_t N, int M, int D, const double* P, const int* y, double gamma, double beta,
+                       const double* alpha) {
+  const size_t w = (size_t)D * M;
   double quad = 0.0, lin = 0.0;
   for (int64_t i = 0; i < N; ++i) {
     if (alpha[i] == 0.0) continue;
     for (int64_t j = 0; j < N; ++j) {
       if (alpha[j] == 0.0) continue;
-      quad += alpha[i] * oracle_k_fk(M, P + (size_t)3 * M * i, P + (size_t)3 * M * j, gamma) * alpha[j];
+      quad += alpha[i] * oracle_k_pts(M, D, P + w * i, P + w * j, gamma) * alpha[j];
     }
     lin += (double)y[i] * pow(beta, 0.5 * (y[i] + 1)) * alpha[i];
   }
   return 0.5 * quad - lin;
 }
+double oracle_loss(int64_t N, int M, const double* P, const int* y, double gamma, double beta,
+                   const double* alpha) {
+  return oracle_loss_pts(N, M, 3, P, y, gamma, beta, alpha);
+}
 
 /* computeKernelMatrixColumn(i) of Algorithm 1: column i of K, evaluated on
  * demand (the lazy evaluation described in Section III-B).                  */
-static void kernel_column(int64_t N, int M, const double* P, double gamma, int64_t i, double* col) {
+static void kernel_column(int64_t N, int M, int D, const double* P, double gamma, int64_t i, double* col) {
+  const size_t w = (size_t)D * M;
 #pragma omp parallel for schedule(static)
-  for (int64_t j = 0; j < N; ++j)
-    col[j] = oracle_k_fk(M, P + (size_t)3 * M * j, P + (size_t)3 * M * i, gamma);
+  for (int64_t j = 0; j < N; ++j) col[j] = oracle_k_pts(M, D, P + w * j, P + w * i, gamma);
 }
 
 /* Trace action codes for oracle_fastron_update.                            */
@@ -242,10 +260,10 @@ static void kernel_column(int64_t N, int M, const double* P, double gamma, int64
  * add/remove updates performed. Optional trace arrays (capacity trace_cap)
  * receive, per update, the action (1 add, 2 remove), the index and the weight
  * change applied to alpha_i.                                                */
-int oracle_fastron_update(int64_t N, int M, const double* P, const int* y, double gamma, double beta,
-                          int64_t iter_max, int64_t s_max, double* alpha, double* F, int64_t* updates,
-                          int64_t* support_idx, int64_t* n_support, int64_t trace_cap, int* trace_act,
-                          int64_t* trace_idx, double* trace_dalpha) {
+int oracle_fastron_update_pts(int64_t N, int M, int D, const double* P, const int* y, double gamma, double beta,
+                              int64_t iter_max, int64_t s_max, double* alpha, double* F, int64_t* updates,
+                              int64_t* support_idx, int64_t* n_support, int64_t trace_cap, int* trace_act,
+                              int64_t* trace_idx, double* trace_dalpha) {
   double* col = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
   int64_t count = 0;
   for (int64_t j = 0; j < N; ++j) count += (alpha[j] != 0.0);
@@ -261,7 +279,7 @@ int oracle_fastron_update(int64_t N, int M, const double* P, const int* y, doubl
     }
     if (imin >= 0 && mmin <= 0.0) {
       int64_t i = imin;
-      kernel_column(N, M, P, gamma, i, col);
+      kernel_column(N, M, D, P, gamma, i, col);
       if (count < s_max || alpha[i] != 0.0) {
         double b = pow(beta, 0.5 * (y[i] + 1));
         double dalpha = b * (double)y[i] - F[i];
@@ -284,7 +302,7 @@ int oracle_fastron_update(int64_t N, int M, const double* P, const int* y, doubl
     }
     if (imax >= 0 && vmax > 0.0) {
       int64_t i = imax;
-      kernel_column(N, M, P, gamma, i, col);
+      kernel_column(N, M, D, P, gamma, i, col);
       double a_i = alpha[i];
       for (int64_t j = 0; j < N; ++j) F[j] -= a_i * col[j];
       alpha[i] = 0.0;
@@ -307,6 +325,14 @@ int oracle_fastron_update(int64_t N, int M, const double* P, const int* y, doubl
   if (updates) *updates = nupd;
   free(col);
   return converged ? 0 : 1;
+}
+
+int oracle_fastron_update(int64_t N, int M, const double* P, const int* y, double gamma, double beta,
+                          int64_t iter_max, int64_t s_max, double* alpha, double* F, int64_t* updates,
+                          int64_t* support_idx, int64_t* n_support, int64_t trace_cap, int* trace_act,
+                          int64_t* trace_idx, double* trace_dalpha) {
+  return oracle_fastron_update_pts(N, M, 3, P, y, gamma, beta, iter_max, s_max, alpha, F, updates, support_idx,
+                                   n_support, trace_cap, trace_act, trace_idx, trace_dalpha);
 }
 
 /* ------------------------------------------------------------------------- */

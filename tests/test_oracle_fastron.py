@@ -142,3 +142,17 @@ def test_warm_start_continues(oracle_mod):
     rest = oracle_mod.fastron_update(P, y, gamma, alpha=part["alpha"], F=part["F"])
     np.testing.assert_allclose(rest["alpha"], full["alpha"], atol=1e-12)
     np.testing.assert_array_equal(rest["support"], full["support"])
+
+
+def test_configuration_kernel_training_claim2(oracle_mod):
+    """Algorithm 1 with the kernel on configurations (M = 1, D = n): at convergence every margin is positive
+    (Claim 2), F equals K alpha with that kernel, and the support set is exactly the nonzero weights."""
+    g = np.random.default_rng(3)
+    X = g.uniform(-np.pi, np.pi, (300, 7))
+    y = np.where(np.sin(X[:, 0]) + 0.5 * np.cos(X[:, 1] + X[:, 2]) > 0.2, 1, -1)
+    out = oracle_mod.fastron_update(X[:, None, :], y, 0.5, beta=1.0)
+    assert out["converged"]
+    K = oracle_mod.gram(X[:, None, :], 0.5)
+    np.testing.assert_allclose(out["F"], K @ out["alpha"], rtol=0, atol=1e-9)
+    assert np.all(y * out["F"] > 0)
+    np.testing.assert_array_equal(out["support"], np.flatnonzero(out["alpha"]))

@@ -101,3 +101,39 @@ def test_score_matches_points_path(oracle_mod):
 
 def test_predict_sign_rule(oracle_mod):
     np.testing.assert_array_equal(oracle_mod.predict([-1e-30, 0.0, 2.0]), [-1, 1, 1])
+
+
+def test_points_kernel_on_configurations(oracle_mod):
+    """Eq. 4 generalised to M points of D coordinates, used with M = 1 and the joint vector (D = n) for the
+    kernel on configurations. Pinned by properties a dropped coordinate, a wrong index or a misplaced gamma
+    would break: rigid motions and coordinate permutations of both vectors leave it unchanged, zero
+    coordinates past the third reduce it to the 3-D control-point kernel, (x, gamma) -> (c x, gamma / c^2)
+    leaves it unchanged, and its Gram matrix has a unit diagonal and is positive definite."""
+    g = np.random.default_rng(5)
+    x, xp = g.uniform(-np.pi, np.pi, 7), g.uniform(-np.pi, np.pi, 7)
+    k = oracle_mod.k_pts(x[None], xp[None], 0.7)
+    d2 = float(np.sum((x - xp) ** 2))
+    assert abs(k - oracle_mod.k_rq(np.zeros(1), np.array([np.sqrt(d2)]), 0.7)) < 1e-15  # depends on |x - x'| only
+    Q, _ = np.linalg.qr(g.standard_normal((7, 7)))
+    b = g.standard_normal(7)
+    assert abs(oracle_mod.k_pts((Q @ x + b)[None], (Q @ xp + b)[None], 0.7) - k) < 1e-13
+    perm = g.permutation(7)
+    assert abs(oracle_mod.k_pts(x[perm][None], xp[perm][None], 0.7) - k) < 1e-15
+    assert abs(oracle_mod.k_pts(3.0 * x[None], 3.0 * xp[None], 0.7 / 9.0) - k) < 1e-14
+    # zero padding: a D = 7 point with coordinates 3..6 equal is the 3-D kernel of its first three
+    x3, xp3 = x.copy(), xp.copy()
+    x3[3:] = xp3[3:] = 0.25
+    assert abs(oracle_mod.k_pts(x3[None], xp3[None], 0.7) - oracle_mod.k_fk(x3[None, :3], xp3[None, :3], 0.7)) < 1e-16
+    # M points of D coordinates average the per-point kernels (Eq. 4's 1/M)
+    P1, P2 = g.standard_normal((3, 5)), g.standard_normal((3, 5))
+    avg = np.mean([oracle_mod.k_pts(P1[m][None], P2[m][None], 0.7) for m in range(3)])
+    assert abs(oracle_mod.k_pts(P1, P2, 0.7) - avg) < 1e-16
+    X = g.uniform(-np.pi, np.pi, (40, 1, 7))
+    K = oracle_mod.gram(X, 0.5)
+    np.testing.assert_array_equal(K, K.T)
+    np.testing.assert_array_equal(np.diag(K), 1.0)
+    np.linalg.cholesky(K)
+    # the model sum over supports
+    alpha = g.standard_normal(40)
+    f = oracle_mod.rbf_score(X[:, 0], alpha, 0.5, X[:5, 0])
+    np.testing.assert_allclose(f, K[:5] @ alpha, rtol=0, atol=1e-13)
