@@ -270,6 +270,33 @@ fastron_status fastron_mlp_screen(fastron_mlp* net, const fastron_chain* chain, 
                                   int64_t workspace_bytes, void* stream);
 int64_t fastron_mlp_screen_workspace_bytes(int64_t N, int32_t n_joints);
 
+/* ---- the kernel on configurations (the paper's comparison, Section IV) ----
+ * Fastron with the rational quadratic kernel of Section II-B, Eq. 3 applied
+ * to the joint vectors themselves, K(x, x') = (1 + gamma/2 ||x - x'||^2)^-2:
+ * the baseline whose support sets, accuracy and query times the paper
+ * compares the FK kernel with. Same conventions as the FK entry points;
+ * n in [1, 16] joint coordinates per configuration.
+ *
+ * fastron_rbf_score: f[j] = sum_s alpha_s K(support_x_s, q_j) and its sign
+ * (label +1 for f >= 0). support_x [S][n], alpha [S], q [N][n] float; f and/or
+ * label may be NULL (not both). S == 0 gives f = 0. The support set is
+ * prepared into stream-ordered scratch memory on every call.              */
+fastron_status fastron_rbf_score(const float* support_x, const float* alpha, int64_t S, int32_t n, float gamma,
+                                 const float* q, int64_t N, float* f, int8_t* label, void* stream);
+
+/* fastron_rbf_train / _f64: Algorithm 1 (Section III-B) with that kernel on
+ * X [N][n] float (device) and labels y [N] int8; arguments, outputs, warm
+ * start, caps and status as for fastron_train / fastron_train_f64 with the
+ * configurations in place of the control points. The FP64 form follows the
+ * FP64 oracle step for step (trace arrays as in fastron_train_f64).        */
+fastron_status fastron_rbf_train(const float* X, const int8_t* y, int64_t N, int32_t n, float gamma, float beta,
+                                 int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
+                                 int64_t* n_support, int64_t* updates, void* stream);
+fastron_status fastron_rbf_train_f64(const float* X, const int8_t* y, int64_t N, int32_t n, double gamma,
+                                     double beta, int64_t iter_max, int64_t s_max, double* alpha, double* F,
+                                     int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                                     int32_t* trace_action, int32_t* trace_index, int64_t trace_cap, void* stream);
+
 /* ---- a9: geometric labels -------------------------------------------------
  * Stands in for the ground-truth collision checker of Section IV: link i is a
  * capsule of radius `radius` around the segment between the origins of

@@ -38,7 +38,8 @@ EXPORTED = [
     "fastron_batch_replay", "fastron_batch_tile_queries", "fastron_batch_destroy", "fastron_mlp_create",
     "fastron_mlp_destroy", "fastron_mlp_param_count", "fastron_mlp_set_params", "fastron_mlp_get_params",
     "fastron_mlp_fit_standardisation", "fastron_mlp_forward", "fastron_mlp_gradients", "fastron_mlp_train_epoch",
-    "fastron_mlp_screen", "fastron_mlp_screen_workspace_bytes",
+    "fastron_mlp_screen", "fastron_mlp_screen_workspace_bytes", "fastron_rbf_score", "fastron_rbf_train",
+    "fastron_rbf_train_f64",
 ]
 
 
@@ -117,6 +118,10 @@ def lib():
         "fastron_mlp_train_epoch": ([vp, vp, vp, vp, i64, i64, f32, ctypes.POINTER(ctypes.c_float), vp], i32),
         "fastron_mlp_screen": ([vp, ch, cp, md, vp, i64, f32, vp, vp, vp, pi64, vp, i64, vp], i32),
         "fastron_mlp_screen_workspace_bytes": ([i64, i32], i64),
+        "fastron_rbf_score": ([vp, vp, i64, i32, f32, vp, i64, vp, vp, vp], i32),
+        "fastron_rbf_train": ([vp, vp, i64, i32, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp], i32),
+        "fastron_rbf_train_f64": ([vp, vp, i64, i32, f64, f64, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp],
+                                  i32),
         "fastron_tune_set": ([ctypes.c_char_p, i64], i32),
         "fastron_tune_get": ([ctypes.c_char_p], i64),
         "fastron_last_error": ([], ctypes.c_char_p),

@@ -16,6 +16,7 @@ from ._native import HostChain, check
 
 __all__ = [
     "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train", "train_batch",
+    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
@@ -203,6 +204,61 @@ def train(P: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, ite
     check(st, allow=(nat.FASTRON_OK, nat.FASTRON_NOT_CONVERGED))
     out = dict(alpha=alpha, F=F, support=support[: ns.value], converged=(st == nat.FASTRON_OK), updates=upd.value)
     if trace_cap:
+        k = min(upd.value, trace_cap)
+        out["trace_action"] = tr_a[:k]
+        out["trace_index"] = tr_i[:k]
+    return out
+
+
+def rbf_score(support_x: torch.Tensor, alpha: torch.Tensor, gamma: float, q: torch.Tensor, want_f=True,
+              want_label=True, out=None):
+    """The model with the kernel on configurations (Eq. 3 on joint vectors): f(q) and its sign."""
+    _dev(support_x, torch.float32, "support_x")
+    _dev(alpha, torch.float32, "alpha")
+    _dev(q, torch.float32, "q")
+    S, n = support_x.shape
+    if q.dim() != 2 or q.shape[1] != n or alpha.shape != (S,):
+        raise ValueError("support_x (S, n), alpha (S,) and q (N, n) do not match")
+    N = q.shape[0]
+    f, lab = out if out is not None else _score_outputs(N, q.device, want_f, want_label)
+    check(nat.lib().fastron_rbf_score(_ptr(support_x), _ptr(alpha), S, n, float(gamma), _ptr(q), N, _ptr(f),
+                                      _ptr(lab), _stream()))
+    return f, lab
+
+
+def rbf_train(X: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, iter_max: int | None = None,
+              s_max: int | None = None, alpha: torch.Tensor | None = None, F: torch.Tensor | None = None,
+              fp64: bool = False, trace_cap: int = 0):
+    """Algorithm 1 with the kernel on configurations on X (N, n). Returns the same dict as train()."""
+    _dev(X, torch.float32, "X")
+    _dev(y, torch.int8, "y")
+    N, n = X.shape
+    if y.shape != (N,):
+        raise ValueError("X must be (N, n) and y (N,)")
+    dt = torch.float64 if fp64 else torch.float32
+    alpha = torch.zeros(N, dtype=dt, device=X.device) if alpha is None else alpha.clone()
+    F = torch.zeros(N, dtype=dt, device=X.device) if F is None else F.clone()
+    _dev(alpha, dt, "alpha")
+    _dev(F, dt, "F")
+    iter_max = 20 * max(N, 1) if iter_max is None else int(iter_max)
+    s_max = max(N, 1) if s_max is None else int(s_max)
+    support = torch.empty(max(N, 1), dtype=torch.int32, device=X.device)
+    ns = ctypes.c_int64(0)
+    upd = ctypes.c_int64(0)
+    tr_a = tr_i = None
+    if fp64:
+        tr_a = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=X.device) if trace_cap else None
+        tr_i = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=X.device) if trace_cap else None
+        st = nat.lib().fastron_rbf_train_f64(_ptr(X), _ptr(y), N, n, float(gamma), float(beta), iter_max, s_max,
+                                             _ptr(alpha), _ptr(F), _ptr(support), ctypes.byref(ns),
+                                             ctypes.byref(upd), _ptr(tr_a), _ptr(tr_i), int(trace_cap), _stream())
+    else:
+        st = nat.lib().fastron_rbf_train(_ptr(X), _ptr(y), N, n, float(gamma), float(beta), iter_max, s_max,
+                                         _ptr(alpha), _ptr(F), _ptr(support), ctypes.byref(ns), ctypes.byref(upd),
+                                         _stream())
+    check(st, allow=(nat.FASTRON_OK, nat.FASTRON_NOT_CONVERGED))
+    out = dict(alpha=alpha, F=F, support=support[: ns.value], converged=(st == nat.FASTRON_OK), updates=upd.value)
+    if fp64 and trace_cap:
         k = min(upd.value, trace_cap)
         out["trace_action"] = tr_a[:k]
         out["trace_index"] = tr_i[:k]

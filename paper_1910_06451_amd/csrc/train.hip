@@ -65,6 +65,7 @@ struct TrainState {
   T half_g;
   T beta;
   int M;
+  int D;               // coordinates per point: 3 for control points, n for joint vectors
   int chunk;           // training points per workgroup
   long long timeout;    // wait limit for the record exchange, in constant-clock ticks
   int p_in_lds;         // the slice's control points are staged in LDS
@@ -121,27 +122,43 @@ __device__ __forceinline__ Rec<T> rec_shfl_down(const Rec<T>& r, int off) {
   return o;
 }
 
-// K_FK between a training point (global memory) and the chosen point (LDS),
-// with direct differences. The FP64 form disables FMA contraction so that it
-// rounds operation by operation in the order the definition is written.
-__device__ __forceinline__ float kfk_pair(const float* __restrict__ pj, const float* pi, int M, float half_g) {
+// The kernel of Eq. 4 between a training point (global memory) and the
+// chosen point (LDS), each M points of D coordinates (D = 3: control points and
+// K_FK; M = 1, D = n: the joint vector and the kernel of Eq. 3 on
+// configurations), with direct differences. The FP64 form disables FMA
+// contraction so that it rounds operation by operation in the order the
+// definition is written.
+__device__ __forceinline__ float kfk_pair(const float* __restrict__ pj, const float* pi, int M, int D, float half_g) {
   float s = 0.f;
-  for (int m = 0; m < M; ++m) {
-    const float dx = pj[3 * m] - pi[3 * m], dy = pj[3 * m + 1] - pi[3 * m + 1], dz = pj[3 * m + 2] - pi[3 * m + 2];
-    const float t = 1.0f + half_g * (dx * dx + dy * dy + dz * dz);
-    const float r = __builtin_amdgcn_rcpf(t);
-    s = fmaf(r, r, s);
+  if (D == 3) {
+    for (int m = 0; m < M; ++m) {
+      const float dx = pj[3 * m] - pi[3 * m], dy = pj[3 * m + 1] - pi[3 * m + 1], dz = pj[3 * m + 2] - pi[3 * m + 2];
+      const float t = 1.0f + half_g * (dx * dx + dy * dy + dz * dz);
+      const float r = __builtin_amdgcn_rcpf(t);
+      s = fmaf(r, r, s);
+    }
+  } else {
+    for (int m = 0; m < M; ++m) {
+      float d2 = 0.f;
+      for (int k = 0; k < D; ++k) {
+        const float diff = pj[D * m + k] - pi[D * m + k];
+        d2 = fmaf(diff, diff, d2);
+      }
+      const float r = __builtin_amdgcn_rcpf(1.0f + half_g * d2);
+      s = fmaf(r, r, s);
+    }
   }
   return s / (float)M;
 }
 
-__device__ __forceinline__ double kfk_pair(const float* __restrict__ pj, const float* pi, int M, double half_g) {
+__device__ __forceinline__ double kfk_pair(const float* __restrict__ pj, const float* pi, int M, int D,
+                                           double half_g) {
 #pragma clang fp contract(off)
   double s = 0.0;
   for (int m = 0; m < M; ++m) {
     double d2 = 0.0;
-    for (int k = 0; k < 3; ++k) {
-      const double diff = (double)pj[3 * m + k] - (double)pi[3 * m + k];
+    for (int k = 0; k < D; ++k) {
+      const double diff = (double)pj[D * m + k] - (double)pi[D * m + k];
       d2 += diff * diff;
     }
     const double t = 1.0 + half_g * d2;
@@ -196,7 +213,7 @@ __global__ void __launch_bounds__(256) k_gram_update(const float* __restrict__ P
   __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (j >= N) return;
-  const float k = kfk_pair(P + j * (int64_t)M * 3, pi_sh, M, half_g);
+  const float k = kfk_pair(P + j * (int64_t)M * 3, pi_sh, M, 3, half_g);
   if (kcol) kcol[j] = k;
   if (F) F[j] = axpy_rn(dalpha, k, F[j]);
 }
@@ -339,9 +356,9 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
   const int64_t j0 = (int64_t)blockIdx.x * st.chunk;
   const int64_t j1 = (j0 + st.chunk < st.N) ? j0 + st.chunk : st.N;
-  const int M = st.M;
+  const int M = st.M, W = M * st.D;  // floats per training point
   if (st.p_in_lds)
-    for (int64_t e = threadIdx.x; e < (j1 - j0) * 3 * M; e += blockDim.x) pslice[e] = st.P[j0 * 3 * M + e];
+    for (int64_t e = threadIdx.x; e < (j1 - j0) * W; e += blockDim.x) pslice[e] = st.P[j0 * W + e];
   unsigned long long* words = reinterpret_cast<unsigned long long*>(st.rec);  // [2][G][K]
 
   T y[PT], F[PT], a[PT];
@@ -438,7 +455,7 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
         d.action = 2;
       }
       if (d.action == 1 || d.action == 2) {
-        if (lane < 3 * M) pi_sh[lane] = st.P[d.i * (int64_t)M * 3 + lane];
+        if (lane < W) pi_sh[lane] = st.P[d.i * (int64_t)W + lane];
         if (blockIdx.x == 0 && lane == 0 && updates < st.trace_cap) {
           st.trace_act[updates] = d.action;
           st.trace_idx[updates] = (int32_t)d.i;
@@ -459,8 +476,8 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
     for (int k = 0; k < PT; ++k) {
       if (jj[k] < j1) {
         // index the LDS slice relative to its own start (pointer arithmetic stays inside each object)
-        const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)M * 3 : st.P + jj[k] * (int64_t)M * 3;
-        const T kv = kfk_pair(pj, pi_sh, M, st.half_g);
+        const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)W : st.P + jj[k] * (int64_t)W;
+        const T kv = kfk_pair(pj, pi_sh, M, st.D, st.half_g);
         F[k] = axpy_rn(d.dalpha, kv, F[k]);
         if (jj[k] == d.i) a[k] = (d.action == 1) ? a[k] + d.dalpha : (T)0;  // Eq. 7 / removal
         point_record(r, jj[k], y[k], F[k], a[k]);
@@ -554,9 +571,9 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
   }
   const int64_t j0 = set_lo + (int64_t)me * st.chunk;
   const int64_t j1 = (j0 + st.chunk < set_hi) ? j0 + st.chunk : set_hi;
-  const int M = st.M;
+  const int M = st.M, W = M * st.D;  // floats per training point
   if (st.p_in_lds)
-    for (int64_t e = lane; e < (j1 - j0) * 3 * M; e += 64) pslice[e] = st.P[j0 * 3 * M + e];
+    for (int64_t e = lane; e < (j1 - j0) * W; e += 64) pslice[e] = st.P[j0 * W + e];
   __syncthreads();
 
   T y[PT], F[PT], a[PT];
@@ -655,7 +672,7 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
       status = d.action == 0 ? 0 : (d.action == 3 ? 1 : -5);
       break;
     }
-    if (lane < 3 * M) pi_sh[lane] = st.P[d.i * (int64_t)M * 3 + lane];
+    if (lane < W) pi_sh[lane] = st.P[d.i * (int64_t)W + lane];
     if (me == 0 && lane == 0 && updates < st.trace_cap) {
       st.trace_act[updates] = d.action;
       st.trace_idx[updates] = (int32_t)d.i;
@@ -675,8 +692,8 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
         if constexpr (MM > 0) {
           kv = kfk_regs<MM>(pjr[k], pir, st.half_g);
         } else {
-          const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)M * 3 : st.P + jj[k] * (int64_t)M * 3;
-          kv = kfk_pair(pj, pi_sh, M, st.half_g);
+          const float* pj = st.p_in_lds ? pslice + (jj[k] - j0) * (int64_t)W : st.P + jj[k] * (int64_t)W;
+          kv = kfk_pair(pj, pi_sh, M, st.D, st.half_g);
         }
         F[k] = axpy_rn(d.dalpha, kv, F[k]);
         if (jj[k] == d.i) a[k] = (d.action == 1) ? a[k] + d.dalpha : (T)0;  // Eq. 7 / removal
@@ -757,13 +774,15 @@ static const void* wave_kernel(int PT, int mm) {
 }
 
 template <typename T>
-static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int32_t M, T gamma, T beta,
+static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int32_t M, int32_t D, T gamma, T beta,
                                  int64_t iter_max, int64_t s_max, T* alpha, T* F, int32_t* support_idx,
                                  int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
                                  int64_t trace_cap, void* stream) {
   clear_error();
   FASTRON_CHECK(N >= 1 && N < INT32_MAX, "N = %lld outside [1, 2^31)", (long long)N);
   FASTRON_CHECK(M >= 1 && M <= FASTRON_MAX_POINTS, "M = %d outside [1, %d]", M, FASTRON_MAX_POINTS);
+  FASTRON_CHECK(D >= 1 && M * D <= 3 * FASTRON_MAX_POINTS, "%d points of %d coordinates exceed %d floats", M, D,
+                3 * FASTRON_MAX_POINTS);
   FASTRON_CHECK(P && y && alpha && F && support_idx, "P, y, alpha, F and support_idx must be non-NULL");
   FASTRON_CHECK(n_support && updates, "n_support and updates must be non-NULL host pointers");
   FASTRON_CHECK(std::isfinite((double)gamma) && gamma > 0, "gamma must be finite and > 0");
@@ -798,9 +817,9 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     if (G <= kWaveChunks * 64) {
       // chains with 4 or 8 control points keep each lane's coordinates in
       // registers (up to 4 points per lane)
-      const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
+      const int mm = (D == 3 && PT <= 4 && (M == 4 || M == 8)) ? M : 0;
       kfn = wave_kernel<T>(PT, mm);
-      lds_bytes = mm ? 0 : (size_t)chunk * 3 * M * sizeof(float);
+      lds_bytes = mm ? 0 : (size_t)chunk * M * D * sizeof(float);
       if (lds_bytes > 48 * 1024) lds_bytes = 0;
       FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
       if (per_cu < 1 || G > (int64_t)per_cu * ncu) kfn = nullptr;
@@ -827,7 +846,7 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
       default: kfn = reinterpret_cast<const void*>(k_train<T, 16>); break;
     }
     // stage each slice's control points in LDS when they fit (48 KB budget)
-    lds_bytes = (size_t)chunk * 3 * M * sizeof(float);
+    lds_bytes = (size_t)chunk * M * D * sizeof(float);
     if (lds_bytes > 48 * 1024) lds_bytes = 0;
     FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
     if (per_cu < 1) return fail(FASTRON_EUNSUPPORTED, "training kernel cannot be resident with %d threads", threads);
@@ -859,6 +878,7 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     st.half_g = gamma / (T)2;
     st.beta = beta;
     st.M = M;
+    st.D = D;
     st.chunk = (int)chunk;
     st.timeout = 400000000ll;  // 4 s at 100 MHz
     st.p_in_lds = lds_bytes > 0 ? 1 : 0;
@@ -986,6 +1006,7 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
     st.half_g = gamma / 2.0f;
     st.beta = beta;
     st.M = M;
+    st.D = 3;
     st.chunk = (int)chunk;
     st.timeout = 400000000ll;  // 4 s at 100 MHz
     st.p_in_lds = lds_bytes > 0 ? 1 : 0;
@@ -1046,7 +1067,7 @@ fastron_status fastron_train(const float* P, const int8_t* y, int64_t N, int32_t
                              int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
                              int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
                              int64_t trace_cap, void* stream) {
-  return train_impl<float>(P, y, N, M, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+  return train_impl<float>(P, y, N, M, 3, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
                            trace_action, trace_index, trace_cap, stream);
 }
 
@@ -1061,7 +1082,26 @@ fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int
                                  int64_t iter_max, int64_t s_max, double* alpha, double* F, int32_t* support_idx,
                                  int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
                                  int64_t trace_cap, void* stream) {
-  return train_impl<double>(P, y, N, M, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+  return train_impl<double>(P, y, N, M, 3, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                            trace_action, trace_index, trace_cap, stream);
+}
+
+fastron_status fastron_rbf_train(const float* X, const int8_t* y, int64_t N, int32_t n, float gamma, float beta,
+                                 int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
+                                 int64_t* n_support, int64_t* updates, void* stream) {
+  clear_error();
+  FASTRON_CHECK(n >= 1 && n <= FASTRON_MAX_JOINTS, "n = %d outside [1, %d]", n, FASTRON_MAX_JOINTS);
+  return train_impl<float>(X, y, N, 1, n, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                           nullptr, nullptr, 0, stream);
+}
+
+fastron_status fastron_rbf_train_f64(const float* X, const int8_t* y, int64_t N, int32_t n, double gamma,
+                                     double beta, int64_t iter_max, int64_t s_max, double* alpha, double* F,
+                                     int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                                     int32_t* trace_action, int32_t* trace_index, int64_t trace_cap, void* stream) {
+  clear_error();
+  FASTRON_CHECK(n >= 1 && n <= FASTRON_MAX_JOINTS, "n = %d outside [1, %d]", n, FASTRON_MAX_JOINTS);
+  return train_impl<double>(X, y, N, 1, n, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
                             trace_action, trace_index, trace_cap, stream);
 }
 
