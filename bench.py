@@ -85,8 +85,9 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
-    ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,batched,retrain,screen",
-                    help="comma-separated extra legs (kernels, forms, precision, dof3, train, batched, retrain, screen)")
+    ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,compare,batched,retrain,screen",
+                    help="comma-separated extra legs (kernels, forms, precision, dof3, train, compare, batched, "
+                         "retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=10, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -97,7 +98,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "batched", "retrain", "screen"}
+    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "compare", "batched", "retrain", "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -194,6 +195,9 @@ def main():
     if "train" in legs:
         log("[bench] training run on 50,000 labelled samples")
         extras["train"] = train_run(api, wl, arm, dev)
+    if "compare" in legs:
+        log("[bench] FK kernel vs kernel on configurations")
+        extras["compare"] = compare_run(api, wl, arm, dev, checks)
     if "batched" in legs:
         log("[bench] batched form: 256 environments")
         extras["batched"] = batched_run(api, wl, arm, gamma, dev, checks)
@@ -390,6 +394,77 @@ def train_run(api, wl, arm, dev):
             "collision_rate": float((y == 1).float().mean().item())}
 
 
+GAMMA_CONFIG_7DOF = 10.0  # the kernel on configurations: grid search over {0.1, 0.3, 1, 3, 10, 30, 100}
+
+
+def rbf_peak(n):
+    """ALU ceiling of the configuration-space score, pair evaluations per second: per pair ceil((n + 1) / 4)
+    FP32 MFMA steps of 4 lanes-worth each, one saturated reciprocal (4), its square and the weighting FMA (1
+    each), in 1/128 CU clock at the published rates (see alu_peak)."""
+    return 256 * 2.4e9 * 128 / (4 * ((n + 1 + 3) // 4) + 6)
+
+
+def compare_run(api, wl, arm, dev, checks, reps=5):
+    """The paper's comparison of the FK kernel with the kernel on configurations (Section IV): both models
+    trained by Algorithm 1 on the same 50,000 device-labelled configurations (20 cubes), each with the kernel
+    parameter its own grid search chose, then checked against the geometric labels of 100,000 held-out
+    configurations and timed on the 1,000,000 benchmark queries."""
+    import torch
+
+    N, NT, NQ = 50_000, 100_000, 1_000_000
+    q = torch.from_numpy(wl.configs("bench7/train", N, arm.n)).to(dev)
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    y, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
+    qt = torch.from_numpy(wl.configs("bench7/heldout", NT, arm.n)).to(dev)
+    yt, _ = api.label_capsule_box(arm, qt, arm.radius, lo, hi, want_clearance=False)
+    yt_np = yt.cpu().numpy()
+    qq = torch.from_numpy(wl.configs("bench7/q", NQ, arm.n)).to(dev)
+    f = torch.empty(NQ, dtype=torch.float32, device=dev)
+    lab = torch.empty(NQ, dtype=torch.int8, device=dev)
+
+    def metrics(pred):
+        pos, neg = yt_np == 1, yt_np == -1
+        return {"accuracy": float(np.mean(pred == yt_np)), "tpr": float(np.mean(pred[pos] == 1)),
+                "tnr": float(np.mean(pred[neg] == -1))}
+
+    res = {"N_train": N, "N_heldout": NT, "N_queries": NQ}
+    # FK kernel
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = api.train(api.fk_points(arm, q), y, GAMMA_TRAIN_7DOF)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sup = out["support"].long()
+    model = api.support_prep(arm, q[sup].contiguous(), out["alpha"][sup].contiguous(), GAMMA_TRAIN_7DOF)
+    _, lt = api.fk_score_prepared(arm, model, qt)
+    ms = _event_ms(lambda: api.fk_score_prepared(arm, model, qq, out=(f, lab)), reps)
+    S = int(sup.numel())
+    res["fk"] = {"gamma": GAMMA_TRAIN_7DOF, "support": S, "updates": out["updates"], "converged": bool(out["converged"]),
+                 "train_ms": t_train * 1e3, **metrics(lt.cpu().numpy()), "query_ms_1M": ms,
+                 "checks_per_s": NQ / (ms * 1e-3), "kernel_evals_per_s": NQ * S / (ms * 1e-3)}
+    # kernel on configurations
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = api.rbf_train(q, y, GAMMA_CONFIG_7DOF)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    sup = out["support"].long()
+    sx, sa = q[sup].contiguous(), out["alpha"][sup].contiguous()
+    _, lt = api.rbf_score(sx, sa, GAMMA_CONFIG_7DOF, qt)
+    ms = _event_ms(lambda: api.rbf_score(sx, sa, GAMMA_CONFIG_7DOF, qq, out=(f, lab)), reps)
+    S = int(sup.numel())
+    kev = NQ * S / (ms * 1e-3)
+    res["configurations"] = {"gamma": GAMMA_CONFIG_7DOF, "support": S, "updates": out["updates"],
+                             "converged": bool(out["converged"]), "train_ms": t_train * 1e3,
+                             **metrics(lt.cpu().numpy()), "query_ms_1M": ms, "checks_per_s": NQ / (ms * 1e-3),
+                             "kernel_evals_per_s": kev, "frac_alu": kev / rbf_peak(arm.n)}
+    idx = np.linspace(0, NQ - 1, 2000).astype(np.int64)
+    checks.append({"kind": "configurations", "sq": sx.cpu().numpy(), "al": sa.cpu().numpy(),
+                   "gamma": GAMMA_CONFIG_7DOF, "q": qq[idx].cpu().numpy(), "f": f[idx].cpu().numpy(),
+                   "lab": lab[idx].cpu().numpy(), "into": res["configurations"]})
+    return res
+
+
 def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
     """256 environments with lognormal support sets and uniform query batches: one persistent graph-replayed
     launch versus one plain launch per environment."""
@@ -577,10 +652,14 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras, checks)
     import oracle
 
     for c in checks:
-        a = c["arm"]
-        dh_c = oracle.dh_table(a.a, a.alpha, a.d, a.theta, a.joint_type)
-        ref = oracle.score(dh_c, a.frames, c["sq"].astype(np.float64), c["al"].astype(np.float64), c["gamma"],
-                           c["q"].astype(np.float64), offset=a.offsets)
+        if c.get("kind") == "configurations":
+            ref = oracle.rbf_score(c["sq"].astype(np.float64), c["al"].astype(np.float64), c["gamma"],
+                                   c["q"].astype(np.float64))
+        else:
+            a = c["arm"]
+            dh_c = oracle.dh_table(a.a, a.alpha, a.d, a.theta, a.joint_type)
+            ref = oracle.score(dh_c, a.frames, c["sq"].astype(np.float64), c["al"].astype(np.float64),
+                               c["gamma"], c["q"].astype(np.float64), offset=a.offsets)
         df = float(np.max(np.abs(c["f"].astype(np.float64) - ref)))
         c["into"]["vs_fp64"] = {"queries": int(ref.size), "max_abs_df": df,
                                 "sign_agreement": float(np.mean(c["lab"] == np.where(ref < 0, -1, 1))),
