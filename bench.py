@@ -85,9 +85,9 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
-    ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,compare,batched,retrain,screen",
-                    help="comma-separated extra legs (kernels, forms, precision, dof3, train, compare, batched, "
-                         "retrain, screen)")
+    ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,compare,obstacles,batched,retrain,screen",
+                    help="comma-separated extra legs (kernels, forms, precision, dof3, train, compare, obstacles, "
+                         "batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=10, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -98,7 +98,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "compare", "batched", "retrain", "screen"}
+    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "batched", "retrain",
+                      "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -198,6 +199,9 @@ def main():
     if "compare" in legs:
         log("[bench] FK kernel vs kernel on configurations")
         extras["compare"] = compare_run(api, wl, arm, dev, checks)
+    if "obstacles" in legs:
+        log("[bench] obstacle-count sweep")
+        extras["obstacles"] = obstacles_run(api, wl, arm, dev, checks)
     if "batched" in legs:
         log("[bench] batched form: 256 environments")
         extras["batched"] = batched_run(api, wl, arm, gamma, dev, checks)
@@ -463,6 +467,60 @@ def compare_run(api, wl, arm, dev, checks, reps=5):
                    "gamma": GAMMA_CONFIG_7DOF, "q": qq[idx].cpu().numpy(), "f": f[idx].cpu().numpy(),
                    "lab": lab[idx].cpu().numpy(), "into": res["configurations"]})
     return res
+
+
+def obstacles_run(api, wl, arm, dev, checks, counts=(1, 5, 10, 20, 30, 50), reps=3):
+    """Support-set size, accuracy and query time against the number of obstacles (the paper's obstacle
+    study, Section IV): for each count, 20,000 training and 20,000 held-out configurations labelled by the
+    device labeller (cubes of side 0.1-0.25 m), both kernels trained by Algorithm 1 and timed on 1,000,000
+    queries."""
+    import torch
+
+    N, NT, NQ = 20_000, 20_000, 1_000_000
+    q = torch.from_numpy(wl.configs("obst/train", N, arm.n)).to(dev)
+    qt = torch.from_numpy(wl.configs("obst/heldout", NT, arm.n)).to(dev)
+    qq = torch.from_numpy(wl.configs("bench7/q", NQ, arm.n)).to(dev)
+    f = torch.empty(NQ, dtype=torch.float32, device=dev)
+    lab = torch.empty(NQ, dtype=torch.int8, device=dev)
+    P = api.fk_points(arm, q)
+    rows = []
+    for c in counts:
+        lo, hi = wl.cubes(f"obst/cubes{c}", c, 0.1, 0.25)
+        y, _ = api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False)
+        yt, _ = api.label_capsule_box(arm, qt, arm.radius, lo, hi, want_clearance=False)
+        yt_np = yt.cpu().numpy()
+        row = {"cubes": c, "collision_rate": float((yt == 1).float().mean().item())}
+        for kind in ("fk", "configurations"):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kind == "fk":
+                out = api.train(P, y, GAMMA_TRAIN_7DOF)
+            else:
+                out = api.rbf_train(q, y, GAMMA_CONFIG_7DOF)
+            torch.cuda.synchronize()
+            t_train = time.perf_counter() - t0
+            sup = out["support"].long()
+            sx, sa = q[sup].contiguous(), out["alpha"][sup].contiguous()
+            if kind == "fk":
+                model = api.support_prep(arm, sx, sa, GAMMA_TRAIN_7DOF)
+                _, lt = api.fk_score_prepared(arm, model, qt)
+                ms = _event_ms(lambda: api.fk_score_prepared(arm, model, qq, out=(f, lab)), reps)
+            else:
+                _, lt = api.rbf_score(sx, sa, GAMMA_CONFIG_7DOF, qt)
+                ms = _event_ms(lambda: api.rbf_score(sx, sa, GAMMA_CONFIG_7DOF, qq, out=(f, lab)), reps)
+            row[kind] = {"support": int(sup.numel()), "converged": bool(out["converged"]), "updates": out["updates"],
+                         "train_ms": t_train * 1e3, "accuracy": float(np.mean(lt.cpu().numpy() == yt_np)),
+                         "query_ms_1M": ms, "us_per_query": ms * 1e3 / NQ}
+            if c == counts[-1]:  # FP64 check of the last models' scores on 1,000 of the timed queries
+                idx = np.linspace(0, NQ - 1, 1000).astype(np.int64)
+                chk = {"sq": sx.cpu().numpy(), "al": sa.cpu().numpy(), "q": qq[idx].cpu().numpy(),
+                       "f": f[idx].cpu().numpy(), "lab": lab[idx].cpu().numpy(), "into": row[kind]}
+                if kind == "fk":
+                    checks.append({"arm": arm, "gamma": GAMMA_TRAIN_7DOF, **chk})
+                else:
+                    checks.append({"kind": "configurations", "gamma": GAMMA_CONFIG_7DOF, **chk})
+        rows.append(row)
+    return {"N_train": N, "N_heldout": NT, "N_queries": NQ, "rows": rows}
 
 
 def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
