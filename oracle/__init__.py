@@ -28,6 +28,9 @@ for Improved Proxy Collision Checking"):
 * ``capsule_box_labels`` -- geometric labeller standing in for the checker used
   in Section IV (not part of the paper's method)
 * ``metrics``          -- Section IV-A, Eq. 10-12 (accuracy, TPR, TNR)
+* ``active_learning_round`` -- Section III-B, the two-stage active learning
+  (samples near every support point, uniform samples) and the model update
+  that follows it
 """
 from __future__ import annotations
 
@@ -341,3 +344,26 @@ def metrics(pred, truth) -> dict:
     return dict(accuracy=(tp + tn) / tot if tot else float("nan"),
                 tpr=tp / (tp + fn) if (tp + fn) else float("nan"),
                 tnr=tn / (tn + fp) if (tn + fp) else float("nan"), tp=tp, tn=tn, fp=fp, fn=fn)
+
+
+def active_learning_round(dh, frame, support_q, alpha, gamma, noise, k, explore, radius, boxes_lo, boxes_hi,
+                          beta=1.0, iter_max=None, s_max=None):
+    """One model update after the two-stage active learning of Section III-B: the new training set is the
+    support set, k samples near each support point (support + noise rows, in float32 like the inputs) and
+    the exploration samples; every row gets a geometric label; F starts as the current model's score of
+    every row (F = K alpha, alpha kept on the supports, on the control points rounded to float32) and
+    Algorithm 1 runs from there on those points. Returns dict(X, y, clearance, F0 and the fastron_update result)."""
+    sq = np.asarray(support_q, dtype=np.float32)
+    S, n = sq.shape
+    noise = np.asarray(noise, dtype=np.float32).reshape(S * k, n)
+    explore = np.asarray(explore, dtype=np.float32).reshape(-1, n)
+    near = (np.repeat(sq, k, axis=0).astype(np.float64) + noise.astype(np.float64)).astype(np.float32)
+    X = np.concatenate([sq, near, explore]).astype(np.float32)
+    a0 = np.zeros(X.shape[0])
+    a0[:S] = np.asarray(alpha, dtype=np.float64)
+    y, clearance = capsule_box_labels(dh, X.astype(np.float64), radius, boxes_lo, boxes_hi)
+    P = control_points(dh, frame, X.astype(np.float64)).astype(np.float32).astype(np.float64)
+    F0 = score_points(P[:S], a0[:S], gamma, P)  # K alpha on the points the update trains on
+    out = fastron_update(P, y, gamma, beta=beta, iter_max=iter_max, s_max=s_max, alpha=a0, F=F0)
+    out.update(X=X, y=y, clearance=clearance, F0=F0)
+    return out

@@ -156,3 +156,44 @@ def test_configuration_kernel_training_claim2(oracle_mod):
     np.testing.assert_allclose(out["F"], K @ out["alpha"], rtol=0, atol=1e-9)
     assert np.all(y * out["F"] > 0)
     np.testing.assert_array_equal(out["support"], np.flatnonzero(out["alpha"]))
+
+
+def test_active_learning_round(oracle_mod):
+    """The update after two-stage active learning (Section III-B). Pins: the assembled set is the support
+    set, support + noise rows and the exploration rows; F0 on the support rows equals K_SS alpha from the
+    Gram matrix; the update converges with every margin positive (Claim 2) and keeps the rows' labels; with
+    no new samples and unchanged obstacles a converged model comes back unchanged after zero updates."""
+    arm = wl.arm_3dof()
+    dh = oracle_mod.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
+    g = np.random.default_rng(11)
+    lo, hi = wl.cubes("al_cubes", 5, 0.15)
+    q = wl.configs("al_train", 400, 3)
+    y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+    P = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32).astype(np.float64)
+    base = oracle_mod.fastron_update(P, y, 10.0)
+    assert base["converged"]
+    sup = base["support"]
+    sq, al = q[sup], base["alpha"][sup]
+    # no new samples, same obstacles: nothing to change
+    same = oracle_mod.active_learning_round(dh, arm.frames, sq, al, 10.0, np.zeros((0, 3)), 0, np.zeros((0, 3)),
+                                            arm.radius, lo, hi)
+    assert same["updates"] == 0 and same["converged"]
+    np.testing.assert_array_equal(same["alpha"], al)
+    # moved obstacles, 2 samples near each support point, 150 uniform samples
+    lo2, hi2 = lo + 0.05, hi + 0.05
+    noise = (0.1 * g.standard_normal((2 * len(sup), 3))).astype(np.float32)
+    explore = g.uniform(-np.pi, np.pi, (150, 3)).astype(np.float32)
+    out = oracle_mod.active_learning_round(dh, arm.frames, sq, al, 10.0, noise, 2, explore, arm.radius, lo2, hi2)
+    X = out["X"]
+    S = len(sup)
+    assert X.shape == (3 * S + 150, 3)
+    np.testing.assert_array_equal(X[:S], sq)
+    np.testing.assert_array_equal(X[S:3 * S], (np.repeat(sq, 2, axis=0) + noise).astype(np.float32))
+    np.testing.assert_array_equal(X[3 * S:], explore)
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64)).astype(np.float32).astype(np.float64)
+    np.testing.assert_allclose(out["F0"][:S], oracle_mod.gram(Ps, 10.0) @ al, rtol=0, atol=1e-12)
+    assert out["converged"]
+    PX = oracle_mod.control_points(dh, arm.frames, X.astype(np.float64)).astype(np.float32).astype(np.float64)
+    K = oracle_mod.gram(PX, 10.0)
+    np.testing.assert_allclose(out["F"], K @ out["alpha"], rtol=0, atol=1e-9)
+    assert np.all(out["y"] * out["F"] > 0)
