@@ -85,9 +85,10 @@ def main():
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
-    ap.add_argument("--legs", default="kernels,forms,precision,dof3,train,compare,obstacles,batched,retrain,screen",
+    ap.add_argument("--legs",
+                    default="kernels,forms,precision,dof3,train,compare,obstacles,active,batched,retrain,screen",
                     help="comma-separated extra legs (kernels, forms, precision, dof3, train, compare, obstacles, "
-                         "batched, retrain, screen)")
+                         "active, batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=10, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -98,8 +99,8 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "batched", "retrain",
-                      "screen"}
+    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "active", "batched",
+                      "retrain", "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
@@ -202,6 +203,9 @@ def main():
     if "obstacles" in legs:
         log("[bench] obstacle-count sweep")
         extras["obstacles"] = obstacles_run(api, wl, arm, dev, checks)
+    if "active" in legs:
+        log("[bench] moving obstacle: model updates after two-stage active learning")
+        extras["active"] = active_run(api, wl, arm, dev)
     if "batched" in legs:
         log("[bench] batched form: 256 environments")
         extras["batched"] = batched_run(api, wl, arm, gamma, dev, checks)
@@ -521,6 +525,72 @@ def obstacles_run(api, wl, arm, dev, checks, counts=(1, 5, 10, 20, 30, 50), reps
                     checks.append({"kind": "configurations", "gamma": GAMMA_CONFIG_7DOF, **chk})
         rows.append(row)
     return {"N_train": N, "N_heldout": NT, "N_queries": NQ, "rows": rows}
+
+
+def active_run(api, wl, arm, dev, steps=10, n_init=20_000, k=2, sigma=0.1, n_explore=2_000, n_test=20_000):
+    """The moving-obstacle experiment (Section III-B's update, Section IV): a single randomly sized cube moves
+    0.05 m along a random direction per step; after each move the model is updated once after two-stage
+    active learning (k samples near each support point with N(0, sigma^2) joint noise, n_explore uniform
+    samples, geometric labels, F = K alpha, Algorithm 1 warm start) and checked against the labels of n_test
+    held-out configurations at the cube's new position. Both kernels; update time from device-synchronised
+    host timers around the whole update."""
+    import torch
+
+    g = wl.rng("active/draws")
+    lo, hi = wl.cubes("active/cube", 1, 0.1, 0.25)
+    centre = 0.5 * (lo + hi)
+    half = 0.5 * (hi - lo)
+    q0 = torch.from_numpy(wl.configs("active/init", n_init, arm.n)).to(dev)
+    qt = torch.from_numpy(wl.configs("active/test", n_test, arm.n)).to(dev)
+    dirs = g.standard_normal((steps, 3))
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    res = {"steps": steps, "n_init": n_init, "k": k, "sigma": sigma, "n_explore": n_explore, "n_test": n_test}
+    for kind, gam in (("fk", GAMMA_TRAIN_7DOF), ("configurations", GAMMA_CONFIG_7DOF)):
+        y0, _ = api.label_capsule_box(arm, q0, arm.radius, lo, hi, want_clearance=False)
+        out = api.train(api.fk_points(arm, q0), y0, gam) if kind == "fk" else api.rbf_train(q0, y0, gam)
+        sup = out["support"].long()
+        sq, sa = q0[sup].contiguous(), out["alpha"][sup].contiguous()
+        c = centre.copy()
+        rows = []
+        gk = wl.rng(f"active/{kind}")
+        for step in range(steps):
+            c = c + 0.05 * dirs[step]
+            lo2, hi2 = c - half, c + half
+            S = sq.shape[0]
+            noise = torch.from_numpy((sigma * gk.standard_normal((S * k, arm.n))).astype(np.float32)).to(dev)
+            explore = torch.from_numpy(gk.uniform(-np.pi, np.pi, (n_explore, arm.n)).astype(np.float32)).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            if kind == "fk":
+                o = api.active_learning_round(arm, sq, sa, gam, noise, k, explore, lo2, hi2)
+                X = o["X"]
+            else:
+                X, a0 = api.active_samples(sq, sa, noise, k, explore)
+                yX, _ = api.label_capsule_box(arm, X, arm.radius, lo2, hi2, want_clearance=False)
+                F0, _ = api.rbf_score(sq, sa, gam, X, want_label=False)
+                o = api.rbf_train(X, yX, gam, alpha=a0, F=F0)
+            torch.cuda.synchronize()
+            t_upd = time.perf_counter() - t0
+            s2 = o["support"].long()
+            sq, sa = X[s2].contiguous(), o["alpha"][s2].contiguous()
+            yt, _ = api.label_capsule_box(arm, qt, arm.radius, lo2, hi2, want_clearance=False)
+            if kind == "fk":
+                _, lt = api.fk_score(arm, sq, sa, gam, qt, want_f=False)
+            else:
+                _, lt = api.rbf_score(sq, sa, gam, qt, want_f=False)
+            yt_np, lt_np = yt.cpu().numpy(), lt.cpu().numpy()
+            pos, neg = yt_np == 1, yt_np == -1
+            rows.append({"rows": int(X.shape[0]), "support": int(s2.numel()), "updates": o["updates"],
+                         "converged": bool(o["converged"]), "update_ms": t_upd * 1e3,
+                         "accuracy": float(np.mean(lt_np == yt_np)),
+                         "tpr": float(np.mean(lt_np[pos] == 1)) if pos.any() else None,
+                         "tnr": float(np.mean(lt_np[neg] == -1))})
+        res[kind] = {"gamma": gam, "initial_support": int(sup.numel()), "per_step": rows,
+                     "mean_update_ms": float(np.mean([r["update_ms"] for r in rows[1:]])),
+                     "mean_accuracy": float(np.mean([r["accuracy"] for r in rows])),
+                     "mean_tpr": float(np.mean([r["tpr"] for r in rows if r["tpr"] is not None])),
+                     "mean_tnr": float(np.mean([r["tnr"] for r in rows]))}
+    return res
 
 
 def batched_run(api, wl, arm, gamma, dev, checks, reps=5):

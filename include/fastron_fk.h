@@ -297,6 +297,21 @@ fastron_status fastron_rbf_train_f64(const float* X, const int8_t* y, int64_t N,
                                      int32_t* support_idx, int64_t* n_support, int64_t* updates,
                                      int32_t* trace_action, int32_t* trace_index, int64_t trace_cap, void* stream);
 
+/* ---- two-stage active learning (Section III-B, after the model update) ----
+ * Assembles the training set of the next model update: X_out rows [0, S) =
+ * the support configurations support_q [S][n] (alpha_out = their weights),
+ * rows S + s k + j = support s plus noise row s k + j of noise [S k][n]
+ * (samples near each support point; alpha_out = 0), and the last E rows =
+ * explore [E][n] (uniform samples over the C-space; alpha_out = 0). The random
+ * draws are the caller's. X_out holds S (1 + k) + E rows of n floats;
+ * alpha_out (may be NULL) as many floats. All arrays are device memory. The
+ * update then labels every row (fastron_label_capsule_box), takes F = the
+ * current model's score of every row (fastron_fk_score; F = K alpha) and
+ * runs fastron_train from (alpha_out, F).                                  */
+fastron_status fastron_active_samples(const float* support_q, const float* alpha, int64_t S, int32_t n,
+                                      const float* noise, int32_t k, const float* explore, int64_t E, float* X_out,
+                                      float* alpha_out, void* stream);
+
 /* ---- a9: geometric labels -------------------------------------------------
  * Stands in for the ground-truth collision checker of Section IV: link i is a
  * capsule of radius `radius` around the segment between the origins of

@@ -16,7 +16,7 @@ from ._native import HostChain, check
 
 __all__ = [
     "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train", "train_batch",
-    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set",
+    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set", "active_samples", "active_learning_round",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
@@ -316,6 +316,38 @@ def label_capsule_box(arm, q: torch.Tensor, radius: float, boxes_lo, boxes_hi, w
     check(nat.lib().fastron_label_capsule_box(ctypes.byref(hc.chain), _ptr(q), N, float(radius), _ptr(boxes),
                                               boxes.shape[0], _ptr(lab), _ptr(clr), _stream()))
     return lab, clr
+
+
+def active_samples(support_q: torch.Tensor, alpha: torch.Tensor, noise: torch.Tensor, k: int,
+                   explore: torch.Tensor):
+    """Training set of the next model update (two-stage active learning, Section III-B): the supports, k
+    samples near each (support + noise row) and the exploration samples; weights kept on the supports."""
+    for t, name in ((support_q, "support_q"), (alpha, "alpha"), (noise, "noise"), (explore, "explore")):
+        _dev(t, torch.float32, name)
+    S, n = support_q.shape
+    E = explore.shape[0]
+    if alpha.shape != (S,) or noise.shape != (S * k, n) or explore.dim() != 2 or explore.shape[1] != n:
+        raise ValueError("support_q (S, n), alpha (S,), noise (S k, n) and explore (E, n) do not match")
+    rows = S * (1 + k) + E
+    X = torch.empty(rows, n, dtype=torch.float32, device=support_q.device)
+    a0 = torch.empty(rows, dtype=torch.float32, device=support_q.device)
+    check(nat.lib().fastron_active_samples(_ptr(support_q), _ptr(alpha), S, n, _ptr(noise), int(k), _ptr(explore),
+                                           E, _ptr(X), _ptr(a0), _stream()))
+    return X, a0
+
+
+def active_learning_round(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, noise: torch.Tensor,
+                          k: int, explore: torch.Tensor, boxes_lo, boxes_hi, beta: float = 1.0,
+                          iter_max: int | None = None, s_max: int | None = None):
+    """One model update after two-stage active learning (Section III-B), every step on the device: assemble
+    the new training set, label every row geometrically, start from F = the current model's score of every
+    row (F = K alpha) and run Algorithm 1. Returns train()'s dict plus X, y and F0."""
+    X, a0 = active_samples(support_q, alpha, noise, k, explore)
+    y, _ = label_capsule_box(arm, X, arm.radius, boxes_lo, boxes_hi, want_clearance=False)
+    F0, _ = fk_score(arm, support_q, alpha, gamma, X, want_label=False)
+    out = train(fk_points(arm, X), y, gamma, beta=beta, iter_max=iter_max, s_max=s_max, alpha=a0, F=F0)
+    out.update(X=X, y=y, F0=F0)
+    return out
 
 
 class Batch:

@@ -177,3 +177,4 @@ fastron_status fastron_rbf_score(const float* support_x, const float* alpha, int
 }
 
 }  // extern "C"
+

@@ -1,0 +1,60 @@
+"""Parity of the model update after two-stage active learning (Section III-B) with the FP64 oracle: the
+device assembles the new training set (supports, samples near each support point, uniform samples), labels
+every row, starts from F = the current model's score of every row and runs Algorithm 1.
+
+The assembled rows must be bit-identical (the perturbation is one float32 addition on both sides), the
+labels identical, F0 within the FP32 bound of the score tests, and the updated FP32 model is judged by
+Claim 2 with the oracle's F = K alpha and by the size of its support set."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1910_06451_amd import api, workloads as wl
+from conftest import announce, oracle_dh
+from test_gpu_score import error_bound
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("arm_name,k,E", [("3dof", 2, 150), ("7dof", 3, 500)])
+def test_active_learning_round_matches_oracle(oracle_mod, dev, arm_name, k, E):
+    arm = wl.arm_3dof() if arm_name == "3dof" else wl.arm_7dof()
+    n = arm.n
+    gamma = 10.0
+    dh = oracle_dh(oracle_mod, arm)
+    lo, hi = wl.cubes(f"al_{arm_name}/cubes", 5, 0.15, 0.25)
+    q = wl.configs(f"al_{arm_name}/train", 600, n)
+    y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+    P = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32).astype(np.float64)
+    base = oracle_mod.fastron_update(P, y, gamma)
+    sup = base["support"]
+    sq = q[sup]
+    al = base["alpha"][sup].astype(np.float32)
+    g = wl.rng(f"al_{arm_name}/draws")
+    noise = (0.1 * g.standard_normal((k * len(sup), n))).astype(np.float32)
+    explore = g.uniform(-np.pi, np.pi, (E, n)).astype(np.float32)
+    lo2, hi2 = lo + 0.05, hi + 0.05  # the obstacles moved
+    ref = oracle_mod.active_learning_round(dh, arm.frames, sq, al.astype(np.float64), gamma, noise, k, explore,
+                                           arm.radius, lo2, hi2)
+    announce(f"active learning round {arm_name} S={len(sup)} k={k} E={E}")
+    out = api.active_learning_round(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma,
+                                    torch.from_numpy(noise).to(dev), k, torch.from_numpy(explore).to(dev), lo2, hi2)
+    X = out["X"].cpu().numpy()
+    np.testing.assert_array_equal(X, ref["X"])
+    yg = out["y"].cpu().numpy()
+    near_zero = np.abs(ref["clearance"]) < 1e-9
+    np.testing.assert_array_equal(yg[~near_zero], ref["y"][~near_zero])
+    PX = oracle_mod.control_points(dh, arm.frames, X.astype(np.float64))
+    tol = error_bound(PX[: len(sup)], al, gamma, PX)
+    assert np.all(np.abs(out["F0"].cpu().numpy() - ref["F0"]) <= tol)
+    assert out["converged"] and ref["converged"]
+    alpha = out["alpha"].cpu().numpy()
+    s2 = out["support"].cpu().numpy()
+    np.testing.assert_array_equal(s2, np.flatnonzero(alpha))
+    P32 = PX.astype(np.float32).astype(np.float64)
+    F_oracle = oracle_mod.score_points(P32[s2], alpha[s2].astype(np.float64), gamma, P32)
+    margins = ref["y"] * F_oracle
+    print(dict(rows=X.shape[0], gpu_support=int(s2.shape[0]), oracle_support=int(ref["support"].shape[0]),
+               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min())))
+    assert np.mean(margins > 0) >= 0.999
+    assert abs(s2.shape[0] - ref["support"].shape[0]) <= 0.05 * ref["support"].shape[0] + 5
