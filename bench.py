@@ -562,7 +562,7 @@ def active_run(api, wl, arm, dev, steps=10, n_init=20_000, k=2, sigma=0.1, n_exp
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if kind == "fk":
-                o = api.active_learning_round(arm, sq, sa, gam, noise, k, explore, lo2, hi2)
+                o = api.active_update(arm, sq, sa, gam, noise, k, explore, lo2, hi2)
                 X = o["X"]
             else:
                 X, a0 = api.active_samples(sq, sa, noise, k, explore)
@@ -829,8 +829,8 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras, checks)
 
 def cpu_rows(oracle, arm, dh, extras):
     """The oracle timed on the other steps of the path, each beside the GPU figure of the same step when the
-    corresponding leg ran: FK (a1), Gram column (a4), Algorithm 1 (a5, 3-DOF workload), labels (a9) and the
-    screening network's forward pass (a8)."""
+    corresponding leg ran: FK (a1), Gram column (a4), Algorithm 1 (a5, 3-DOF workload), labels (a9), the
+    screening network's forward pass (a8) and the score with the kernel on configurations."""
     from oracle import mlp_oracle
     from paper_1910_06451_amd import workloads as wl
 
@@ -865,6 +865,14 @@ def cpu_rows(oracle, arm, dh, extras):
         rows["train_3dof"] = {"oracle_ms": t * 1e3, "oracle_updates": r3["updates"],
                               "gpu_ms_fp64": d3["train_ms_fp64"], "gpu_updates": d3["updates"],
                               "sample": "2,000 labelled 3-DOF configurations, gamma = 10"}
+    cmp_ = extras.get("compare", {}).get("configurations")
+    if cmp_:
+        sx, sa = wl.model("cpu_rows/config", cmp_["support"], arm.n)
+        qc = qs[:4096, : arm.n]
+        _, t = timed(lambda: oracle.rbf_score(sx.astype(np.float64), sa.astype(np.float64), GAMMA_CONFIG_7DOF, qc))
+        rows["configuration_score"] = {"oracle_kernel_evals_per_s": qc.shape[0] * sx.shape[0] / t,
+                                       "sample": f"4,096 queries against {cmp_['support']:,} supports",
+                                       "gpu_kernel_evals_per_s": cmp_["kernel_evals_per_s"]}
     params = [p.astype(np.float64) for p in wl.split_mlp_params(wl.mlp_init(24, 256, name="cpu_rows"), 24)]
     X = P[:65_536].reshape(-1, 24)
     _, t = timed(lambda: mlp_oracle.forward(params, X, X.mean(axis=0), X.std(axis=0) + 1e-9))

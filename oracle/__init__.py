@@ -28,7 +28,7 @@ for Improved Proxy Collision Checking"):
 * ``capsule_box_labels`` -- geometric labeller standing in for the checker used
   in Section IV (not part of the paper's method)
 * ``metrics``          -- Section IV-A, Eq. 10-12 (accuracy, TPR, TNR)
-* ``active_learning_round`` -- Section III-B, the two-stage active learning
+* ``active_update`` -- Section III-B, the two-stage active learning
   (samples near every support point, uniform samples) and the model update
   that follows it
 """
@@ -346,8 +346,8 @@ def metrics(pred, truth) -> dict:
                 tnr=tn / (tn + fp) if (tn + fp) else float("nan"), tp=tp, tn=tn, fp=fp, fn=fn)
 
 
-def active_learning_round(dh, frame, support_q, alpha, gamma, noise, k, explore, radius, boxes_lo, boxes_hi,
-                          beta=1.0, iter_max=None, s_max=None):
+def active_update(dh, frame, support_q, alpha, gamma, noise, k, explore, radius, boxes_lo, boxes_hi,
+                  beta=1.0, iter_max=None, s_max=None):
     """One model update after the two-stage active learning of Section III-B: the new training set is the
     support set, k samples near each support point (support + noise rows, in float32 like the inputs) and
     the exploration samples; every row gets a geometric label; F starts as the current model's score of

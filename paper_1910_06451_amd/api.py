@@ -16,7 +16,7 @@ from ._native import HostChain, check
 
 __all__ = [
     "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train", "train_batch",
-    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set", "active_samples", "active_learning_round",
+    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set", "active_samples", "active_update",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
@@ -336,9 +336,9 @@ def active_samples(support_q: torch.Tensor, alpha: torch.Tensor, noise: torch.Te
     return X, a0
 
 
-def active_learning_round(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, noise: torch.Tensor,
-                          k: int, explore: torch.Tensor, boxes_lo, boxes_hi, beta: float = 1.0,
-                          iter_max: int | None = None, s_max: int | None = None):
+def active_update(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, noise: torch.Tensor,
+                  k: int, explore: torch.Tensor, boxes_lo, boxes_hi, beta: float = 1.0,
+                  iter_max: int | None = None, s_max: int | None = None):
     """One model update after two-stage active learning (Section III-B), every step on the device: assemble
     the new training set, label every row geometrically, start from F = the current model's score of every
     row (F = K alpha) and run Algorithm 1. Returns train()'s dict plus X, y and F0."""

@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 
 @pytest.mark.parametrize("arm_name,k,E", [("3dof", 2, 150), ("7dof", 3, 500)])
-def test_active_learning_round_matches_oracle(oracle_mod, dev, arm_name, k, E):
+def test_active_update_matches_oracle(oracle_mod, dev, arm_name, k, E):
     arm = wl.arm_3dof() if arm_name == "3dof" else wl.arm_7dof()
     n = arm.n
     gamma = 10.0
@@ -34,11 +34,11 @@ def test_active_learning_round_matches_oracle(oracle_mod, dev, arm_name, k, E):
     noise = (0.1 * g.standard_normal((k * len(sup), n))).astype(np.float32)
     explore = g.uniform(-np.pi, np.pi, (E, n)).astype(np.float32)
     lo2, hi2 = lo + 0.05, hi + 0.05  # the obstacles moved
-    ref = oracle_mod.active_learning_round(dh, arm.frames, sq, al.astype(np.float64), gamma, noise, k, explore,
-                                           arm.radius, lo2, hi2)
-    announce(f"active learning round {arm_name} S={len(sup)} k={k} E={E}")
-    out = api.active_learning_round(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma,
-                                    torch.from_numpy(noise).to(dev), k, torch.from_numpy(explore).to(dev), lo2, hi2)
+    ref = oracle_mod.active_update(dh, arm.frames, sq, al.astype(np.float64), gamma, noise, k, explore,
+                                   arm.radius, lo2, hi2)
+    announce(f"active-learning update {arm_name} S={len(sup)} k={k} E={E}")
+    out = api.active_update(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma,
+                            torch.from_numpy(noise).to(dev), k, torch.from_numpy(explore).to(dev), lo2, hi2)
     X = out["X"].cpu().numpy()
     np.testing.assert_array_equal(X, ref["X"])
     yg = out["y"].cpu().numpy()

@@ -158,7 +158,7 @@ def test_configuration_kernel_training_claim2(oracle_mod):
     np.testing.assert_array_equal(out["support"], np.flatnonzero(out["alpha"]))
 
 
-def test_active_learning_round(oracle_mod):
+def test_active_update(oracle_mod):
     """The update after two-stage active learning (Section III-B). Pins: the assembled set is the support
     set, support + noise rows and the exploration rows; F0 on the support rows equals K_SS alpha from the
     Gram matrix; the update converges with every margin positive (Claim 2) and keeps the rows' labels; with
@@ -175,15 +175,15 @@ def test_active_learning_round(oracle_mod):
     sup = base["support"]
     sq, al = q[sup], base["alpha"][sup]
     # no new samples, same obstacles: nothing to change
-    same = oracle_mod.active_learning_round(dh, arm.frames, sq, al, 10.0, np.zeros((0, 3)), 0, np.zeros((0, 3)),
-                                            arm.radius, lo, hi)
+    same = oracle_mod.active_update(dh, arm.frames, sq, al, 10.0, np.zeros((0, 3)), 0, np.zeros((0, 3)),
+                                    arm.radius, lo, hi)
     assert same["updates"] == 0 and same["converged"]
     np.testing.assert_array_equal(same["alpha"], al)
     # moved obstacles, 2 samples near each support point, 150 uniform samples
     lo2, hi2 = lo + 0.05, hi + 0.05
     noise = (0.1 * g.standard_normal((2 * len(sup), 3))).astype(np.float32)
     explore = g.uniform(-np.pi, np.pi, (150, 3)).astype(np.float32)
-    out = oracle_mod.active_learning_round(dh, arm.frames, sq, al, 10.0, noise, 2, explore, arm.radius, lo2, hi2)
+    out = oracle_mod.active_update(dh, arm.frames, sq, al, 10.0, noise, 2, explore, arm.radius, lo2, hi2)
     X = out["X"]
     S = len(sup)
     assert X.shape == (3 * S + 150, 3)
