@@ -232,6 +232,8 @@ def rbf_train(X: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0,
     """Algorithm 1 with the kernel on configurations on X (N, n). Returns the same dict as train()."""
     _dev(X, torch.float32, "X")
     _dev(y, torch.int8, "y")
+    if trace_cap and not fp64:
+        raise ValueError("the update trace is recorded by the FP64 mode only (fp64=True)")
     N, n = X.shape
     if y.shape != (N,):
         raise ValueError("X must be (N, n) and y (N,)")

@@ -98,3 +98,21 @@ def test_rbf_train_fp32_claim2(oracle_mod, dev):
     f, lab = api.rbf_score(X[out["support"].long()].contiguous(), out["alpha"][out["support"].long()].contiguous(),
                            1.0, X[:512].contiguous())
     np.testing.assert_allclose(f.cpu().numpy(), F_oracle[:512], rtol=0, atol=1e-3)
+
+
+def test_rbf_score_full_size_sampled(oracle_mod, dev):
+    """The comparison leg's launch: 1,000,000 7-DOF queries against 20,043 supports in one call; the oracle
+    checks 1,000 sampled outputs (and the last), and every label is the sign of its score."""
+    S, N, gamma = 20_043, 1_000_000, 10.0
+    sx, al = wl.model("rbf_full", S, 7)
+    q = wl.configs("rbf_full/q", N, 7)
+    announce("rbf_score full size S=20043 N=1e6")
+    f, lab = api.rbf_score(torch.from_numpy(sx).to(dev), torch.from_numpy(al).to(dev), gamma,
+                           torch.from_numpy(q).to(dev))
+    f, lab = f.cpu().numpy(), lab.cpu().numpy()
+    idx = np.unique(np.concatenate([wl.rng("rbf_full/sample").choice(N, 1000, replace=False), [N - 1]]))
+    ref = oracle_mod.rbf_score(sx.astype(np.float64), al.astype(np.float64), gamma, q[idx].astype(np.float64))
+    tol = error_bound(sx.astype(np.float64)[:, None, :], al, gamma, q[idx].astype(np.float64)[:, None, :])
+    print(check_scores(f[idx], lab[idx], ref, tol))
+    assert np.all(np.isfinite(f))
+    np.testing.assert_array_equal(lab, np.where(f < 0, -1, 1))
