@@ -94,6 +94,25 @@ def test_validation_before_device_work(lib):
     assert lib.fastron_train(*args(1.0, 10, gamma=0.0)) == nat.FASTRON_EINVAL
     assert lib.fastron_train(*args(1.0, 10, gamma=float("nan"))) == nat.FASTRON_EINVAL
     assert lib.fastron_gram_update(fake, 100, 8, 10.0, 100, 1.0, fake, None, None) == nat.FASTRON_EINVAL  # i >= N
+    # the kernel on configurations
+    assert lib.fastron_rbf_score(None, None, 0, 7, 1.0, None, 0, None, None, None) == nat.FASTRON_OK  # N = 0
+    assert lib.fastron_rbf_score(fake, fake, 10, 0, 1.0, fake, 10, fake, None, None) == nat.FASTRON_EINVAL  # n < 1
+    assert lib.fastron_rbf_score(fake, fake, 10, 17, 1.0, fake, 10, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_rbf_score(fake, fake, 10, 7, -1.0, fake, 10, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_rbf_score(None, None, 10, 7, 1.0, fake, 10, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_rbf_score(fake, fake, 10, 7, 1.0, fake, 10, None, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_rbf_train(fake, fake, 100, 0, 1.0, 1.0, 10, 10, fake, fake, fake, ctypes.byref(ns),
+                                 ctypes.byref(up), None) == nat.FASTRON_EINVAL
+    assert lib.fastron_rbf_train(fake, fake, 100, 7, 1.0, 0.5, 10, 10, fake, fake, fake, ctypes.byref(ns),
+                                 ctypes.byref(up), None) == nat.FASTRON_EINVAL  # beta < 1
+    assert lib.fastron_rbf_train_f64(fake, fake, 100, 7, 0.0, 1.0, 10, 10, fake, fake, fake, ctypes.byref(ns),
+                                     ctypes.byref(up), None, None, 0, None) == nat.FASTRON_EINVAL
+    # active-learning assembly
+    assert lib.fastron_active_samples(None, None, 0, 7, None, 0, None, 0, None, None, None) == nat.FASTRON_OK
+    assert lib.fastron_active_samples(fake, fake, 10, 7, None, 2, None, 0, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_active_samples(fake, fake, 10, 7, fake, 2, None, 5, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_active_samples(fake, fake, 10, 7, fake, 2, fake, 5, None, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_active_samples(fake, fake, -1, 7, fake, 2, fake, 5, fake, None, None) == nat.FASTRON_EINVAL
 
 
 def _frames_lib(lib, a, d, types, include_base):
