@@ -127,12 +127,16 @@ def main():
         step()
     torch.cuda.synchronize()
     log(f"[bench] timing {args.steps} steps")
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for i in range(args.steps):
+        marks[i].record()
         step()
+    marks[-1].record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms = (t1 - t0) * 1e3 / args.steps
+    step_ms = [marks[i].elapsed_time(marks[i + 1]) for i in range(args.steps)]
     checks_per_s = N / (ms * 1e-3)
 
     # dominant kernel alone: score against a prepared model, timed with events on the launch stream
@@ -150,7 +154,19 @@ def main():
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
+    def kernel_spread(flags, reps):
+        """Per-launch durations from an event pair around each launch: (median, min)."""
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for a, b in ev:
+            a.record(stream)
+            api.fk_score_prepared(arm, model, q, flags=flags, out=(f, lab))
+            b.record(stream)
+        torch.cuda.synchronize()
+        per = [a.elapsed_time(b) for a, b in ev]
+        return float(np.median(per)), float(np.min(per))
+
     k_ms = kernel_ms(api.SCORE_FP32, args.steps)
+    k_med, k_min = kernel_spread(api.SCORE_FP32, max(20, args.steps))
     if args.calibrate_copy:
         src = torch.ones(64 << 20, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
@@ -169,7 +185,8 @@ def main():
                 # queries (n floats each) + the FP32 part of the packed support set (256 B header,
                 # 16-support tiles of 80 * Mp + 16 floats) + outputs (float score + int8 label)
                 "algorithmic_bytes": N * arm.n * 4 + 256 + -(-S // 16) * (80 * ((arm.M + 3) & ~3) + 16) * 4 + N * 5,
-                "kernel": f"k_score_mfma<{Mm},double>", "kernel_ms": k_ms, "cp_evals_per_launch": cp_per_launch}
+                "kernel": f"k_score_mfma<{Mm},double>", "kernel_ms": k_ms,
+                "kernel_ms_median": k_med, "kernel_ms_min": k_min, "cp_evals_per_launch": cp_per_launch}
     f_gpu = f.clone()
     lab_gpu = lab.cpu().numpy()
     f_np = f_gpu.cpu().numpy()
@@ -231,6 +248,8 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms,
+        "step_ms_median": float(np.median(step_ms)),
+        "step_ms_min": float(np.min(step_ms)),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
