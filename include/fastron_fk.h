@@ -147,8 +147,8 @@ fastron_status fastron_fk_score_prepared(const fastron_chain* chain, const fastr
  * keeps T = 1.01 (1 + 2 gamma R^2), an upper bound on t, within
  * T^(2 Mm) <= 2^120 and T <= 2^16, or T <= 2^8 for FASTRON_BF16_PLAIN, and
  * the tuning key "score.rational" is 1); 0 = one saturated reciprocal per
- * value (always for FASTRON_SCORE_VALU). Negative: FASTRON_EINVAL for a bad
- * chain, gamma <= 0 or unknown flags.                                       */
+ * value. Negative: FASTRON_EINVAL for a bad chain, gamma <= 0 or unknown
+ * flags.                                                                    */
 int32_t fastron_score_rational(const fastron_chain* chain, const fastron_cpoints* cp, float gamma, uint32_t flags);
 
 /* Convenience form: prepares the support set (a2) into stream-ordered scratch
@@ -332,12 +332,13 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *   "train.wave_groups" grid cap of the single-wave kernel, 1..512 (256)
  *   "train.blocks"      workgroups of the multi-wave grid, 0 = automatic
  *   "train.threads"     threads per multi-wave workgroup: 256, 512 or 1024
- *   "score.rational"    1 (default): the MFMA scoring kernels (FP32, BF16,
- *                       batched) sum a pair's 1/t^2 terms as one running
- *                       fraction (one reciprocal per pair) when a bound on
- *                       the chain's reach keeps the fraction in range (see
- *                       fastron_score_rational); 0: one saturated reciprocal
- *                       per value always. The two agree to FP32 rounding.
+ *   "score.rational"    1 (default): the scoring kernels (FP32 MFMA and
+ *                       VALU, BF16, batched) sum a pair's 1/t^2 terms as one
+ *                       running fraction (one reciprocal per pair) when a
+ *                       bound on the chain's reach keeps the fraction in
+ *                       range (see fastron_score_rational); 0: one saturated
+ *                       reciprocal per value always. The two agree to FP32
+ *                       rounding.
  *   "score.bf16_blocks" query blocks of 16 whose BF16 operands the BF16 score
  *                       kernel keeps resident per pass: 4 (default) or 2
  *                       (fewer registers, more waves; same results)

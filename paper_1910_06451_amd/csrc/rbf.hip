@@ -55,35 +55,45 @@ __global__ void __launch_bounds__(256) k_rbf_prep(const float* __restrict__ sx, 
   T[64 * KS + 16 + sl] = real ? alpha[s] : 0.f;
 }
 
-// One wave scores 64 queries (4 blocks of 16) against every tile.
+// One wave scores QB = 4 blocks of 16 queries against every tile. Each lane
+// reads the coordinates it feeds the contraction (and its query's norm)
+// straight from the query array once; the tile loop then touches only the
+// tiles. (Eight blocks per wave measured within 5 % at 1,000,000 queries and
+// slower at small N.)
 template <int KS>
 __global__ void __launch_bounds__(256) k_score_rbf(const float* __restrict__ q, int64_t N, int n, float gamma,
                                                     const float* __restrict__ tiles, int64_t ntiles,
                                                     float* __restrict__ f, int8_t* __restrict__ label) {
-  __shared__ float lds[4][64][4 * KS + 1];
+  constexpr int QB = 4;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int64_t qbase = ((int64_t)blockIdx.x * 4 + wave) * 64;
-  {
-    const int64_t j = qbase + lane;
-    float nrm = 0.f;
-    for (int k = 0; k < 4 * KS; ++k) {
-      float v = 0.f;
-      if (k < n && j < N) {
-        v = q[j * n + k];
-        nrm = fmaf(v, v, nrm);
-      }
-      lds[wave][lane][k] = v;
-    }
-    lds[wave][lane][n] = 1.0f + 0.5f * gamma * nrm;
-  }
-  __syncthreads();
+  const int64_t qbase = ((int64_t)blockIdx.x * 4 + wave) * (16 * QB);
   const int g = lane >> 4, col = lane & 15;
-  float B[4][KS];
+  float B[QB][KS];
 #pragma unroll
-  for (int b = 0; b < 4; ++b)
+  for (int b = 0; b < QB; ++b) {
+    const int64_t j = qbase + 16 * b + col;
+    float nrm = 0.f;
 #pragma unroll
-    for (int c = 0; c < KS; ++c) B[b][c] = lds[wave][16 * b + col][4 * c + g];
-  float fpart[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int c = 0; c < KS; ++c) B[b][c] = 0.f;
+    if (j < N) {
+#pragma unroll
+      for (int k = 0; k < 4 * KS; ++k) {
+        if (k < n) {
+          const float v = q[j * n + k];
+          nrm = fmaf(v, v, nrm);
+          if ((k & 3) == g) B[b][k >> 2] = v;
+        }
+      }
+    }
+    // entry n of B is c_q (1 past the end of the queries, whose outputs are not written)
+    const float cq = 1.0f + 0.5f * gamma * nrm;
+#pragma unroll
+    for (int c = 0; c < KS; ++c)
+      if (4 * c + g == n) B[b][c] = cq;
+  }
+  float fpart[QB];
+#pragma unroll
+  for (int b = 0; b < QB; ++b) fpart[b] = 0.f;
   for (int64_t t = 0; t < ntiles; ++t) {
     const float* T = tiles + t * rbf_tile_floats(KS);
     float Av[KS];
@@ -92,7 +102,7 @@ __global__ void __launch_bounds__(256) k_score_rbf(const float* __restrict__ q, 
     const rf4 Cv = *reinterpret_cast<const rf4*>(T + 64 * KS + 4 * g);
     const rf4 W = *reinterpret_cast<const rf4*>(T + 64 * KS + 16 + 4 * g);
 #pragma unroll
-    for (int b = 0; b < 4; ++b) {
+    for (int b = 0; b < QB; ++b) {
       rf4 d = Cv;
 #pragma unroll
       for (int c = 0; c < KS; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[c], B[b][c], d, 0, 0, 0);
@@ -106,7 +116,7 @@ __global__ void __launch_bounds__(256) k_score_rbf(const float* __restrict__ q, 
     }
   }
 #pragma unroll
-  for (int b = 0; b < 4; ++b) {
+  for (int b = 0; b < QB; ++b) {
     float v = fpart[b];
     v += __shfl_xor(v, 16);
     v += __shfl_xor(v, 32);

@@ -87,7 +87,7 @@ def test_score_parity(oracle_mod, dev, arm_name, S, N):
 def test_rational_and_saturated_sums(oracle_mod, dev, arm_name):
     """Both ways of summing 1/t^2 over a pair's control points (running fraction with one reciprocal per
     pair; saturated reciprocal per value) meet the bound against the oracle on the same inputs, single-model
-    and batched, and agree with each other to within the bound."""
+    (MFMA and VALU forms) and batched, and agree with each other to within the bound."""
     arm = wl.arm_3dof() if arm_name == "3dof" else wl.arm_7dof()
     gamma, S, N = 10.0, 517, 1999
     sq, al, q = _case(arm, S, N, gamma, f"rat_{arm_name}")
@@ -106,6 +106,8 @@ def test_rational_and_saturated_sums(oracle_mod, dev, arm_name):
             f, lab = api.fk_score_prepared(arm, model, q_d)
             out[rat] = f.cpu().numpy()
             print(rat, check_scores(out[rat], lab.cpu().numpy(), ref, tol))
+            fv, lv = api.fk_score_prepared(arm, model, q_d, flags=api.SCORE_VALU)
+            check_scores(fv.cpu().numpy(), lv.cpu().numpy(), ref, tol)
             b = api.Batch(arm, [S], [N], gamma)
             b.prepare(sq_d, al_d)
             fb, lb = b.score(q_d)
