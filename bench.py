@@ -831,7 +831,7 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras, checks)
         form["sign_agreement_vs_fp64"] = float(np.mean(form["labels"][idx] == sign_ref))
     cpu = {"value": n / dt, "unit": "checks/s", "cores": oracle.num_threads(), "kind": "oracle",
            "sample": f"{n} evenly spaced queries of the same workload (S={sq.shape[0]}), {dt:.1f} s",
-           "logical_cpus": os.cpu_count(), "cpu_model": _cpu_model()}
+           "logical_cpus": os.cpu_count(), "physical_cores": _physical_cores(), "cpu_model": _cpu_model()}
     # one thread on a 10,000-query subset (the paper's thread count is not stated)
     threads = oracle.num_threads()
     oracle.set_num_threads(1)
@@ -911,6 +911,26 @@ def _cpu_model():
     except OSError:
         pass
     return None
+
+
+def _physical_cores():
+    """Distinct (package, core) pairs among the CPUs this process may run on, from /proc/cpuinfo."""
+    try:
+        allowed = os.sched_getaffinity(0)
+        cores, cpu, pkg = set(), None, None
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "processor":
+                    cpu, pkg = int(val), None
+                elif key == "physical id":
+                    pkg = val
+                elif key == "core id" and cpu in allowed:
+                    cores.add((pkg, val))
+        return len(cores) or None
+    except (OSError, ValueError):
+        return None
 
 
 if __name__ == "__main__":
