@@ -309,6 +309,7 @@ def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
     t_fk = _event_ms(lambda: api.fk_points(arm, q), reps)
     t_gram = _event_ms(lambda: api.gram_update(P, 10.0, 12345, 0.5, F=F, want_kcol=False), reps)
     t_lab = _event_ms(lambda: api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False), 3)
+    t_clr = _event_ms(lambda: api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=True), 3)
     b_fk = N * (arm.n * 4 + arm.M * 12)
     b_gram = N * (arm.M * 12 + 8)
     hbm = 8.0e12
@@ -317,8 +318,10 @@ def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
                           "GB_per_s": b_fk / (t_fk * 1e-3) / 1e9, "frac_hbm": b_fk / (t_fk * 1e-3) / hbm},
             "gram_update": {"ms": t_gram, "points_per_s": N / (t_gram * 1e-3), "bytes": b_gram,
                             "GB_per_s": b_gram / (t_gram * 1e-3) / 1e9, "frac_hbm": b_gram / (t_gram * 1e-3) / hbm},
+            # (link, box) pairs decided per second, culled ones included
             "label_capsule_box": {"ms": t_lab, "configs_per_s": N / (t_lab * 1e-3),
-                                  "segment_box_tests_per_s": N * arm.n * 20 / (t_lab * 1e-3)}}
+                                  "link_box_pairs_per_s": N * arm.n * 20 / (t_lab * 1e-3),
+                                  "ms_with_clearance": t_clr, "configs_per_s_with_clearance": N / (t_clr * 1e-3)}}
 
 
 def precision_run(api, wl, arm, gamma, dev, checks, S=16_384, N=4_194_304, fp64_sample=1_048_576, reps=5):

@@ -12,6 +12,12 @@
 // t = 0 if g'(0) >= 0, t = 1 if g'(1) <= 0, and otherwise the root of g',
 // found here by bisection to double-precision resolution. Everything is FP64,
 // one thread per configuration.
+//
+// Culling: the gap between the box and the segment's bounding box is a lower
+// bound on their distance, so a (link, box) pair whose gap exceeds the best
+// distance found so far (plus 1e-12 m, far above the rounding of either
+// computation) cannot lower the minimum and is skipped. When only labels are
+// asked for, a configuration stops at its first touching pair.
 #include <cmath>
 
 #include "fastron_internal.h"
@@ -62,6 +68,18 @@ __device__ __forceinline__ double seg_box_d2(const double A[3], const double D[3
   return fmin(gl, gh);
 }
 
+// Squared gap between the box and the bounding box of the segment A -> A + D.
+__device__ __forceinline__ double bbox_gap2(const double A[3], const double D[3], const double* box) {
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 3; ++k) {
+    const double b = A[k] + D[k];
+    const double g = fmax(fmax(box[k] - fmax(A[k], b), fmin(A[k], b) - box[3 + k]), 0.0);
+    s += g * g;
+  }
+  return s;
+}
+
 __global__ void __launch_bounds__(256) k_label(ChainArgs c, const float* __restrict__ q, int64_t N, double radius,
                                                 const double* __restrict__ boxes, int nbox,
                                                 int8_t* __restrict__ label, float* __restrict__ clearance) {
@@ -92,9 +110,12 @@ __global__ void __launch_bounds__(256) k_label(ChainArgs c, const float* __restr
     zx = nzx; zy = nzy; zz = nzz;
     const double D[3] = {o[0] - A[0], o[1] - A[1], o[2] - A[2]};
     for (int b = 0; b < nbox; ++b) {
+      const double reach = best + radius + 1e-12;  // >= 1e-12: best >= -radius
+      if (bbox_gap2(A, D, boxes + 6 * b) > reach * reach) continue;
       const double d = sqrt(seg_box_d2(A, D, boxes + 6 * b)) - radius;
       best = fmin(best, d);
     }
+    if (!clearance && best <= 0.0) break;
   }
   label[j] = (best <= 0.0) ? (int8_t)1 : (int8_t)-1;
   if (clearance) clearance[j] = (float)best;

@@ -3,7 +3,8 @@
 Both decide 'distance <= radius' in FP64, with different algorithms (the
 oracle minimises the piecewise quadratic exactly, the device bisects the
 derivative), so labels must agree bit for bit except where the clearance is
-within rounding of zero."""
+within rounding of zero. The label-only mode (early exit at the first touching
+pair) must give the same labels as the mode that also returns the clearance."""
 import numpy as np
 import pytest
 import torch
@@ -28,6 +29,9 @@ def test_labels_match_oracle(oracle_mod, dev, arm_name, N, n_cubes):
     announce(f"label {arm_name} N={N} cubes={n_cubes}")
     lab, clr = api.label_capsule_box(arm, torch.from_numpy(q).to(dev), arm.radius, lo, hi)
     lab, clr = lab.cpu().numpy(), clr.cpu().numpy()
+    # labels alone: the kernel stops at a configuration's first touching pair; same decisions
+    lab_only, _ = api.label_capsule_box(arm, torch.from_numpy(q).to(dev), arm.radius, lo, hi, want_clearance=False)
+    np.testing.assert_array_equal(lab_only.cpu().numpy(), lab)
     ref, ref_clr = oracle_mod.capsule_box_labels(oracle_dh(oracle_mod, arm), q.astype(np.float64), arm.radius, lo,
                                                  hi)
     near = np.abs(ref_clr) < 1e-9
