@@ -51,3 +51,42 @@ def test_fk_points_empty(dev):
     arm = wl.arm_7dof()
     P = api.fk_points(arm, torch.zeros((0, 7), dtype=torch.float32, device=dev))
     assert P.shape == (0, 8, 3)
+
+
+@pytest.mark.parametrize("n,prismatic", [(8, (2, 5)), (16, ()), (7, (6,))])
+def test_fk_points_long_general_chains(oracle_mod, dev, n, prismatic):
+    """Chains of 7 to 16 joints run the FP64 chain with every joint's sine and cosine computed up front: angle
+    offsets, prismatic joints, a base transform, repeated frames, the base frame and point offsets; each
+    coordinate within one float32 ulp of the oracle's FP64 result."""
+    g = wl.rng(f"fk_long_{n}")
+    frames = np.concatenate([[0], np.arange(max(1, n - 12), n + 1), [n, n // 2]]).astype(np.int32)  # <= 16 points
+    arm = wl.Arm(a=g.uniform(0.05, 0.2, n), alpha=g.choice(np.array([0.0, np.pi / 2, -np.pi / 2]), size=n),
+                 d=g.uniform(-0.1, 0.1, n), theta=g.uniform(-0.5, 0.5, n),
+                 joint_type=np.isin(np.arange(n), prismatic).astype(np.int32), frames=frames,
+                 offsets=g.uniform(-0.05, 0.05, (frames.shape[0], 3)))
+    base = np.eye(4)
+    base[:3, :3] = [[0, 0, 1], [1, 0, 0], [0, 1, 0]]
+    base[:3, 3] = [0.2, -0.1, 0.3]
+    arm.base = base
+    q = wl.configs(f"fk_long_{n}/q", 4099, n, lo=-3.0, hi=3.0)
+    announce(f"fk_points long chain n={n} prismatic={prismatic}")
+    P = api.fk_points(arm, torch.from_numpy(q).to(dev)).cpu().numpy().astype(np.float64)
+    ref = oracle_mod.control_points(oracle_dh(oracle_mod, arm), arm.frames, q.astype(np.float64),
+                                    offset=arm.offsets, base=base)
+    err = np.abs(P - ref)
+    assert np.all(err <= _ulp32(ref) + 1e-30), err.max()
+
+
+def test_fk_points_large_joint_values(oracle_mod, dev):
+    """Joint values beyond the range of the branch-free angle reduction (|theta| > 1e5) take the library sine
+    and cosine; ordinary lanes of the same wave keep the fast path."""
+    arm = wl.arm_7dof()
+    q = wl.configs("fk_large/q", 1000, arm.n)
+    q[::7, 3] = np.float32(3.0e5)
+    q[1::11, 0] = np.float32(-1.0e7)
+    q[2::13, 6] = np.float32(9.99e4)  # just inside the fast range
+    announce("fk_points large joint values")
+    P = api.fk_points(arm, torch.from_numpy(q).to(dev)).cpu().numpy().astype(np.float64)
+    ref = oracle_mod.control_points(oracle_dh(oracle_mod, arm), arm.frames, q.astype(np.float64))
+    err = np.abs(P - ref)
+    assert np.all(err <= _ulp32(ref) + 1e-30), err.max()
