@@ -316,10 +316,14 @@ fastron_status fastron_active_samples(const float* support_q, const float* alpha
  * Stands in for the ground-truth collision checker of Section IV: link i is a
  * capsule of radius `radius` around the segment between the origins of
  * frames i-1 and i; obstacles are axis-aligned boxes, a DEVICE array of nbox
- * rows (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z) in double, 0 <= nbox <= 4096.
- * label[j] = +1 if some capsule touches some box (exact segment-box distance
- * <= radius), else -1. clearance[j] (may be NULL) = min distance - radius.
- * Computed in FP64.                                                         */
+ * rows (lo_x, lo_y, lo_z, hi_x, hi_y, hi_z) in double, 0 <= nbox <= 4096,
+ * with lo <= hi on every axis (the caller's duty: the array is not read on
+ * the host; an inverted box gives unspecified labels). label[j] = +1 if some
+ * capsule touches some box (exact segment-box distance <= radius), else -1.
+ * clearance[j] (may be NULL) = min distance - radius. Computed in FP64;
+ * pairs that a bounding-box bound shows cannot lower the minimum are
+ * skipped, and without clearance a configuration stops at its first
+ * touching pair (same labels).                                              */
 fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float* q, int64_t N, double radius,
                                          const double* boxes, int32_t nbox, int8_t* label, float* clearance,
                                          void* stream);

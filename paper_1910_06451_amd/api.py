@@ -305,12 +305,14 @@ def train_batch(P: torch.Tensor, y: torch.Tensor, offsets, gamma: float, beta: f
 
 def label_capsule_box(arm, q: torch.Tensor, radius: float, boxes_lo, boxes_hi, want_clearance=True):
     """Geometric labels (+1 collision / -1 free, int8) and clearance (float32, min distance - radius)."""
+    lo = np.asarray(boxes_lo, dtype=np.float64).reshape(-1, 3)
+    hi = np.asarray(boxes_hi, dtype=np.float64).reshape(-1, 3)
+    if lo.shape != hi.shape or np.any(~(lo <= hi)):
+        raise ValueError("boxes need lo <= hi on every axis and as many lo as hi corners")
     hc = _chain(arm)
     _dev(q, torch.float32, "q")
     if q.dim() != 2 or q.shape[1] != hc.n:
         raise ValueError(f"q must be (N, {hc.n})")
-    lo = np.asarray(boxes_lo, dtype=np.float64).reshape(-1, 3)
-    hi = np.asarray(boxes_hi, dtype=np.float64).reshape(-1, 3)
     boxes = torch.from_numpy(np.ascontiguousarray(np.concatenate([lo, hi], axis=1))).to(q.device)
     N = q.shape[0]
     lab = torch.empty(N, dtype=torch.int8, device=q.device)

@@ -233,3 +233,23 @@ def test_score_form_choice(lib):
         api.score_rational(arm, -1.0)
     with pytest.raises(Exception):
         api.score_rational(arm, 10.0, 0x40)
+
+
+def test_label_binding_rejects_inverted_boxes():
+    """The labeller's bounding-box culling assumes lo <= hi on every axis; the binding checks the host-side
+    corners before any device work (the C entry point cannot read the device array on the host)."""
+    import torch
+    from paper_1910_06451_amd import api
+    arm = wl.arm_7dof()
+    q = torch.zeros((4, arm.n), dtype=torch.float32)
+    lo = np.array([[0.0, 0.0, 0.0], [0.2, 0.1, 0.0]])
+    hi = np.array([[0.1, 0.1, 0.1], [0.1, 0.3, 0.2]])  # second box inverted along x
+    with pytest.raises(ValueError, match="lo <= hi"):
+        api.label_capsule_box(arm, q, arm.radius, lo, hi)
+    with pytest.raises(ValueError, match="lo <= hi"):
+        api.label_capsule_box(arm, q, arm.radius, lo[:1], hi)
+    with pytest.raises(ValueError, match="lo <= hi"):
+        api.label_capsule_box(arm, q, arm.radius, np.array([[np.nan, 0.0, 0.0]]), hi[:1])
+    # well-formed boxes pass the check and reach the device-tensor check
+    with pytest.raises(ValueError, match="device tensor"):
+        api.label_capsule_box(arm, q, arm.radius, lo[:1], hi[:1])
