@@ -130,6 +130,8 @@ bool rational_sum_ok(const ChainArgs& c, float gamma, double t_limit) {
 // through LDS: the block reads its 256 n floats and writes its 256 x 3M
 // floats with consecutive lanes on consecutive words, and each thread works
 // on its own row in LDS. Dynamic LDS: 256 (n + 3M) floats (at most 64 KB).
+// Serves chains below 7 joints (FP32 chain); longer chains run
+// k_fk_points_fixed below.
 template <typename R>
 __global__ void __launch_bounds__(256) k_fk_points(ChainArgs c, const float* __restrict__ q, int64_t N,
                                                     float* __restrict__ P) {
@@ -520,7 +522,7 @@ fastron_status fastron_fk_points(const fastron_chain* chain, const fastron_cpoin
     switch (c.n) {
       FASTRON_FK_FIXED(7) FASTRON_FK_FIXED(8) FASTRON_FK_FIXED(9) FASTRON_FK_FIXED(10) FASTRON_FK_FIXED(11)
       FASTRON_FK_FIXED(12) FASTRON_FK_FIXED(13) FASTRON_FK_FIXED(14) FASTRON_FK_FIXED(15) FASTRON_FK_FIXED(16)
-      default: hipLaunchKernelGGL(k_fk_points<double>, grid, dim3(256), lds, s, c, q, N, P); break;
+      default: return fail(FASTRON_EINVAL, "n = %d joints outside [7, 16]", c.n);  // pack_chain bounds n
     }
   } else
     hipLaunchKernelGGL(k_fk_points<float>, grid, dim3(256), lds, s, c, q, N, P);
