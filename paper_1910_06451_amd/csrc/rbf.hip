@@ -94,26 +94,43 @@ __global__ void __launch_bounds__(256) k_score_rbf(const float* __restrict__ q, 
   float fpart[QB];
 #pragma unroll
   for (int b = 0; b < QB; ++b) fpart[b] = 0.f;
-  for (int64_t t = 0; t < ntiles; ++t) {
+  // Software pipeline: the MFMAs of tile t + 1 are issued before the vector
+  // work on tile t's results, so that work does not wait on the matrix
+  // unit's latency. The last iteration recomputes the last tile (in range,
+  // results unused) instead of branching.
+  auto contract = [&](int64_t t, rf4 (&d)[QB], rf4& W) {
     const float* T = tiles + t * rbf_tile_floats(KS);
     float Av[KS];
 #pragma unroll
     for (int c = 0; c < KS; ++c) Av[c] = T[c * 64 + lane];
     const rf4 Cv = *reinterpret_cast<const rf4*>(T + 64 * KS + 4 * g);
-    const rf4 W = *reinterpret_cast<const rf4*>(T + 64 * KS + 16 + 4 * g);
+    W = *reinterpret_cast<const rf4*>(T + 64 * KS + 16 + 4 * g);
 #pragma unroll
     for (int b = 0; b < QB; ++b) {
-      rf4 d = Cv;
+      rf4 x = Cv;
 #pragma unroll
-      for (int c = 0; c < KS; ++c) d = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[c], B[b][c], d, 0, 0, 0);
+      for (int c = 0; c < KS; ++c) x = __builtin_amdgcn_mfma_f32_16x16x4f32(Av[c], B[b][c], x, 0, 0, 0);
+      d[b] = x;
+    }
+  };
+  rf4 dcur[QB], Wcur;
+  contract(0, dcur, Wcur);
+  for (int64_t t = 0; t < ntiles; ++t) {
+    rf4 dnxt[QB], Wnxt;
+    contract(t + 1 < ntiles ? t + 1 : t, dnxt, Wnxt);
+#pragma unroll
+    for (int b = 0; b < QB; ++b) {
       float acc = fpart[b];
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float x = rbf_rcp_sat(d[r]);
-        acc = fmaf(W[r], x * x, acc);
+        const float x = rbf_rcp_sat(dcur[b][r]);
+        acc = fmaf(Wcur[r], x * x, acc);
       }
       fpart[b] = acc;
     }
+#pragma unroll
+    for (int b = 0; b < QB; ++b) dcur[b] = dnxt[b];
+    Wcur = Wnxt;
   }
 #pragma unroll
   for (int b = 0; b < QB; ++b) {
