@@ -55,3 +55,53 @@ def test_adam_first_step_closed_form():
     np.testing.assert_allclose(new[0], p[0] - 1e-2 * np.sign(grad[0]), atol=1e-8)
     np.testing.assert_allclose(m[0], 0.1 * grad[0])
     np.testing.assert_allclose(v[0], 0.001 * grad[0] ** 2)
+
+
+def _golden(name):
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        return json.load(fh)
+
+
+def test_forward_tiny_network_by_hand():
+    """Standardisation, both hidden layers and the head against a network worked by hand
+    (golden/mlp_tiny_forward.json): every hidden unit is active in one sample and inactive in the other."""
+    gd = _golden("mlp_tiny_forward.json")
+    params = [np.array(gd[k], np.float64) for k in ("W1", "b1", "W2", "b2", "w3")] + [np.array(gd["b3"])]
+    z, (xs, a1, h1, a2, h2) = mo.forward(params, np.array(gd["x"]), np.array(gd["mu"]), np.array(gd["sd"]))
+    np.testing.assert_array_equal(xs, np.array(gd["xs"]))
+    np.testing.assert_array_equal(a1, np.array(gd["a1"]))
+    np.testing.assert_array_equal(a2, np.array(gd["a2"]))
+    np.testing.assert_array_equal(h1, np.maximum(np.array(gd["a1"]), 0.0))
+    np.testing.assert_array_equal(h2, np.maximum(np.array(gd["a2"]), 0.0))
+    np.testing.assert_array_equal(z, np.array(gd["z"]))
+
+
+def test_adam_three_steps_by_hand():
+    """Three Adam steps with a varying gradient against exact fractions (golden/adam_three_steps.json):
+    the moments, both bias corrections (1 - beta^t at t = 1, 2, 3) and the weight after each step."""
+    from fractions import Fraction
+
+    gd = _golden("adam_three_steps.json")
+    p = [np.array([gd["p0"]])]
+    m = [np.zeros(1)]
+    v = [np.zeros(1)]
+    for k, (g, st) in enumerate(zip(gd["grads"], gd["steps"])):
+        p, m, v = mo.adam_step(p, [np.array([g])], m, v, step=st["t"], lr=gd["lr"], beta1=gd["beta1"],
+                               beta2=gd["beta2"], eps=gd["eps"])
+        assert abs(m[0][0] - float(Fraction(st["m"]))) <= 1e-15 * abs(float(Fraction(st["m"])))
+        assert abs(v[0][0] - float(Fraction(st["v"]))) <= 1e-15 * abs(float(Fraction(st["v"])))
+        assert abs(p[0][0] - gd["p"][k]) <= 1e-15, (st["t"], p[0][0], gd["p"][k])
+
+
+def test_adam_constant_gradient_moves_by_lr():
+    """With a constant gradient g the bias-corrected moments are exactly g and g^2 at every step, so each step
+    moves every weight by lr |g| / (|g| + eps); a wrong bias-correction power breaks this from step 2 on."""
+    g = np.array([[0.3, -1.7], [2.5, -0.01]])
+    p = [np.zeros((2, 2))]
+    m = [np.zeros((2, 2))]
+    v = [np.zeros((2, 2))]
+    for t in range(1, 6):
+        p, m, v = mo.adam_step(p, [g], m, v, step=t, lr=1e-2)
+        np.testing.assert_allclose(p[0], -t * 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
