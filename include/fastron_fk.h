@@ -158,18 +158,33 @@ fastron_status fastron_fk_score(const fastron_chain* chain, const fastron_cpoint
                                 int8_t* label, uint32_t flags, void* stream);
 
 /* ---- a4: Gram column and F update (Section III-B, Eq. 8; Algorithm 1) ----
- * kcol[j] = K_FK(X_j, X_i) for all j, and F[j] += delta_alpha * kcol[j].
- * P [N][M][3] are the control points of the training set (fastron_fk_points
- * output). F (in/out) and kcol (out) may each be NULL (not both).           */
-fastron_status fastron_gram_update(const float* P, int64_t N, int32_t M, float gamma, int64_t i, float delta_alpha,
-                                   float* F, float* kcol, void* stream);
+ * kcol[j] = K_FK(X_j, X_i) for all j, and F[j] += delta_alpha * kcol[j]
+ * (delta_alpha = b_i y_i - F_i for an add or adjust, -alpha_i for a removal).
+ * X [N][n] float are the training configurations (device); their control
+ * points are computed with fastron_fk_points into stream-ordered scratch of
+ * N * M * 3 floats that is released before the call returns. F (in/out,
+ * [N]) and kcol (out, [N]) may each be NULL (not both). Errors:
+ * FASTRON_EINVAL for N < 1, i outside [0, N), gamma <= 0 or non-finite
+ * delta_alpha (nothing launched); FASTRON_ENOMEM if the scratch cannot be
+ * allocated. Asynchronous on `stream`.                                      */
+fastron_status fastron_gram_update(const fastron_chain* chain, const fastron_cpoints* cp, const float* X, int64_t N,
+                                   float gamma, int64_t i, float delta_alpha, float* F, float* kcol, void* stream);
+
+/* Points form of the same update: P [N][M][3] float are the training set's
+ * control points (fastron_fk_points output), so repeated columns over one
+ * training set do not repeat its forward kinematics. Same results as
+ * fastron_gram_update on the configurations P was computed from.           */
+fastron_status fastron_gram_update_points(const float* P, int64_t N, int32_t M, float gamma, int64_t i,
+                                          float delta_alpha, float* F, float* kcol, void* stream);
 
 /* ---- a5: Fastron model update, Algorithm 1 (Section III-B) --------------
  * Runs Algorithm 1 on the device: greedy add/adjust of the most negative
  * margin y_i F_i (lowest index on ties), removal of redundant support points
  * (largest y_i (F_i - alpha_i) over alpha_i != 0, lowest index on ties),
  * caps iter_max and s_max, then removeNonsupportPoints.
- *   P [N][M][3] float   control points of the training set
+ *   X [N][n] float      training configurations (device); their control
+ *                       points go into stream-ordered scratch of N * M * 3
+ *                       floats, released before the call returns
  *   y [N] int8          +1 in collision, -1 free
  *   alpha, F [N]        in/out; zeros = fresh model, else a previous model
  *                       (loadPreviousModel: F must equal K alpha)
@@ -177,21 +192,41 @@ fastron_status fastron_gram_update(const float* P, int64_t N, int32_t M, float g
  *   n_support, updates  HOST out: |S| and the number of add/remove updates
  * beta >= 1 is the conditional bias (Eq. 5). The call synchronises `stream`.
  * Returns FASTRON_OK when the loop ended by break, FASTRON_NOT_CONVERGED when
- * iter_max updates were made first. fastron_train_f64 keeps alpha and F in
- * double and evaluates the kernel in FP64 (reference-precision mode).
- * trace_action / trace_index (device int32 [trace_cap], may be NULL) record
- * the first trace_cap updates: action 1 = add, 2 = remove.                  */
-fastron_status fastron_train(const float* P, const int8_t* y, int64_t N, int32_t M, float gamma, float beta,
-                             int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
-                             int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
-                             int64_t trace_cap, void* stream);
-fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma, double beta,
-                                 int64_t iter_max, int64_t s_max, double* alpha, double* F, int32_t* support_idx,
-                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
-                                 int64_t trace_cap, void* stream);
+ * iter_max updates were made first (outputs are a valid partial model),
+ * FASTRON_EINVAL for bad arguments (nothing launched), FASTRON_EDEVICE if the
+ * device-side record exchange exceeded its wait budget. fastron_train_f64
+ * keeps alpha and F in double and evaluates the kernel in FP64
+ * (reference-precision mode). trace_action / trace_index (device int32
+ * [trace_cap], may be NULL) record the first trace_cap updates: action 1 =
+ * add, 2 = remove.                                                          */
+fastron_status fastron_train(const fastron_chain* chain, const fastron_cpoints* cp, const float* X, const int8_t* y,
+                             int64_t N, float gamma, float beta, int64_t iter_max, int64_t s_max, float* alpha,
+                             float* F, int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                             int32_t* trace_action, int32_t* trace_index, int64_t trace_cap, void* stream);
+fastron_status fastron_train_f64(const fastron_chain* chain, const fastron_cpoints* cp, const float* X,
+                                 const int8_t* y, int64_t N, double gamma, double beta, int64_t iter_max,
+                                 int64_t s_max, double* alpha, double* F, int32_t* support_idx, int64_t* n_support,
+                                 int64_t* updates, int32_t* trace_action, int32_t* trace_index, int64_t trace_cap,
+                                 void* stream);
+
+/* Points forms: the same update on P [N][M][3] float control points
+ * (fastron_fk_points output) instead of configurations -- for callers that
+ * keep the training set's control points (the moving-obstacle updates
+ * re-train on rows whose points are already known). Bit-identical to
+ * fastron_train / fastron_train_f64 on the configurations P came from.      */
+fastron_status fastron_train_points(const float* P, const int8_t* y, int64_t N, int32_t M, float gamma, float beta,
+                                    int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
+                                    int64_t* n_support, int64_t* updates, int32_t* trace_action,
+                                    int32_t* trace_index, int64_t trace_cap, void* stream);
+fastron_status fastron_train_points_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma,
+                                        double beta, int64_t iter_max, int64_t s_max, double* alpha, double* F,
+                                        int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                                        int32_t* trace_action, int32_t* trace_index, int64_t trace_cap,
+                                        void* stream);
 
 /* Several independent training sets (Algorithm 1 each, FP32) in one launch,
- * e.g. the environments of the batched form after their obstacles moved:
+ * e.g. the environments of the batched form after their obstacles moved
+ * (points form: P [N_total][M][3] from fastron_fk_points):
  * set e is rows offsets[e] .. offsets[e+1] - 1 of P, y, alpha and F
  * (offsets: HOST array of E + 1 int64, strictly increasing from 0). The sets
  * advance concurrently, each with its own exchange, and each ends exactly as
@@ -215,10 +250,13 @@ fastron_status fastron_train_batch(const float* P, const int8_t* y, int32_t E, c
  *                           ONE persistent launch (work items claimed in
  *                           longest-first order from a device counter)
  *   fastron_batch_autotune  times the work-item shapes (16, 32, 64 queries)
- *                           on these arguments and keeps the fastest; syncs
+ *                           on these arguments and keeps the fastest; syncs.
+ *                           It discards a graph captured before it.
  *   fastron_batch_capture   records {counter reset, scoring launch} with these
  *                           pointers into a HIP graph on `stream` (non-null)
- *   fastron_batch_replay    launches the captured graph
+ *   fastron_batch_replay    launches the captured graph; FASTRON_EINVAL when
+ *                           none is held (never captured, or discarded by a
+ *                           later autotune)
  * Results equal fastron_fk_score_prepared on each environment's model.     */
 typedef struct fastron_batch fastron_batch;
 fastron_status fastron_batch_create(const fastron_chain* chain, const fastron_cpoints* cp, int32_t E,
@@ -286,7 +324,7 @@ fastron_status fastron_rbf_score(const float* support_x, const float* alpha, int
 
 /* fastron_rbf_train / _f64: Algorithm 1 (Section III-B) with that kernel on
  * X [N][n] float (device) and labels y [N] int8; arguments, outputs, warm
- * start, caps and status as for fastron_train / fastron_train_f64 with the
+ * start, caps and status as for fastron_train_points / _f64 with the
  * configurations in place of the control points. The FP64 form follows the
  * FP64 oracle step for step (trace arrays as in fastron_train_f64).        */
 fastron_status fastron_rbf_train(const float* X, const int8_t* y, int64_t N, int32_t n, float gamma, float beta,
@@ -307,7 +345,7 @@ fastron_status fastron_rbf_train_f64(const float* X, const int8_t* y, int64_t N,
  * alpha_out (may be NULL) as many floats. All arrays are device memory. The
  * update then labels every row (fastron_label_capsule_box), takes F = the
  * current model's score of every row (fastron_fk_score; F = K alpha) and
- * runs fastron_train from (alpha_out, F).                                  */
+ * runs fastron_train_points from (alpha_out, F) on the rows' control points.                                  */
 fastron_status fastron_active_samples(const float* support_q, const float* alpha, int64_t S, int32_t n,
                                       const float* noise, int32_t k, const float* explore, int64_t E, float* X_out,
                                       float* alpha_out, void* stream);

@@ -32,7 +32,8 @@ BF16_SPLIT3 = 0x20
 
 EXPORTED = [
     "fastron_control_point_frames", "fastron_fk_points", "fastron_model_bytes", "fastron_support_prep", "fastron_fk_score_prepared",
-    "fastron_score_rational", "fastron_fk_score", "fastron_gram_update", "fastron_train", "fastron_train_f64", "fastron_train_batch", "fastron_label_capsule_box",
+    "fastron_score_rational", "fastron_fk_score", "fastron_gram_update", "fastron_gram_update_points", "fastron_train", "fastron_train_f64",
+    "fastron_train_points", "fastron_train_points_f64", "fastron_train_batch", "fastron_label_capsule_box",
     "fastron_tune_set", "fastron_tune_get", "fastron_last_error", "fastron_version", "fastron_batch_create",
     "fastron_batch_prepare", "fastron_batch_score", "fastron_batch_autotune", "fastron_batch_capture",
     "fastron_batch_replay", "fastron_batch_tile_queries", "fastron_batch_destroy", "fastron_mlp_create",
@@ -94,9 +95,15 @@ def lib():
         "fastron_fk_score_prepared": ([ch, cp, md, vp, i64, vp, vp, ctypes.c_uint32, vp], i32),
         "fastron_score_rational": ([ch, cp, f32, ctypes.c_uint32], i32),
         "fastron_fk_score": ([ch, cp, vp, vp, i64, f32, vp, i64, vp, vp, ctypes.c_uint32, vp], i32),
-        "fastron_gram_update": ([vp, i64, i32, f32, i64, f32, vp, vp, vp], i32),
-        "fastron_train": ([vp, vp, i64, i32, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp], i32),
-        "fastron_train_f64": ([vp, vp, i64, i32, f64, f64, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp], i32),
+        "fastron_gram_update": ([ch, cp, vp, i64, f32, i64, f32, vp, vp, vp], i32),
+        "fastron_gram_update_points": ([vp, i64, i32, f32, i64, f32, vp, vp, vp], i32),
+        "fastron_train": ([ch, cp, vp, vp, i64, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp], i32),
+        "fastron_train_f64": ([ch, cp, vp, vp, i64, f64, f64, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp],
+                              i32),
+        "fastron_train_points": ([vp, vp, i64, i32, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp],
+                                 i32),
+        "fastron_train_points_f64": ([vp, vp, i64, i32, f64, f64, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64,
+                                      vp], i32),
         "fastron_train_batch": ([vp, vp, i32, pi64, i32, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp], i32),
         "fastron_label_capsule_box": ([ch, vp, i64, f64, vp, i32, vp, vp, vp], i32),
         "fastron_batch_create": ([ch, cp, i32, pi64, pi64, f32, ctypes.POINTER(vp)], i32),

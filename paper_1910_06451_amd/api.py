@@ -7,6 +7,7 @@ of the method happens here.
 from __future__ import annotations
 
 import ctypes
+import sys
 
 import numpy as np
 import torch
@@ -15,7 +16,8 @@ from . import _native as nat
 from ._native import HostChain, check
 
 __all__ = [
-    "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "train", "train_batch",
+    "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "gram_update_points", "train", "train_points",
+    "train_batch",
     "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set", "active_samples", "active_update",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
@@ -160,47 +162,62 @@ def fk_score(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, q:
     return f, lab
 
 
-def gram_update(P: torch.Tensor, gamma: float, i: int, delta_alpha: float, F: torch.Tensor | None = None,
-                want_kcol=True):
-    """kcol = K_FK(X_j, X_i) over j; F += delta_alpha * kcol (in place). Returns kcol (or None)."""
+def gram_update_points(P: torch.Tensor, gamma: float, i: int, delta_alpha: float, F: torch.Tensor | None = None,
+                       want_kcol=True):
+    """kcol = K_FK(X_j, X_i) over j on control points P (N, M, 3); F += delta_alpha * kcol (in place).
+    Returns kcol (or None)."""
     _dev(P, torch.float32, "P")
     if P.dim() != 3 or P.shape[2] != 3:
         raise ValueError("P must be (N, M, 3)")
     N, M = P.shape[0], P.shape[1]
+    F = _gram_F(F, N)
+    kcol = torch.empty(N, dtype=torch.float32, device=P.device) if want_kcol else None
+    check(nat.lib().fastron_gram_update_points(_ptr(P), N, M, float(gamma), int(i), float(delta_alpha), _ptr(F),
+                                               _ptr(kcol), _stream()))
+    return kcol
+
+
+def gram_update(arm, X: torch.Tensor, gamma: float, i: int, delta_alpha: float, F: torch.Tensor | None = None,
+                want_kcol=True):
+    """The same update on configurations X (N, n): their control points are computed by the library."""
+    hc = _chain(arm)
+    _dev(X, torch.float32, "X")
+    if X.dim() != 2 or X.shape[1] != hc.n:
+        raise ValueError(f"X must be (N, {hc.n})")
+    N = X.shape[0]
+    F = _gram_F(F, N)
+    kcol = torch.empty(N, dtype=torch.float32, device=X.device) if want_kcol else None
+    check(nat.lib().fastron_gram_update(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), _ptr(X), N, float(gamma),
+                                        int(i), float(delta_alpha), _ptr(F), _ptr(kcol), _stream()))
+    return kcol
+
+
+def _gram_F(F, N):
     if F is not None:
         _dev(F, torch.float32, "F")
         if F.shape != (N,):
             raise ValueError("F must be (N,)")
-    kcol = torch.empty(N, dtype=torch.float32, device=P.device) if want_kcol else None
-    check(nat.lib().fastron_gram_update(_ptr(P), N, M, float(gamma), int(i), float(delta_alpha), _ptr(F),
-                                        _ptr(kcol), _stream()))
-    return kcol
+    return F
 
 
-def train(P: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, iter_max: int | None = None,
-          s_max: int | None = None, alpha: torch.Tensor | None = None, F: torch.Tensor | None = None,
-          fp64: bool = False, trace_cap: int = 0):
-    """Algorithm 1 on the device. Returns dict(alpha, F, support, converged, updates[, trace])."""
-    _dev(P, torch.float32, "P")
+def _train_state(N, device, y, alpha, F, fp64, iter_max, s_max, trace_cap):
     _dev(y, torch.int8, "y")
-    N, M = P.shape[0], P.shape[1]
-    if P.dim() != 3 or P.shape[2] != 3 or y.shape != (N,):
-        raise ValueError("P must be (N, M, 3) and y (N,)")
+    if y.shape != (N,):
+        raise ValueError("y must hold one label per training row")
     dt = torch.float64 if fp64 else torch.float32
-    alpha = torch.zeros(N, dtype=dt, device=P.device) if alpha is None else alpha.clone()
-    F = torch.zeros(N, dtype=dt, device=P.device) if F is None else F.clone()
+    alpha = torch.zeros(N, dtype=dt, device=device) if alpha is None else alpha.clone()
+    F = torch.zeros(N, dtype=dt, device=device) if F is None else F.clone()
     _dev(alpha, dt, "alpha")
     _dev(F, dt, "F")
     iter_max = 20 * max(N, 1) if iter_max is None else int(iter_max)
     s_max = max(N, 1) if s_max is None else int(s_max)
-    support = torch.empty(max(N, 1), dtype=torch.int32, device=P.device)
-    tr_a = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=P.device) if trace_cap else None
-    tr_i = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=P.device) if trace_cap else None
-    ns = ctypes.c_int64(0)
-    upd = ctypes.c_int64(0)
-    fn = nat.lib().fastron_train_f64 if fp64 else nat.lib().fastron_train
-    st = fn(_ptr(P), _ptr(y), N, M, float(gamma), float(beta), iter_max, s_max, _ptr(alpha), _ptr(F),
-            _ptr(support), ctypes.byref(ns), ctypes.byref(upd), _ptr(tr_a), _ptr(tr_i), int(trace_cap), _stream())
+    support = torch.empty(max(N, 1), dtype=torch.int32, device=device)
+    tr_a = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=device) if trace_cap else None
+    tr_i = torch.zeros(max(trace_cap, 1), dtype=torch.int32, device=device) if trace_cap else None
+    return alpha, F, iter_max, s_max, support, tr_a, tr_i
+
+
+def _train_result(st, alpha, F, support, ns, upd, tr_a, tr_i, trace_cap):
     check(st, allow=(nat.FASTRON_OK, nat.FASTRON_NOT_CONVERGED))
     out = dict(alpha=alpha, F=F, support=support[: ns.value], converged=(st == nat.FASTRON_OK), updates=upd.value)
     if trace_cap:
@@ -208,6 +225,46 @@ def train(P: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, ite
         out["trace_action"] = tr_a[:k]
         out["trace_index"] = tr_i[:k]
     return out
+
+
+def train_points(P: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, iter_max: int | None = None,
+                 s_max: int | None = None, alpha: torch.Tensor | None = None, F: torch.Tensor | None = None,
+                 fp64: bool = False, trace_cap: int = 0):
+    """Algorithm 1 on the device over control points P (N, M, 3).
+    Returns dict(alpha, F, support, converged, updates[, trace])."""
+    _dev(P, torch.float32, "P")
+    if P.dim() != 3 or P.shape[2] != 3:
+        raise ValueError("P must be (N, M, 3)")
+    N, M = P.shape[0], P.shape[1]
+    alpha, F, iter_max, s_max, support, tr_a, tr_i = _train_state(N, P.device, y, alpha, F, fp64, iter_max, s_max,
+                                                                  trace_cap)
+    ns = ctypes.c_int64(0)
+    upd = ctypes.c_int64(0)
+    fn = nat.lib().fastron_train_points_f64 if fp64 else nat.lib().fastron_train_points
+    st = fn(_ptr(P), _ptr(y), N, M, float(gamma), float(beta), iter_max, s_max, _ptr(alpha), _ptr(F),
+            _ptr(support), ctypes.byref(ns), ctypes.byref(upd), _ptr(tr_a), _ptr(tr_i), int(trace_cap), _stream())
+    return _train_result(st, alpha, F, support, ns, upd, tr_a, tr_i, trace_cap)
+
+
+def train(arm, X: torch.Tensor, y: torch.Tensor, gamma: float, beta: float = 1.0, iter_max: int | None = None,
+          s_max: int | None = None, alpha: torch.Tensor | None = None, F: torch.Tensor | None = None,
+          fp64: bool = False, trace_cap: int = 0):
+    """Algorithm 1 on the device over configurations X (N, n) of the arm (its control points computed by the
+    library). Returns the same dict as train_points()."""
+    hc = _chain(arm)
+    _dev(X, torch.float32, "X")
+    if X.dim() != 2 or X.shape[1] != hc.n:
+        raise ValueError(f"X must be (N, {hc.n})")
+    N = X.shape[0]
+    alpha, F, iter_max, s_max, support, tr_a, tr_i = _train_state(N, X.device, y, alpha, F, fp64, iter_max, s_max,
+                                                                  trace_cap)
+    ns = ctypes.c_int64(0)
+    upd = ctypes.c_int64(0)
+    fn = nat.lib().fastron_train_f64 if fp64 else nat.lib().fastron_train
+    st = fn(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), _ptr(X), _ptr(y), N, float(gamma), float(beta),
+            iter_max, s_max, _ptr(alpha), _ptr(F), _ptr(support), ctypes.byref(ns), ctypes.byref(upd), _ptr(tr_a),
+            _ptr(tr_i), int(trace_cap), _stream())
+    return _train_result(st, alpha, F, support, ns, upd, tr_a, tr_i, trace_cap)
 
 
 def rbf_score(support_x: torch.Tensor, alpha: torch.Tensor, gamma: float, q: torch.Tensor, want_f=True,
@@ -345,11 +402,11 @@ def active_update(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: floa
                   iter_max: int | None = None, s_max: int | None = None):
     """One model update after two-stage active learning (Section III-B), every step on the device: assemble
     the new training set, label every row geometrically, start from F = the current model's score of every
-    row (F = K alpha) and run Algorithm 1. Returns train()'s dict plus X, y and F0."""
+    row (F = K alpha) and run Algorithm 1. Returns train_points()'s dict plus X, y and F0."""
     X, a0 = active_samples(support_q, alpha, noise, k, explore)
     y, _ = label_capsule_box(arm, X, arm.radius, boxes_lo, boxes_hi, want_clearance=False)
     F0, _ = fk_score(arm, support_q, alpha, gamma, X, want_label=False)
-    out = train(fk_points(arm, X), y, gamma, beta=beta, iter_max=iter_max, s_max=s_max, alpha=a0, F=F0)
+    out = train_points(fk_points(arm, X), y, gamma, beta=beta, iter_max=iter_max, s_max=s_max, alpha=a0, F=F0)
     out.update(X=X, y=y, F0=F0)
     return out
 
@@ -427,6 +484,10 @@ class Batch:
             self._h = None
 
     def __del__(self):
+        # No library calls while the interpreter shuts down (the HIP runtime may be tearing down too); the
+        # process releases the device memory anyway.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -522,6 +583,10 @@ class MLP:
             self._h = None
 
     def __del__(self):
+        # No library calls while the interpreter shuts down (the HIP runtime may be tearing down too); the
+        # process releases the device memory anyway.
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -121,10 +121,11 @@ struct fastron_batch {
 
 namespace {
 
+void drop_graph(fastron_batch* b);
+
 void free_batch(fastron_batch* b) {
   if (!b) return;
-  if (b->exec) (void)hipGraphExecDestroy(b->exec);
-  if (b->graph) (void)hipGraphDestroy(b->graph);
+  drop_graph(b);
   (void)hipFree(b->d_support_off);
   (void)hipFree(b->d_tile_off);
   (void)hipFree(b->d_tiles);
@@ -134,8 +135,19 @@ void free_batch(fastron_batch* b) {
   delete b;
 }
 
+// A captured graph holds the launch it recorded by value (kernel, grid and
+// item count), so it does not follow a rebuilt work list: drop it, and let a
+// replay report that it has to be captured again.
+void drop_graph(fastron_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
 // Work items for tile shape qb, longest first.
 fastron_status build_items(fastron_batch* b, int qb, hipStream_t s) {
+  drop_graph(b);
   const int per = 16 * qb;
   std::vector<BatchItem> items;
   for (int e = 0; e < b->E; ++e) {
@@ -342,7 +354,8 @@ fastron_status fastron_batch_capture(fastron_batch* b, const float* q, float* f,
 
 fastron_status fastron_batch_replay(fastron_batch* b, void* stream) {
   clear_error();
-  FASTRON_CHECK(b != nullptr && b->exec != nullptr, "no captured graph (call fastron_batch_capture first)");
+  FASTRON_CHECK(b != nullptr && b->exec != nullptr,
+                "no captured graph (call fastron_batch_capture first, and again after fastron_batch_autotune)");
   FASTRON_HIP(hipGraphLaunch(b->exec, as_stream(stream)));
   return FASTRON_OK;
 }

@@ -15,7 +15,9 @@ namespace fastron {
 //   variant 2 (split3): + lo(p).hi(p') + hi(p).lo(p') + mid(p).mid(p')
 // c_q and c_s enter as three bf16 parts each against unit entries (exact to
 // FP32 rounding), so the accumulator input is zero and no FP32 operand block
-// has to be streamed besides the weights.
+// has to be streamed besides the weights. Every t is clamped to t >= 1 (the
+// squared distance to >= 0) before 1/t^2, so each K_RQ stays within (0, 1]
+// whatever the cancellation in the BF16 cross term.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned short bf16_rne_d(float x) {
   uint32_t u = __float_as_uint(x);
@@ -102,7 +104,7 @@ __global__ void __launch_bounds__(256) k_score_bf16(ChainArgs c, const float* __
       const f4 W = *reinterpret_cast<const f4*>(T + woff + 4 * g);
 #pragma unroll
       for (int b = 0; b < QB; ++b) {
-        PairSum<RAT> ps;
+        PairSum<RAT, true> ps;
 #pragma unroll
         for (int m = 0; m < MM; ++m) ps.add(m, __builtin_amdgcn_mfma_f32_16x16x32_bf16(Av[m], B[b][m], zero, 0, 0, 0));
         fpart[b] = ps.finish(W, fpart[b]);

@@ -773,17 +773,17 @@ static const void* wave_kernel(int PT, int mm) {
   return wave_kernel_mm<T, 0>(PT);
 }
 
+// Host validation shared by the points and configuration forms (before any HIP call).
 template <typename T>
-static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int32_t M, int32_t D, T gamma, T beta,
-                                 int64_t iter_max, int64_t s_max, T* alpha, T* F, int32_t* support_idx,
-                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
-                                 int64_t trace_cap, void* stream) {
-  clear_error();
+static fastron_status check_train_args(const int8_t* y, int64_t N, int32_t M, int32_t D, T gamma, T beta,
+                                       int64_t iter_max, int64_t s_max, const T* alpha, const T* F,
+                                       const int32_t* support_idx, const int64_t* n_support, const int64_t* updates,
+                                       const int32_t* trace_action, const int32_t* trace_index, int64_t trace_cap) {
   FASTRON_CHECK(N >= 1 && N < INT32_MAX, "N = %lld outside [1, 2^31)", (long long)N);
   FASTRON_CHECK(M >= 1 && M <= FASTRON_MAX_POINTS, "M = %d outside [1, %d]", M, FASTRON_MAX_POINTS);
   FASTRON_CHECK(D >= 1 && M * D <= 3 * FASTRON_MAX_POINTS, "%d points of %d coordinates exceed %d floats", M, D,
                 3 * FASTRON_MAX_POINTS);
-  FASTRON_CHECK(P && y && alpha && F && support_idx, "P, y, alpha, F and support_idx must be non-NULL");
+  FASTRON_CHECK(y && alpha && F && support_idx, "y, alpha, F and support_idx must be non-NULL");
   FASTRON_CHECK(n_support && updates, "n_support and updates must be non-NULL host pointers");
   FASTRON_CHECK(std::isfinite((double)gamma) && gamma > 0, "gamma must be finite and > 0");
   FASTRON_CHECK(std::isfinite((double)beta) && beta >= 1, "beta must be >= 1 (Eq. 5)");
@@ -791,6 +791,19 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   FASTRON_CHECK(s_max >= 1, "s_max must be >= 1");
   FASTRON_CHECK(trace_cap >= 0 && (trace_cap == 0 || (trace_action && trace_index)),
                 "trace arrays must be non-NULL when trace_cap > 0");
+  return FASTRON_OK;
+}
+
+template <typename T>
+static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int32_t M, int32_t D, T gamma, T beta,
+                                 int64_t iter_max, int64_t s_max, T* alpha, T* F, int32_t* support_idx,
+                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
+                                 int64_t trace_cap, void* stream) {
+  clear_error();
+  FASTRON_CHECK(P != nullptr, "P is NULL");
+  fastron_status cs = check_train_args<T>(y, N, M, D, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support,
+                                          updates, trace_action, trace_index, trace_cap);
+  if (cs != FASTRON_OK) return cs;
   hipStream_t s = as_stream(stream);
   int dev = 0;
   FASTRON_HIP(hipGetDevice(&dev));
@@ -1039,14 +1052,68 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
   return all_converged ? FASTRON_OK : FASTRON_NOT_CONVERGED;
 }
 
+// Configuration forms: Algorithm 1's input is a dataset of configurations
+// (Section III-B). Their control points (a1, one FK per configuration) go
+// into stream-ordered scratch of N x M x 3 floats, and the points form runs on
+// them: the same kernels, so the two forms give bit-identical results.
+template <typename T>
+static fastron_status train_configs(const fastron_chain* chain, const fastron_cpoints* cp, const float* X,
+                                    const int8_t* y, int64_t N, T gamma, T beta, int64_t iter_max, int64_t s_max,
+                                    T* alpha, T* F, int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                                    int32_t* trace_action, int32_t* trace_index, int64_t trace_cap, void* stream) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(X != nullptr, "X is NULL");
+  st = check_train_args<T>(y, N, c.M, 3, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                           trace_action, trace_index, trace_cap);
+  if (st != FASTRON_OK) return st;
+  hipStream_t s = as_stream(stream);
+  float* P = nullptr;
+  FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&P), (size_t)N * c.M * 3 * sizeof(float), s));
+  st = fastron_fk_points(chain, cp, X, N, P, stream);
+  if (st == FASTRON_OK)
+    st = train_impl<T>(P, y, N, c.M, 3, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
+                       trace_action, trace_index, trace_cap, stream);
+  const hipError_t ef = hipFreeAsync(P, s);
+  if (st != FASTRON_OK && st != FASTRON_NOT_CONVERGED) return st;
+  if (ef != hipSuccess) return fail(FASTRON_EHIP, "hipFreeAsync failed: %s", hipGetErrorString(ef));
+  return st;
+}
+
 }  // namespace fastron
 
 using namespace fastron;
 
 extern "C" {
 
-fastron_status fastron_gram_update(const float* P, int64_t N, int32_t M, float gamma, int64_t i, float delta_alpha,
-                                   float* F, float* kcol, void* stream) {
+fastron_status fastron_gram_update(const fastron_chain* chain, const fastron_cpoints* cp, const float* X, int64_t N,
+                                   float gamma, int64_t i, float delta_alpha, float* F, float* kcol, void* stream) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(N >= 1, "N = %lld < 1", (long long)N);
+  FASTRON_CHECK(i >= 0 && i < N, "i = %lld outside [0, N)", (long long)i);
+  FASTRON_CHECK(X != nullptr, "X is NULL");
+  FASTRON_CHECK(F != nullptr || kcol != nullptr, "F and kcol are both NULL");
+  FASTRON_CHECK(std::isfinite(gamma) && gamma > 0.f, "gamma must be finite and > 0");
+  FASTRON_CHECK(std::isfinite(delta_alpha), "delta_alpha must be finite");
+  FASTRON_CHECK((N + 255) / 256 <= INT32_MAX, "N too large");
+  hipStream_t s = as_stream(stream);
+  float* P = nullptr;
+  FASTRON_HIP(hipMallocAsync(reinterpret_cast<void**>(&P), (size_t)N * c.M * 3 * sizeof(float), s));
+  st = fastron_fk_points(chain, cp, X, N, P, stream);
+  if (st == FASTRON_OK) st = fastron_gram_update_points(P, N, c.M, gamma, i, delta_alpha, F, kcol, stream);
+  const hipError_t ef = hipFreeAsync(P, s);
+  if (st != FASTRON_OK) return st;
+  if (ef != hipSuccess) return fail(FASTRON_EHIP, "hipFreeAsync failed: %s", hipGetErrorString(ef));
+  return FASTRON_OK;
+}
+
+fastron_status fastron_gram_update_points(const float* P, int64_t N, int32_t M, float gamma, int64_t i,
+                                          float delta_alpha, float* F, float* kcol, void* stream) {
   clear_error();
   FASTRON_CHECK(N >= 1, "N = %lld < 1", (long long)N);
   FASTRON_CHECK(M >= 1 && M <= FASTRON_MAX_POINTS, "M = %d outside [1, %d]", M, FASTRON_MAX_POINTS);
@@ -1063,10 +1130,27 @@ fastron_status fastron_gram_update(const float* P, int64_t N, int32_t M, float g
   return FASTRON_OK;
 }
 
-fastron_status fastron_train(const float* P, const int8_t* y, int64_t N, int32_t M, float gamma, float beta,
-                             int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
-                             int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
-                             int64_t trace_cap, void* stream) {
+fastron_status fastron_train(const fastron_chain* chain, const fastron_cpoints* cp, const float* X, const int8_t* y,
+                             int64_t N, float gamma, float beta, int64_t iter_max, int64_t s_max, float* alpha,
+                             float* F, int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                             int32_t* trace_action, int32_t* trace_index, int64_t trace_cap, void* stream) {
+  return train_configs<float>(chain, cp, X, y, N, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support,
+                              updates, trace_action, trace_index, trace_cap, stream);
+}
+
+fastron_status fastron_train_f64(const fastron_chain* chain, const fastron_cpoints* cp, const float* X,
+                                 const int8_t* y, int64_t N, double gamma, double beta, int64_t iter_max,
+                                 int64_t s_max, double* alpha, double* F, int32_t* support_idx, int64_t* n_support,
+                                 int64_t* updates, int32_t* trace_action, int32_t* trace_index, int64_t trace_cap,
+                                 void* stream) {
+  return train_configs<double>(chain, cp, X, y, N, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support,
+                               updates, trace_action, trace_index, trace_cap, stream);
+}
+
+fastron_status fastron_train_points(const float* P, const int8_t* y, int64_t N, int32_t M, float gamma, float beta,
+                                    int64_t iter_max, int64_t s_max, float* alpha, float* F, int32_t* support_idx,
+                                    int64_t* n_support, int64_t* updates, int32_t* trace_action,
+                                    int32_t* trace_index, int64_t trace_cap, void* stream) {
   return train_impl<float>(P, y, N, M, 3, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
                            trace_action, trace_index, trace_cap, stream);
 }
@@ -1078,10 +1162,11 @@ fastron_status fastron_train_batch(const float* P, const int8_t* y, int32_t E, c
                           stream);
 }
 
-fastron_status fastron_train_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma, double beta,
-                                 int64_t iter_max, int64_t s_max, double* alpha, double* F, int32_t* support_idx,
-                                 int64_t* n_support, int64_t* updates, int32_t* trace_action, int32_t* trace_index,
-                                 int64_t trace_cap, void* stream) {
+fastron_status fastron_train_points_f64(const float* P, const int8_t* y, int64_t N, int32_t M, double gamma,
+                                        double beta, int64_t iter_max, int64_t s_max, double* alpha, double* F,
+                                        int32_t* support_idx, int64_t* n_support, int64_t* updates,
+                                        int32_t* trace_action, int32_t* trace_index, int64_t trace_cap,
+                                        void* stream) {
   return train_impl<double>(P, y, N, M, 3, gamma, beta, iter_max, s_max, alpha, F, support_idx, n_support, updates,
                             trace_action, trace_index, trace_cap, stream);
 }

@@ -88,12 +88,26 @@ def test_validation_before_device_work(lib):
     fake = vp(256)  # never dereferenced: validation fails first
     args = lambda beta, s_max, gamma=10.0: (fake, fake, 100, 8, gamma, beta, 10, s_max, fake, fake, fake,
                                             ctypes.byref(ns), ctypes.byref(up), None, None, 0, None)
-    assert lib.fastron_train(*args(0.5, 10)) == nat.FASTRON_EINVAL  # beta < 1 (Eq. 5)
+    assert lib.fastron_train_points(*args(0.5, 10)) == nat.FASTRON_EINVAL  # beta < 1 (Eq. 5)
     assert "beta" in nat.last_error()
-    assert lib.fastron_train(*args(1.0, 0)) == nat.FASTRON_EINVAL  # s_max < 1
-    assert lib.fastron_train(*args(1.0, 10, gamma=0.0)) == nat.FASTRON_EINVAL
-    assert lib.fastron_train(*args(1.0, 10, gamma=float("nan"))) == nat.FASTRON_EINVAL
-    assert lib.fastron_gram_update(fake, 100, 8, 10.0, 100, 1.0, fake, None, None) == nat.FASTRON_EINVAL  # i >= N
+    assert lib.fastron_train_points(*args(1.0, 0)) == nat.FASTRON_EINVAL  # s_max < 1
+    assert lib.fastron_train_points(*args(1.0, 10, gamma=0.0)) == nat.FASTRON_EINVAL
+    assert lib.fastron_train_points(*args(1.0, 10, gamma=float("nan"))) == nat.FASTRON_EINVAL
+    assert lib.fastron_gram_update_points(fake, 100, 8, 10.0, 100, 1.0, fake, None, None) == nat.FASTRON_EINVAL
+    # the configuration forms validate the chain and every argument before their FK scratch is allocated
+    xargs = lambda beta, s_max, gamma=10.0, chain=ch: (chain, cp, fake, fake, 100, gamma, beta, 10, s_max, fake,
+                                                       fake, fake, ctypes.byref(ns), ctypes.byref(up), None, None,
+                                                       0, None)
+    assert lib.fastron_train(*xargs(0.5, 10)) == nat.FASTRON_EINVAL
+    assert "beta" in nat.last_error()
+    assert lib.fastron_train(*xargs(1.0, 0)) == nat.FASTRON_EINVAL
+    assert lib.fastron_train_f64(*xargs(1.0, 10, gamma=0.0)) == nat.FASTRON_EINVAL
+    assert lib.fastron_train(*xargs(1.0, 10, chain=None)) == nat.FASTRON_EINVAL
+    assert lib.fastron_train(ch, cp, None, fake, 100, 10.0, 1.0, 10, 10, fake, fake, fake, ctypes.byref(ns),
+                             ctypes.byref(up), None, None, 0, None) == nat.FASTRON_EINVAL  # X NULL
+    assert lib.fastron_gram_update(ch, cp, fake, 100, 10.0, 100, 1.0, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_gram_update(ch, cp, fake, 100, 10.0, 5, 1.0, None, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_gram_update(None, cp, fake, 100, 10.0, 5, 1.0, fake, None, None) == nat.FASTRON_EINVAL
     # the kernel on configurations
     assert lib.fastron_rbf_score(None, None, 0, 7, 1.0, None, 0, None, None, None) == nat.FASTRON_OK  # N = 0
     assert lib.fastron_rbf_score(fake, fake, 10, 0, 1.0, fake, 10, fake, None, None) == nat.FASTRON_EINVAL  # n < 1

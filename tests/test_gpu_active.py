@@ -10,7 +10,7 @@ import pytest
 import torch
 
 from paper_1910_06451_amd import api, workloads as wl
-from conftest import announce, oracle_dh
+from conftest import announce, assert_claim2, oracle_dh
 from test_gpu_score import error_bound
 
 pytestmark = pytest.mark.gpu
@@ -54,7 +54,8 @@ def test_active_update_matches_oracle(oracle_mod, dev, arm_name, k, E):
     P32 = PX.astype(np.float32).astype(np.float64)
     F_oracle = oracle_mod.score_points(P32[s2], alpha[s2].astype(np.float64), gamma, P32)
     margins = ref["y"] * F_oracle
+    non_positive = assert_claim2(ref["y"], F_oracle, out["F"].cpu().numpy())
     print(dict(rows=X.shape[0], gpu_support=int(s2.shape[0]), oracle_support=int(ref["support"].shape[0]),
-               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min())))
-    assert np.mean(margins > 0) >= 0.999
+               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min()),
+               non_positive_fp64_margins=non_positive))
     assert abs(s2.shape[0] - ref["support"].shape[0]) <= 0.05 * ref["support"].shape[0] + 5

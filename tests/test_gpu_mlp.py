@@ -166,7 +166,7 @@ def test_screening_gain(oracle_mod, dev):
     q20 = torch.from_numpy(wl.configs("gain/fastron", 20_000, 7)).to(dev)
     y20, _ = api.label_capsule_box(arm, q20, arm.radius, lo, hi, want_clearance=False)
     announce("gain: fastron fallback model")
-    fit = api.train(api.fk_points(arm, q20), y20, 30.0, s_max=2000)
+    fit = api.train_points(api.fk_points(arm, q20), y20, 30.0, s_max=2000)
     sup = fit["support"].long()
     model = api.support_prep(arm, q20[sup].contiguous(), fit["alpha"][sup].contiguous(), 30.0)
     q = torch.from_numpy(wl.configs("gain/q", 400_000, 7)).to(dev)

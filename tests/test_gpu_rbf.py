@@ -9,7 +9,7 @@ import pytest
 import torch
 
 from paper_1910_06451_amd import api, workloads as wl
-from conftest import announce
+from conftest import announce, assert_claim2
 from test_gpu_score import check_scores, error_bound
 from test_gpu_train import labelled_set
 
@@ -83,11 +83,11 @@ def test_rbf_train_fp32_claim2(oracle_mod, dev):
     X64 = q.astype(np.float64)
     F_oracle = oracle_mod.rbf_score(X64[sup], alpha[sup].astype(np.float64), 1.0, X64)
     margins = y * F_oracle
-    assert np.abs(out["F"].cpu().numpy() - F_oracle).max() < 1e-3
-    assert np.mean(margins > 0) >= 0.999, np.mean(margins > 0)
+    non_positive = assert_claim2(y, F_oracle, out["F"].cpu().numpy())
     ref = oracle_mod.fastron_update(X64[:, None, :], y, 1.0)
     print(dict(gpu_support=int(sup.shape[0]), oracle_support=int(ref["support"].shape[0]),
-               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min())))
+               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min()),
+               non_positive_fp64_margins=non_positive))
     assert abs(sup.shape[0] - ref["support"].shape[0]) <= 0.05 * ref["support"].shape[0] + 5
     announce("rbf_train fp32 warm start")
     part = api.rbf_train(X, yd, 1.0, iter_max=100)

@@ -12,7 +12,7 @@ import pytest
 import torch
 
 from paper_1910_06451_amd import api, workloads as wl
-from conftest import announce, oracle_dh
+from conftest import announce, assert_claim2, oracle_dh
 
 pytestmark = pytest.mark.gpu
 
@@ -41,7 +41,7 @@ def test_gram_update_parity(oracle_mod, dev):
     F0 = wl.rng("gram/F").standard_normal(5003).astype(np.float32)
     F = torch.from_numpy(F0).to(dev)
     announce("gram_update N=5003")
-    kcol = api.gram_update(P, 10.0, 4999, -0.75, F=F).cpu().numpy()
+    kcol = api.gram_update_points(P, 10.0, 4999, -0.75, F=F).cpu().numpy()
     ref = np.array([oracle_mod.k_fk(P32[j].astype(np.float64), P32[4999].astype(np.float64), 10.0)
                     for j in range(5003)])
     assert np.abs(kcol - ref).max() <= 1e-6
@@ -56,7 +56,7 @@ def test_train_fp64_step_exact(oracle_mod, dev, beta):
     q, P32, y = labelled_set(oracle_mod, arm, "train3", 2000, 5, 0.15)
     ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 10.0, beta=beta, trace=True)
     announce(f"train_f64 3dof N=2000 beta={beta}")
-    out = api.train(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, beta=beta, fp64=True,
+    out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, beta=beta, fp64=True,
                     trace_cap=ref["updates"] + 10)
     assert out["converged"] == ref["converged"]
     assert out["updates"] == ref["updates"]
@@ -72,15 +72,15 @@ def test_train_fp64_warm_start_and_caps(oracle_mod, dev):
     q, P32, y = labelled_set(oracle_mod, arm, "train3b", 1500, 5, 0.15)
     P, yd = torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev)
     announce("train_f64 warm start")
-    full = api.train(P, yd, 10.0, fp64=True)
-    part = api.train(P, yd, 10.0, fp64=True, iter_max=25)
+    full = api.train_points(P, yd, 10.0, fp64=True)
+    part = api.train_points(P, yd, 10.0, fp64=True, iter_max=25)
     assert not part["converged"] and part["updates"] == 25
-    rest = api.train(P, yd, 10.0, fp64=True, alpha=part["alpha"], F=part["F"])
+    rest = api.train_points(P, yd, 10.0, fp64=True, alpha=part["alpha"], F=part["F"])
     assert rest["converged"]
     assert torch.equal(rest["alpha"], full["alpha"])
     assert torch.equal(rest["support"], full["support"])
     announce("train_f64 s_max cap")
-    capped = api.train(P, yd, 10.0, fp64=True, s_max=7)
+    capped = api.train_points(P, yd, 10.0, fp64=True, s_max=7)
     ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 10.0, s_max=7)
     assert capped["support"].shape[0] <= 7
     np.testing.assert_array_equal(capped["support"].cpu().numpy(), ref["support"])
@@ -93,7 +93,7 @@ def test_train_fp32_claim2(oracle_mod, dev):
     arm = wl.arm_7dof()
     q, P32, y = labelled_set(oracle_mod, arm, "train7", 5000, 20, 0.1, 0.25)
     announce("train fp32 7dof N=5000")
-    out = api.train(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0)
+    out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0)
     assert out["converged"]
     alpha = out["alpha"].cpu().numpy()
     sup = out["support"].cpu().numpy()
@@ -102,12 +102,11 @@ def test_train_fp32_claim2(oracle_mod, dev):
     P64 = P32.astype(np.float64)
     F_oracle = oracle_mod.score_points(P64[sup], alpha[sup].astype(np.float64), 10.0, P64)
     margins = y * F_oracle
-    F_gpu = out["F"].cpu().numpy()
-    assert np.abs(F_gpu - F_oracle).max() < 1e-3
-    assert np.mean(margins > 0) >= 0.999, np.mean(margins > 0)
+    non_positive = assert_claim2(y, F_oracle, out["F"].cpu().numpy())
     ref = oracle_mod.fastron_update(P64, y, 10.0)
     print(dict(gpu_support=int(sup.shape[0]), oracle_support=int(ref["support"].shape[0]),
-               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min())))
+               gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min()),
+               non_positive_fp64_margins=non_positive))
     assert abs(sup.shape[0] - ref["support"].shape[0]) <= 0.05 * ref["support"].shape[0] + 5
 
 
@@ -118,13 +117,13 @@ def test_train_edge_cases(oracle_mod, dev):
     P32 = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
     P = torch.from_numpy(P32).to(dev)
     announce("train: all labels free")
-    out = api.train(P, -torch.ones(300, dtype=torch.int8, device=dev), 10.0)
+    out = api.train_points(P, -torch.ones(300, dtype=torch.int8, device=dev), 10.0)
     assert out["converged"] and out["support"].tolist() == [0] and float(out["alpha"][0]) == -1.0
     announce("train: single point")
-    out = api.train(P[:1].contiguous(), torch.ones(1, dtype=torch.int8, device=dev), 10.0, beta=3.0)
+    out = api.train_points(P[:1].contiguous(), torch.ones(1, dtype=torch.int8, device=dev), 10.0, beta=3.0)
     assert out["converged"] and float(out["alpha"][0]) == 3.0
     announce("train: iter_max = 0")
-    out = api.train(P, -torch.ones(300, dtype=torch.int8, device=dev), 10.0, iter_max=0)
+    out = api.train_points(P, -torch.ones(300, dtype=torch.int8, device=dev), 10.0, iter_max=0)
     assert not out["converged"] and out["updates"] == 0 and out["support"].numel() == 0
 
 
@@ -149,7 +148,7 @@ def test_three_dof_end_to_end(oracle_mod, dev):
     announce("3dof end to end: train_f64 N=2000")
     q_d = torch.from_numpy(q).to(dev)
     # training input: the oracle's control points rounded to FP32, so both trajectories see the same values
-    out = api.train(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, fp64=True)
+    out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, fp64=True)
     sup = out["support"].cpu().numpy()
     np.testing.assert_array_equal(sup, ref["support"])
     a32 = out["alpha"].cpu().numpy()[sup].astype(np.float32)
@@ -175,7 +174,7 @@ def test_three_dof_end_to_end(oracle_mod, dev):
 def test_train_full_size_claim2(oracle_mod, dev):
     """The benchmark's training run at full size: 50,000 labelled 7-DOF configurations (20 cubes), gamma = 30.
     The model must converge, its F must agree with F = K alpha recomputed in FP64 by the oracle, and that FP64
-    F must give a positive margin to (nearly) every training point (Claim 2)."""
+    F must give every training point a positive margin, up to the stated FP32 drift (Claim 2)."""
     arm = wl.arm_7dof()
     dh = oracle_dh(oracle_mod, arm)
     q = wl.configs("bench7/train", 50_000, arm.n)
@@ -184,7 +183,7 @@ def test_train_full_size_claim2(oracle_mod, dev):
     y = y.astype(np.int8)
     P32 = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
     announce("train fp32 7dof N=50000 gamma=30")
-    out = api.train(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 30.0)
+    out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 30.0)
     assert out["converged"]
     alpha = out["alpha"].cpu().numpy()
     sup = out["support"].cpu().numpy()
@@ -194,16 +193,16 @@ def test_train_full_size_claim2(oracle_mod, dev):
     F_oracle = oracle_mod.score_points(P64[sup], alpha[sup].astype(np.float64), 30.0, P64)
     F_gpu = out["F"].cpu().numpy()
     margins = y * F_oracle
+    non_positive = assert_claim2(y, F_oracle, F_gpu, drift=1e-2)
     print(dict(support=int(sup.size), updates=out["updates"], max_dF=float(np.abs(F_gpu - F_oracle).max()),
-               frac_positive=float(np.mean(margins > 0)), min_margin=float(margins.min())))
-    assert np.all(y * F_gpu > 0)
-    assert np.abs(F_gpu - F_oracle).max() < 1e-2
-    assert np.mean(margins > 0) >= 0.999
+               frac_positive=float(np.mean(margins > 0)), min_margin=float(margins.min()),
+               non_positive_fp64_margins=non_positive))
 
 
 def test_train_batch_matches_single_sets(oracle_mod, dev):
     """Several training sets in one launch (ragged sizes, one set of a single point) end exactly as each set
-    trained alone: same weights, F, support and update count; also from a warm start after relabelling."""
+    trained alone: same weights, F, support and update count; also from a warm start after relabelling. Each
+    set's model also satisfies Claim 2 against the oracle's F = K alpha."""
     arm = wl.arm_7dof()
     dh = oracle_dh(oracle_mod, arm)
     sizes = [1, 777, 2048, 3001, 64]
@@ -224,12 +223,52 @@ def test_train_batch_matches_single_sets(oracle_mod, dev):
     for e in range(len(sizes)):
         sl = slice(int(off[e]), int(off[e + 1]))
         announce(f"train single set {e} (N={sizes[e]})")
-        s0 = api.train(P[sl].contiguous(), Y0[sl].contiguous(), 30.0, iter_max=iters, s_max=4000)
-        s1 = api.train(P[sl].contiguous(), Y1[sl].contiguous(), 30.0, iter_max=iters, s_max=4000,
+        s0 = api.train_points(P[sl].contiguous(), Y0[sl].contiguous(), 30.0, iter_max=iters, s_max=4000)
+        s1 = api.train_points(P[sl].contiguous(), Y1[sl].contiguous(), 30.0, iter_max=iters, s_max=4000,
                        alpha=s0["alpha"], F=s0["F"])
         for b, s_ in ((b0, s0), (b1, s1)):
             assert torch.equal(b["alpha"][sl], s_["alpha"]), e
             assert torch.equal(b["F"][sl], s_["F"]), e
             assert torch.equal(b["supports"][e], s_["support"]), e
         assert b0["updates"][e] == s0["updates"] and b1["updates"][e] == s1["updates"], e
+        # Claim 2 per set against the oracle's F = K alpha (no set reaches s_max, so every run ended by break)
+        P64 = P[sl].cpu().numpy().astype(np.float64)
+        for b, yy in ((b0, y0), (b1, y1)):
+            a = b["alpha"][sl].cpu().numpy()
+            sup = np.flatnonzero(a)
+            F_oracle = oracle_mod.score_points(P64[sup], a[sup].astype(np.float64), 30.0, P64)
+            assert_claim2(yy[sl], F_oracle, b["F"][sl].cpu().numpy())
     assert b0["converged"] and b1["converged"]
+
+
+def test_configuration_forms_match_points_forms(oracle_mod, dev):
+    """fastron_train / fastron_train_f64 / fastron_gram_update take the training configurations themselves
+    (Algorithm 1's input is a dataset of configurations, Section III-B) and compute their control points; the
+    results are bit-identical to the points forms run on fastron_fk_points of the same configurations."""
+    arm = wl.arm_7dof()
+    q, _, y = labelled_set(oracle_mod, arm, "xform", 3001, 20, 0.1, 0.25)
+    X, yd = torch.from_numpy(q).to(dev), torch.from_numpy(y).to(dev)
+    P = api.fk_points(arm, X)
+    for fp64 in (False, True):
+        cap = 4096 if fp64 else 0
+        announce(f"train configuration form fp64={fp64} N=3001")
+        a = api.train(arm, X, yd, 30.0, fp64=fp64, trace_cap=cap)
+        announce(f"train points form fp64={fp64} N=3001")
+        b = api.train_points(P, yd, 30.0, fp64=fp64, trace_cap=cap)
+        assert a["converged"] == b["converged"] and a["updates"] == b["updates"]
+        for k in ("alpha", "F", "support") + (("trace_action", "trace_index") if fp64 else ()):
+            assert torch.equal(a[k], b[k]), k
+    announce("train configuration form warm start, capped")
+    part = api.train(arm, X, yd, 30.0, iter_max=100)
+    assert not part["converged"] and part["updates"] == 100
+    rest = api.train(arm, X, yd, 30.0, alpha=part["alpha"], F=part["F"])
+    rest_p = api.train_points(P, yd, 30.0, alpha=part["alpha"], F=part["F"])
+    assert torch.equal(rest["alpha"], rest_p["alpha"]) and torch.equal(rest["F"], rest_p["F"])
+    F0 = torch.from_numpy(wl.rng("xform/F").standard_normal(3001).astype(np.float32)).to(dev)
+    for i, da in ((0, 1.0), (1500, -0.5), (3000, 2.0)):
+        announce(f"gram_update configuration vs points form i={i}")
+        F1, F2 = F0.clone(), F0.clone()
+        k1 = api.gram_update(arm, X, 10.0, i, da, F=F1)
+        k2 = api.gram_update_points(P, 10.0, i, da, F=F2)
+        assert torch.equal(k1, k2) and torch.equal(F1, F2)
+        assert float(k1[i]) == 1.0
