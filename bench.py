@@ -307,7 +307,7 @@ def kernels_run(api, wl, arm, dev, N=4_194_304, reps=10):
     F = torch.zeros(N, dtype=torch.float32, device=dev)
     lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
     t_fk = _event_ms(lambda: api.fk_points(arm, q), reps)
-    t_gram = _event_ms(lambda: api.gram_update(P, 10.0, 12345, 0.5, F=F, want_kcol=False), reps)
+    t_gram = _event_ms(lambda: api.gram_update_points(P, 10.0, 12345, 0.5, F=F, want_kcol=False), reps)
     t_lab = _event_ms(lambda: api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=False), 3)
     t_clr = _event_ms(lambda: api.label_capsule_box(arm, q, arm.radius, lo, hi, want_clearance=True), 3)
     b_fk = N * (arm.n * 4 + arm.M * 12)
@@ -371,7 +371,7 @@ def dof3_run(api, wl, dev, checks, reps=20):
             break
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = api.train(api.fk_points(arm, q), y, 10.0, fp64=True)
+    out = api.train_points(api.fk_points(arm, q), y, 10.0, fp64=True)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     sup = out["support"].long()
@@ -415,7 +415,7 @@ def train_run(api, wl, arm, dev):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     P = api.fk_points(arm, q)
-    out = api.train(P, y, GAMMA_TRAIN_7DOF)
+    out = api.train_points(P, y, GAMMA_TRAIN_7DOF)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     return {"N": N, "gamma": GAMMA_TRAIN_7DOF, "label_ms": (t1 - t0) * 1e3, "train_ms": (t2 - t1) * 1e3,
@@ -461,7 +461,7 @@ def compare_run(api, wl, arm, dev, checks, reps=5):
     # FK kernel
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    out = api.train(api.fk_points(arm, q), y, GAMMA_TRAIN_7DOF)
+    out = api.train_points(api.fk_points(arm, q), y, GAMMA_TRAIN_7DOF)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     sup = out["support"].long()
@@ -520,7 +520,7 @@ def obstacles_run(api, wl, arm, dev, checks, counts=(1, 5, 10, 20, 30, 50), reps
             torch.cuda.synchronize()
             t0 = time.perf_counter()
             if kind == "fk":
-                out = api.train(P, y, GAMMA_TRAIN_7DOF)
+                out = api.train_points(P, y, GAMMA_TRAIN_7DOF)
             else:
                 out = api.rbf_train(q, y, GAMMA_CONFIG_7DOF)
             torch.cuda.synchronize()
@@ -569,7 +569,7 @@ def active_run(api, wl, arm, dev, steps=10, n_init=20_000, k=2, sigma=0.1, n_exp
     res = {"steps": steps, "n_init": n_init, "k": k, "sigma": sigma, "n_explore": n_explore, "n_test": n_test}
     for kind, gam in (("fk", GAMMA_TRAIN_7DOF), ("configurations", GAMMA_CONFIG_7DOF)):
         y0, _ = api.label_capsule_box(arm, q0, arm.radius, lo, hi, want_clearance=False)
-        out = api.train(api.fk_points(arm, q0), y0, gam) if kind == "fk" else api.rbf_train(q0, y0, gam)
+        out = api.train_points(api.fk_points(arm, q0), y0, gam) if kind == "fk" else api.rbf_train(q0, y0, gam)
         sup = out["support"].long()
         sq, sa = q0[sup].contiguous(), out["alpha"][sup].contiguous()
         c = centre.copy()
@@ -705,10 +705,10 @@ def retrain_run(api, wl, arm, dev, n_env=16, N=20_000):
     seq = []
     for e in range(n_env):
         sl = slice(e * N, (e + 1) * N)
-        first = api.train(P[sl].contiguous(), Y0[sl].contiguous(), GAMMA_TRAIN_7DOF)
+        first = api.train_points(P[sl].contiguous(), Y0[sl].contiguous(), GAMMA_TRAIN_7DOF)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        second = api.train(P[sl].contiguous(), Y1[sl].contiguous(), GAMMA_TRAIN_7DOF, alpha=first["alpha"],
+        second = api.train_points(P[sl].contiguous(), Y1[sl].contiguous(), GAMMA_TRAIN_7DOF, alpha=first["alpha"],
                            F=first["F"])
         torch.cuda.synchronize()
         seq.append(second)
@@ -765,7 +765,7 @@ def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304
     # fallback Fastron model (S_max = 4,000)
     q50 = torch.from_numpy(wl.configs("bench7/train", 50_000, arm.n)).to(dev)
     y50, _ = api.label_capsule_box(arm, q50, arm.radius, lo, hi, want_clearance=False)
-    fit = api.train(api.fk_points(arm, q50), y50, GAMMA_TRAIN_7DOF, s_max=4000)
+    fit = api.train_points(api.fk_points(arm, q50), y50, GAMMA_TRAIN_7DOF, s_max=4000)
     sup = fit["support"].long()
     model = api.support_prep(arm, q50[sup].contiguous(), fit["alpha"][sup].contiguous(), GAMMA_TRAIN_7DOF)
     # queries and their geometric labels
