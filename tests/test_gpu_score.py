@@ -356,9 +356,9 @@ def test_score_general_chains(oracle_mod, dev, case):
 @pytest.mark.parametrize("Mm", list(range(1, 17)))
 def test_score_every_moving_point_count(oracle_mod, dev, Mm):
     """Every instantiation of the scoring kernels over the number of moving control points (1..16): an
-    Mm-joint chain (FP32 chain below 7 joints, FP64 from 7) with a point on the base frame and one on each
-    moving frame, MFMA and VALU forms, ragged S and N."""
-    arm = _random_chain(f"mm{Mm}", Mm, np.arange(0, Mm + 1))
+    Mm-joint chain (FP32 chain below 7 joints, FP64 from 7) with a point on each moving frame and, while the
+    total stays within 16 points, one on the base frame; MFMA and VALU forms, ragged S and N."""
+    arm = _random_chain(f"mm{Mm}", Mm, np.arange(0 if Mm < 16 else 1, Mm + 1))
     gamma, S, N = 10.0, 37, 203
     sq, al = wl.model(f"mm{Mm}", S, arm.n)
     q = wl.configs(f"mm{Mm}/q", N, arm.n)
