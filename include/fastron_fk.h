@@ -157,6 +157,26 @@ fastron_status fastron_fk_score(const fastron_chain* chain, const fastron_cpoint
                                 const float* alpha, int64_t S, float gamma, const float* q, int64_t N, float* f,
                                 int8_t* label, uint32_t flags, void* stream);
 
+/* ---- scoring that allocates nothing ---------------------------------------
+ * For callers that cannot allocate device memory during a call: code under
+ * HIP graph capture, tight serving loops, hosts that forbid hipMalloc. Same
+ * arguments, validation and results as fastron_fk_score, but the prepared
+ * support set (a2) goes into a static device buffer of
+ * FASTRON_NOALLOC_SCRATCH_BYTES per device that the library holds until the
+ * process ends, instead of stream-ordered scratch; no allocating call is
+ * made. A support set whose prepared size fastron_model_bytes(S, M) exceeds
+ * the buffer is rejected with FASTRON_EINVAL before any device work (at
+ * M = 8 up to S = 20,864 fit; at M = 16 up to S = 10,448). The first call
+ * on a device looks up the buffer's address (FASTRON_EHIP if that fails).
+ * Every call on one device shares its buffer and keeps the last call's
+ * contents: calls ordered on one stream are safe, but calls that overlap in
+ * time on one device (unordered streams, several host threads) race and
+ * give undefined results.                                                   */
+#define FASTRON_NOALLOC_SCRATCH_BYTES (16ll << 20)
+fastron_status fastron_fk_score_noalloc(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,
+                                        const float* alpha, int64_t S, float gamma, const float* q, int64_t N, float* f,
+                                        int8_t* label, uint32_t flags, void* stream);
+
 /* ---- a4: Gram column and F update (Section III-B, Eq. 8; Algorithm 1) ----
  * kcol[j] = K_FK(X_j, X_i) for all j, and F[j] += delta_alpha * kcol[j]
  * (delta_alpha = b_i y_i - F_i for an add or adjust, -alpha_i for a removal).

@@ -40,7 +40,7 @@ EXPORTED = [
     "fastron_mlp_destroy", "fastron_mlp_param_count", "fastron_mlp_set_params", "fastron_mlp_get_params",
     "fastron_mlp_fit_standardisation", "fastron_mlp_forward", "fastron_mlp_gradients", "fastron_mlp_train_epoch",
     "fastron_mlp_screen", "fastron_mlp_screen_workspace_bytes", "fastron_rbf_score", "fastron_rbf_train",
-    "fastron_rbf_train_f64", "fastron_active_samples",
+    "fastron_rbf_train_f64", "fastron_active_samples", "fastron_fk_score_noalloc",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
         "fastron_fk_score_prepared": ([ch, cp, md, vp, i64, vp, vp, ctypes.c_uint32, vp], i32),
         "fastron_score_rational": ([ch, cp, f32, ctypes.c_uint32], i32),
         "fastron_fk_score": ([ch, cp, vp, vp, i64, f32, vp, i64, vp, vp, ctypes.c_uint32, vp], i32),
+        "fastron_fk_score_noalloc": ([ch, cp, vp, vp, i64, f32, vp, i64, vp, vp, ctypes.c_uint32, vp], i32),
         "fastron_gram_update": ([ch, cp, vp, i64, f32, i64, f32, vp, vp, vp], i32),
         "fastron_gram_update_points": ([vp, i64, i32, f32, i64, f32, vp, vp, vp], i32),
         "fastron_train": ([ch, cp, vp, vp, i64, f32, f32, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp], i32),

@@ -162,6 +162,26 @@ def fk_score(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, q:
     return f, lab
 
 
+def fk_score_noalloc(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, q: torch.Tensor,
+                     flags: int = SCORE_FP32, out=None):
+    """fk_score with the prepared support set in the library's static device buffer (no device allocation by
+    the library). `out` = (f, label) preallocated by the caller (either may be None); returns it."""
+    hc = _chain(arm)
+    _dev(support_q, torch.float32, "support_q")
+    _dev(alpha, torch.float32, "alpha")
+    _dev(q, torch.float32, "q")
+    S = support_q.shape[0]
+    if support_q.dim() != 2 or support_q.shape[1] != hc.n or alpha.shape != (S,):
+        raise ValueError("support_q must be (S, n) and alpha (S,)")
+    if q.dim() != 2 or q.shape[1] != hc.n:
+        raise ValueError(f"q must be (N, {hc.n})")
+    f, lab = out if out is not None else _score_outputs(q.shape[0], q.device, True, True)
+    check(nat.lib().fastron_fk_score_noalloc(ctypes.byref(hc.chain), ctypes.byref(hc.cpoints), _ptr(support_q),
+                                             _ptr(alpha), S, float(gamma), _ptr(q), q.shape[0], _ptr(f), _ptr(lab),
+                                             int(flags), _stream()))
+    return f, lab
+
+
 def gram_update_points(P: torch.Tensor, gamma: float, i: int, delta_alpha: float, F: torch.Tensor | None = None,
                        want_kcol=True):
     """kcol = K_FK(X_j, X_i) over j on control points P (N, M, 3); F += delta_alpha * kcol (in place).

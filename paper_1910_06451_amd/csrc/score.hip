@@ -18,6 +18,7 @@
 // lane groups are reduced with shuffles at the end. Points fixed to the base contribute exactly 1 per pair and arrive as
 // the constant f_const.
 #include <cmath>
+#include <mutex>
 
 #include "score_device.h"
 
@@ -243,6 +244,65 @@ fastron_status fastron_fk_score(const fastron_chain* chain, const fastron_cpoint
   if (st != FASTRON_OK) return st;
   if (e != hipSuccess) return fail(FASTRON_EHIP, "hipFreeAsync failed: %s", hipGetErrorString(e));
   return FASTRON_OK;
+}
+
+// Scoring without allocation: the prepared support set goes into this
+// file-scope device buffer (one copy per device, alive until the process
+// ends) instead of stream-ordered scratch. Host code never passes the
+// symbol itself to a kernel: its device address is looked up once per device
+// with hipGetSymbolAddress and kept in g_noalloc_ptr.
+static __device__ __align__(256) unsigned char scratch[FASTRON_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kMaxDevices] = {};
+
+fastron_status noalloc_scratch(void** out) {
+  int dev = 0;
+  FASTRON_HIP(hipGetDevice(&dev));
+  FASTRON_CHECK(dev >= 0 && dev < kMaxDevices, "device %d outside [0, %d)", dev, kMaxDevices);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr)
+      return fail(FASTRON_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return FASTRON_OK;
+}
+}  // namespace
+
+fastron_status fastron_fk_score_noalloc(const fastron_chain* chain, const fastron_cpoints* cp, const float* support_q,
+                                        const float* alpha, int64_t S, float gamma, const float* q, int64_t N, float* f,
+                                        int8_t* label, uint32_t flags, void* stream) {
+  clear_error();
+  ChainArgs c;
+  fastron_status st = pack_chain(chain, cp, &c, true);
+  if (st != FASTRON_OK) return st;
+  FASTRON_CHECK(S >= 0, "S = %lld < 0", (long long)S);
+  FASTRON_CHECK(S == 0 || (support_q && alpha), "support_q and alpha must be non-NULL when S > 0");
+  FASTRON_CHECK(std::isfinite(gamma) && gamma > 0.f, "gamma must be finite and > 0");
+  const int64_t bytes = fastron::model_bytes(S, c.M);
+  FASTRON_CHECK(bytes <= FASTRON_NOALLOC_SCRATCH_BYTES,
+                "S = %lld supports at M = %d need %lld bytes of prepared model; the static buffer holds %lld",
+                (long long)S, c.M, (long long)bytes, (long long)FASTRON_NOALLOC_SCRATCH_BYTES);
+  fastron_model probe{S, c.M, gamma, reinterpret_cast<void*>(256), bytes};
+  st = check_score_args(c, &probe, q, N, f, label, flags);
+  if (st != FASTRON_OK) return st;
+  if (N == 0) return FASTRON_OK;
+  void* blob = nullptr;
+  st = noalloc_scratch(&blob);
+  if (st != FASTRON_OK) return st;
+  // fastron_support_prep writes every byte of the blob that the scoring kernels
+  // read (header, every tile including padded supports), so nothing left by a
+  // previous call survives into this one.
+  fastron_model model{S, c.M, gamma, blob, bytes};
+  st = fastron_support_prep(chain, cp, support_q, alpha, S, gamma, &model, stream);
+  if (st != FASTRON_OK) return st;
+  return score_launch(c, &model, q, N, f, label, flags, as_stream(stream));
 }
 
 }  // extern "C"

@@ -121,6 +121,17 @@ def test_validation_before_device_work(lib):
                                  ctypes.byref(up), None) == nat.FASTRON_EINVAL  # beta < 1
     assert lib.fastron_rbf_train_f64(fake, fake, 100, 7, 0.0, 1.0, 10, 10, fake, fake, fake, ctypes.byref(ns),
                                      ctypes.byref(up), None, None, 0, None) == nat.FASTRON_EINVAL
+    # the scoring form that allocates nothing refuses a model too large for its static buffer up front
+    S_big = 1
+    while lib.fastron_model_bytes(S_big, 8) <= 16 << 20:
+        S_big += 16
+    assert lib.fastron_fk_score_noalloc(ch, cp, fake, fake, S_big, 10.0, fake, 10, fake, None, 0,
+                                        None) == nat.FASTRON_EINVAL
+    assert "static buffer" in nat.last_error()
+    assert lib.fastron_fk_score_noalloc(ch, cp, fake, fake, 100, 0.0, fake, 10, fake, None, 0,
+                                        None) == nat.FASTRON_EINVAL
+    assert lib.fastron_fk_score_noalloc(ch, cp, None, None, 0, 10.0, None, 0, None, None, 0,
+                                        None) == nat.FASTRON_OK  # N = 0
     # active-learning assembly
     assert lib.fastron_active_samples(None, None, 0, 7, None, 0, None, 0, None, None, None) == nat.FASTRON_OK
     assert lib.fastron_active_samples(fake, fake, 10, 7, None, 2, None, 0, fake, None, None) == nat.FASTRON_EINVAL
