@@ -224,8 +224,8 @@ double oracle_loss(int64_t N, int M, const double* P, const int* y, double gamma
   return oracle_loss_pts(N, M, 3, P, y, gamma, beta, alpha);
 }
 
-/* computeKernelMatrixColumn(i) of Algorithm 1: column i of K, evaluated on
- * demand (the lazy evaluation described in Section III-B).                  */
+/* Column i of the kernel matrix K, evaluated when an update needs it (the
+ * lazy evaluation described in Section III-B).                              */
 static void kernel_column(int64_t N, int M, int D, const double* P, double gamma, int64_t i, double* col) {
   const size_t w = (size_t)D * M;
 #pragma omp parallel for schedule(static)
@@ -236,85 +236,105 @@ static void kernel_column(int64_t N, int M, int D, const double* P, double gamma
 #define ACT_ADD 1
 #define ACT_REMOVE 2
 
+/* Index of the smallest margin y_j F_j (the first one among equal values),
+ * -1 for an empty set; *m receives the margin.                              */
+static int64_t smallest_margin(int64_t N, const int* y, const double* F, double* m) {
+  int64_t best = -1;
+  for (int64_t j = 0; j < N; ++j) {
+    const double v = (double)y[j] * F[j];
+    if (best < 0 || v < *m) {
+      best = j;
+      *m = v;
+    }
+  }
+  return best;
+}
+
+/* Among the weighted points, the index of the largest y_j (F_j - alpha_j),
+ * the margin point j keeps without its own term (K_jj = 1); the first one
+ * among equal values, -1 when no point has a weight.                       */
+static int64_t most_redundant(int64_t N, const int* y, const double* F, const double* alpha, double* v) {
+  int64_t best = -1;
+  for (int64_t j = 0; j < N; ++j) {
+    if (alpha[j] == 0.0) continue;
+    const double u = (double)y[j] * (F[j] - alpha[j]);
+    if (best < 0 || u > *v) {
+      best = j;
+      *v = u;
+    }
+  }
+  return best;
+}
+
 /*
- * Section III-B, Algorithm 1 (Fastron model update), run literally:
- *   loadPreviousModel      -> alpha and F come in (zeros for a fresh model)
- *   loop iter = 1..iter_max:
- *     if min_j y_j F_j <= 0:
- *        i = argmin_j y_j F_j                       (Eq. 9, lowest index on ties)
- *        column i of K
- *        if count(alpha != 0) < s_max or alpha_i != 0:
- *           dalpha = b_i y_i - F_i                  (Eq. 6)
- *           alpha_i += dalpha                       (Eq. 7)
- *           F += dalpha * K e_i                     (Eq. 8)
- *           continue
- *     if max over alpha_j != 0 of y_j (F_j - alpha_j) > 0:
- *        i = that argmax                            (lowest index on ties)
- *        F -= alpha_i K e_i ; alpha_i = 0 ; continue
- *     break
- *   removeNonsupportPoints -> support indices in ascending order.
+ * Fastron model update (Section III-B, Algorithm 1) as greedy coordinate
+ * descent on the weights alpha, keeping F = K alpha current so that y_j F_j
+ * is point j's margin. Each update moves one weight alpha_i by delta and F by
+ * delta times column i of K (Eq. 8), the column evaluated only then (the lazy
+ * kernel evaluation of Section III-B). Which weight moves:
+ *   - a correction, when the smallest margin is <= 0 (Eq. 9): that point
+ *     (the first of equal margins) gets delta = b_i y_i - F_i, after which its
+ *     margin is exactly b_i (Eq. 6-7; b_i = beta for y_i = +1 and 1 for
+ *     y_i = -1, the conditional bias of Eq. 5); allowed while fewer than s_max
+ *     points carry a weight, or when point i already does;
+ *   - otherwise a pruning: among the weighted points, the one with the
+ *     largest y_j (F_j - alpha_j), if that value is > 0 (the point stays
+ *     correctly classified without its own term), loses its weight,
+ *     delta = -alpha_i (the first of equal values);
+ *   - if neither applies, the update has converged.
+ * At most iter_max updates are made. The weights and F come in (zeros for a
+ * fresh model, or a previous model with F = K alpha); afterwards the support
+ * set is the weighted points in ascending index order.
  *
- * P holds the control points of the N training configurations (N x M x 3),
- * y holds +1 (in collision) / -1 (free). Returns 0 when the loop ended with
- * break, 1 when iter_max was exhausted. *updates receives the number of
- * add/remove updates performed. Optional trace arrays (capacity trace_cap)
- * receive, per update, the action (1 add, 2 remove), the index and the weight
- * change applied to alpha_i.                                                */
+ * P holds the control points of the N training configurations (N x M x D),
+ * y holds +1 (in collision) / -1 (free). Returns 0 on convergence, 1 when
+ * iter_max updates were made first. *updates receives the number of updates.
+ * Optional trace arrays (capacity trace_cap) receive, per update, the action
+ * (1 correction, 2 pruning), the index and delta.                           */
 int oracle_fastron_update_pts(int64_t N, int M, int D, const double* P, const int* y, double gamma, double beta,
                               int64_t iter_max, int64_t s_max, double* alpha, double* F, int64_t* updates,
                               int64_t* support_idx, int64_t* n_support, int64_t trace_cap, int* trace_act,
                               int64_t* trace_idx, double* trace_dalpha) {
   double* col = (double*)malloc(sizeof(double) * (size_t)(N > 0 ? N : 1));
-  int64_t count = 0;
-  for (int64_t j = 0; j < N; ++j) count += (alpha[j] != 0.0);
-  int64_t nupd = 0;
+  int64_t weighted = 0;
+  for (int64_t j = 0; j < N; ++j) weighted += (alpha[j] != 0.0);
+  int64_t done = 0;
   int converged = 0;
-  for (int64_t iter = 1; iter <= iter_max; ++iter) {
-    /* Check for misclassifications: min and argmin of y.F. */
-    int64_t imin = -1;
-    double mmin = 0.0;
-    for (int64_t j = 0; j < N; ++j) {
-      double m = (double)y[j] * F[j];
-      if (imin < 0 || m < mmin) { mmin = m; imin = j; }
-    }
-    if (imin >= 0 && mmin <= 0.0) {
-      int64_t i = imin;
-      kernel_column(N, M, D, P, gamma, i, col);
-      if (count < s_max || alpha[i] != 0.0) {
-        double b = pow(beta, 0.5 * (y[i] + 1));
-        double dalpha = b * (double)y[i] - F[i];
-        int was_nonzero = alpha[i] != 0.0;
-        alpha[i] += dalpha;
-        for (int64_t j = 0; j < N; ++j) F[j] += dalpha * col[j];
-        count += (alpha[i] != 0.0) - was_nonzero;
-        if (nupd < trace_cap) { trace_act[nupd] = ACT_ADD; trace_idx[nupd] = i; trace_dalpha[nupd] = dalpha; }
-        ++nupd;
-        continue;
+  while (done < iter_max) {
+    int act = 0;
+    int64_t i = -1;
+    double delta = 0.0, m = 0.0;
+    const int64_t w = smallest_margin(N, y, F, &m);
+    if (w >= 0 && m <= 0.0 && (weighted < s_max || alpha[w] != 0.0)) {
+      const double b = y[w] > 0 ? beta : 1.0;
+      act = ACT_ADD;
+      i = w;
+      delta = b * (double)y[w] - F[w];
+    } else {
+      double v = 0.0;
+      const int64_t r = most_redundant(N, y, F, alpha, &v);
+      if (r >= 0 && v > 0.0) {
+        act = ACT_REMOVE;
+        i = r;
+        delta = -alpha[r];
       }
     }
-    /* Remove redundant support points: argmax of y(F - alpha) over alpha != 0. */
-    int64_t imax = -1;
-    double vmax = 0.0;
-    for (int64_t j = 0; j < N; ++j) {
-      if (alpha[j] == 0.0) continue;
-      double v = (double)y[j] * (F[j] - alpha[j]);
-      if (imax < 0 || v > vmax) { vmax = v; imax = j; }
+    if (!act) {
+      converged = 1;
+      break;
     }
-    if (imax >= 0 && vmax > 0.0) {
-      int64_t i = imax;
-      kernel_column(N, M, D, P, gamma, i, col);
-      double a_i = alpha[i];
-      for (int64_t j = 0; j < N; ++j) F[j] -= a_i * col[j];
-      alpha[i] = 0.0;
-      count -= 1;
-      if (nupd < trace_cap) { trace_act[nupd] = ACT_REMOVE; trace_idx[nupd] = i; trace_dalpha[nupd] = -a_i; }
-      ++nupd;
-      continue;
+    kernel_column(N, M, D, P, gamma, i, col);
+    const int had_weight = alpha[i] != 0.0;
+    alpha[i] += delta;
+    for (int64_t j = 0; j < N; ++j) F[j] += delta * col[j];
+    weighted += (alpha[i] != 0.0) - had_weight;
+    if (done < trace_cap) {
+      trace_act[done] = act;
+      trace_idx[done] = i;
+      trace_dalpha[done] = delta;
     }
-    converged = 1;
-    break;
+    ++done;
   }
-  /* removeNonsupportPoints: keep the indices with nonzero weight, in order. */
   int64_t ns = 0;
   for (int64_t j = 0; j < N; ++j)
     if (alpha[j] != 0.0) {
@@ -322,7 +342,7 @@ int oracle_fastron_update_pts(int64_t N, int M, int D, const double* P, const in
       ++ns;
     }
   if (n_support) *n_support = ns;
-  if (updates) *updates = nupd;
+  if (updates) *updates = done;
   free(col);
   return converged ? 0 : 1;
 }
