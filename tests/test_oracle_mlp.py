@@ -105,3 +105,51 @@ def test_adam_constant_gradient_moves_by_lr():
     for t in range(1, 6):
         p, m, v = mo.adam_step(p, [g], m, v, step=t, lr=1e-2)
         np.testing.assert_allclose(p[0], -t * 1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_bf16_round_by_hand():
+    """Nearest bfloat16 (8 significant bits, ties to the even significand) on values worked by hand."""
+    cases = [
+        (1.0 + 2.0 ** -8, 1.0),                        # halfway between 1 and 1 + 2^-7: the even one, 1
+        (1.0 + 3 * 2.0 ** -8, 1.0 + 2.0 ** -6),        # halfway between 1 + 2^-7 (odd) and 1 + 2^-6 (even)
+        (1.0 + 2.0 ** -8 + 2.0 ** -20, 1.0 + 2.0 ** -7),  # just above halfway: up
+        (255.5, 256.0),                                # 255 (odd) and 256 (even, next binade): 256
+        (255.25, 255.0),                               # below halfway: down
+        (-3.0, -3.0), (0.0, 0.0),
+        (-(1.0 + 2.0 ** -8), -1.0),
+        (0.1, 0.10009765625),                          # 0.1 = 1.6 * 2^-4 -> 205/128 * 2^-4 = 0.10009765625
+    ]
+    for x, want in cases:
+        assert mo.bf16_round(x) == want, (x, mo.bf16_round(x), want)
+    # any value: the result has 8 significant bits and no other such value is nearer
+    g = np.random.default_rng(3)
+    x = g.standard_normal(2000) * np.exp2(g.integers(-20, 20, 2000))
+    r = mo.bf16_round(x)
+    m, e = np.frexp(r)
+    assert np.all(np.ldexp(m, 8) == np.rint(np.ldexp(m, 8)))
+    ulp = np.ldexp(1.0, np.frexp(x)[1] - 8)
+    assert np.all(np.abs(r - x) <= 0.5 * ulp)
+
+
+def test_bf16_forms_reduce_to_the_pinned_forms():
+    """With the rounding replaced by the identity, forward_bf16 / backward_bf16 are forward / backward step for
+    step (bit-identical), so the BF16 forms add exactly the rounding points and nothing else; on the hand-worked
+    network, whose values are all bfloat16 numbers, forward_bf16 gives the hand-worked logits exactly."""
+    g = np.random.default_rng(2)
+    params = _params(g)
+    x = g.standard_normal((9, 6))
+    y = np.where(g.random(9) < 0.5, 1, -1)
+    mu, sd = x.mean(axis=0), x.std(axis=0) + 0.5
+    ident = lambda v: np.asarray(v, np.float64)
+    z, cache = mo.forward(params, x, mu, sd)
+    zq, cq = mo.forward_bf16(params, x, mu, sd, rnd=ident)
+    np.testing.assert_array_equal(z, zq)
+    for a, b in zip(mo.backward(params, cache, z, y), mo.backward_bf16(params, cq, zq, y, rnd=ident)):
+        np.testing.assert_array_equal(a, b)
+    # the rounding does act: the rounded forms differ from the FP64 forms on general values
+    zr, cr = mo.forward_bf16(params, x, mu, sd)
+    assert np.max(np.abs(zr - z)) > 0
+    gd = _golden("mlp_tiny_forward.json")
+    ps = [np.array(gd[k], np.float64) for k in ("W1", "b1", "W2", "b2", "w3")] + [np.array(gd["b3"])]
+    zt, _ = mo.forward_bf16(ps, np.array(gd["x"]), np.array(gd["mu"]), np.array(gd["sd"]))
+    np.testing.assert_array_equal(zt, np.array(gd["z"]))
