@@ -925,6 +925,16 @@ fastron_status fastron_mlp_get_params(const fastron_mlp* n, float* params, float
   return FASTRON_OK;
 }
 
+fastron_status fastron_mlp_get_adam_state(const fastron_mlp* n, float* m, float* v, int64_t* step, void* stream) {
+  clear_error();
+  FASTRON_CHECK(n != nullptr, "network is NULL");
+  hipStream_t s = as_stream(stream);
+  if (m) FASTRON_HIP(hipMemcpyAsync(m, n->adam_m, n->n_params * 4, hipMemcpyDeviceToDevice, s));
+  if (v) FASTRON_HIP(hipMemcpyAsync(v, n->adam_v, n->n_params * 4, hipMemcpyDeviceToDevice, s));
+  if (step) *step = n->step;
+  return FASTRON_OK;
+}
+
 fastron_status fastron_mlp_fit_standardisation(fastron_mlp* n, const float* P, int64_t N, void* stream) {
   clear_error();
   FASTRON_CHECK(n && P, "network and P must be non-NULL");
