@@ -316,6 +316,10 @@ fastron_status fastron_mlp_set_params(fastron_mlp* net, const float* params, con
                                       void* stream);
 fastron_status fastron_mlp_get_params(const fastron_mlp* net, float* params, float* grads, float* mu, float* sd,
                                       void* stream);
+/* Adam state: first and second moments (device [fastron_mlp_param_count],
+ * same order as the parameters; either may be NULL) and the number of
+ * optimiser steps taken since the last fastron_mlp_set_params (host).     */
+fastron_status fastron_mlp_get_adam_state(const fastron_mlp* net, float* m, float* v, int64_t* step, void* stream);
 fastron_status fastron_mlp_fit_standardisation(fastron_mlp* net, const float* P, int64_t N, void* stream);
 fastron_status fastron_mlp_forward(fastron_mlp* net, const float* P, int64_t N, float* logits, void* stream);
 fastron_status fastron_mlp_gradients(fastron_mlp* net, const float* P, const int8_t* y, int64_t N, float* loss,
@@ -363,12 +367,20 @@ fastron_status fastron_rbf_train_f64(const float* X, const int8_t* y, int64_t N,
  * explore [E][n] (uniform samples over the C-space; alpha_out = 0). The random
  * draws are the caller's. X_out holds S (1 + k) + E rows of n floats;
  * alpha_out (may be NULL) as many floats. All arrays are device memory. The
- * update then labels every row (fastron_label_capsule_box), takes F = the
+ * update then labels every row (fastron_label_capsule_box), zeroes the weights
+ * of supports whose label changed (fastron_active_relabel), takes F = the
  * current model's score of every row (fastron_fk_score; F = K alpha) and
- * runs fastron_train_points from (alpha_out, F) on the rows' control points.                                  */
+ * runs fastron_train_points from (alpha_out, F) on the rows' control points. */
 fastron_status fastron_active_samples(const float* support_q, const float* alpha, int64_t S, int32_t n,
                                       const float* noise, int32_t k, const float* explore, int64_t E, float* X_out,
                                       float* alpha_out, void* stream);
+
+/* After relabelling, a support point whose new label y[i] disagrees with the
+ * sign of its weight alpha[i] violates the constraint y_i alpha_i >= 0 of
+ * Eq. 5 that Algorithm 1 maintains; fastron_active_relabel sets such weights
+ * to zero for the first S rows (y int8, alpha float, device, in place), so
+ * that the update starts from a model that satisfies it. S == 0 is a no-op.  */
+fastron_status fastron_active_relabel(const int8_t* y, int64_t S, float* alpha, void* stream);
 
 /* ---- a9: geometric labels -------------------------------------------------
  * Stands in for the ground-truth collision checker of Section IV: link i is a

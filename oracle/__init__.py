@@ -50,6 +50,11 @@ MAX_JOINTS = 64
 MAX_POINTS = 64
 
 
+# Plain -O2 for the baseline x86-64 target: no -march, so no FMA contraction, which keeps every FP64 result
+# the unfused arithmetic of the C source (the device's FP64 training mode matches it step for step).
+BUILD_FLAGS = "gcc -O2 -fopenmp (x86-64 baseline ISA, no FMA contraction)"
+
+
 def build() -> str:
     """Compile the C oracle with gcc (plain -O2, OpenMP across queries)."""
     cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-Wall", "-o", _LIB_PATH, _SRC, "-lm"]
@@ -350,9 +355,9 @@ def active_update(dh, frame, support_q, alpha, gamma, noise, k, explore, radius,
                   beta=1.0, iter_max=None, s_max=None):
     """One model update after the two-stage active learning of Section III-B: the new training set is the
     support set, k samples near each support point (support + noise rows, in float32 like the inputs) and
-    the exploration samples; every row gets a geometric label; F starts as the current model's score of
-    every row (F = K alpha, alpha kept on the supports, on the control points rounded to float32) and
-    Algorithm 1 runs from there on those points. Returns dict(X, y, clearance, F0 and the fastron_update result)."""
+    the exploration samples; every row gets a geometric label; supports whose new label disagrees with the
+    sign of their weight get weight 0; F starts as the current model's score of every row (F = K alpha on the
+    control points rounded to float32) and Algorithm 1 runs from there on those points. Returns dict(X, y, clearance, F0 and the fastron_update result)."""
     sq = np.asarray(support_q, dtype=np.float32)
     S, n = sq.shape
     noise = np.asarray(noise, dtype=np.float32).reshape(S * k, n)
@@ -362,8 +367,13 @@ def active_update(dh, frame, support_q, alpha, gamma, noise, k, explore, radius,
     a0 = np.zeros(X.shape[0])
     a0[:S] = np.asarray(alpha, dtype=np.float64)
     y, clearance = capsule_box_labels(dh, X.astype(np.float64), radius, boxes_lo, boxes_hi)
+    # A support point whose new label disagrees with the sign of its weight breaks the constraint
+    # y_i alpha_i >= 0 of Eq. 5 that Algorithm 1 maintains; its weight is set to zero before the update
+    # (the previous model projected onto the constraint), so F0 = K alpha starts from a feasible model.
+    flipped = y[:S].astype(np.float64) * a0[:S] < 0
+    a0[:S][flipped] = 0.0
     P = control_points(dh, frame, X.astype(np.float64)).astype(np.float32).astype(np.float64)
     F0 = score_points(P[:S], a0[:S], gamma, P)  # K alpha on the points the update trains on
     out = fastron_update(P, y, gamma, beta=beta, iter_max=iter_max, s_max=s_max, alpha=a0, F=F0)
-    out.update(X=X, y=y, clearance=clearance, F0=F0)
+    out.update(X=X, y=y, clearance=clearance, F0=F0, alpha0=a0, relabelled=np.nonzero(flipped)[0])
     return out

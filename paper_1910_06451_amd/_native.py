@@ -40,7 +40,8 @@ EXPORTED = [
     "fastron_mlp_destroy", "fastron_mlp_param_count", "fastron_mlp_set_params", "fastron_mlp_get_params",
     "fastron_mlp_fit_standardisation", "fastron_mlp_forward", "fastron_mlp_gradients", "fastron_mlp_train_epoch",
     "fastron_mlp_screen", "fastron_mlp_screen_workspace_bytes", "fastron_rbf_score", "fastron_rbf_train",
-    "fastron_rbf_train_f64", "fastron_active_samples", "fastron_fk_score_noalloc",
+    "fastron_rbf_train_f64", "fastron_active_samples", "fastron_fk_score_noalloc", "fastron_mlp_get_adam_state",
+    "fastron_active_relabel",
 ]
 
 
@@ -120,6 +121,7 @@ def lib():
         "fastron_mlp_param_count": ([vp], i64),
         "fastron_mlp_set_params": ([vp, vp, vp, vp, vp], i32),
         "fastron_mlp_get_params": ([vp, vp, vp, vp, vp, vp], i32),
+        "fastron_mlp_get_adam_state": ([vp, vp, vp, pi64, vp], i32),
         "fastron_mlp_fit_standardisation": ([vp, vp, i64, vp], i32),
         "fastron_mlp_forward": ([vp, vp, i64, vp, vp], i32),
         "fastron_mlp_gradients": ([vp, vp, vp, i64, ctypes.POINTER(ctypes.c_float), vp], i32),
@@ -131,6 +133,7 @@ def lib():
         "fastron_rbf_train_f64": ([vp, vp, i64, i32, f64, f64, i64, i64, vp, vp, vp, pi64, pi64, vp, vp, i64, vp],
                                   i32),
         "fastron_active_samples": ([vp, vp, i64, i32, vp, i32, vp, i64, vp, vp, vp], i32),
+        "fastron_active_relabel": ([vp, i64, vp, vp], i32),
         "fastron_tune_set": ([ctypes.c_char_p, i64], i32),
         "fastron_tune_get": ([ctypes.c_char_p], i64),
         "fastron_last_error": ([], ctypes.c_char_p),

@@ -18,7 +18,7 @@ from ._native import HostChain, check
 __all__ = [
     "control_point_frames", "fk_points", "model_bytes", "support_prep", "fk_score_prepared", "fk_score", "gram_update", "gram_update_points", "train", "train_points",
     "train_batch",
-    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set", "active_samples", "active_update",
+    "rbf_score", "rbf_train", "score_rational", "tune_get", "tune_set", "active_samples", "active_relabel", "active_update",
     "label_capsule_box", "PreparedModel", "Batch", "MLP", "SCORE_FP32", "SCORE_BF16", "SCORE_VALU", "BF16_PLAIN", "BF16_SPLIT2",
     "BF16_SPLIT3",
 ]
@@ -417,17 +417,31 @@ def active_samples(support_q: torch.Tensor, alpha: torch.Tensor, noise: torch.Te
     return X, a0
 
 
+def active_relabel(y: torch.Tensor, alpha: torch.Tensor, S: int):
+    """Zero (in place) the weights of the first S rows whose label y disagrees with the weight's sign."""
+    _dev(y, torch.int8, "y")
+    _dev(alpha, torch.float32, "alpha")
+    if S < 0 or S > min(y.shape[0], alpha.shape[0]):
+        raise ValueError("S must lie within both arrays")
+    check(nat.lib().fastron_active_relabel(_ptr(y), int(S), _ptr(alpha), _stream()))
+    return alpha
+
+
 def active_update(arm, support_q: torch.Tensor, alpha: torch.Tensor, gamma: float, noise: torch.Tensor,
                   k: int, explore: torch.Tensor, boxes_lo, boxes_hi, beta: float = 1.0,
                   iter_max: int | None = None, s_max: int | None = None):
     """One model update after two-stage active learning (Section III-B), every step on the device: assemble
-    the new training set, label every row geometrically, start from F = the current model's score of every
-    row (F = K alpha) and run Algorithm 1. Returns train_points()'s dict plus X, y and F0."""
+    the new training set, label every row geometrically, zero the weights of supports whose label changed,
+    start from F = the current model's score of every row (F = K alpha) and run Algorithm 1. Returns
+    train_points()'s dict plus X, y, F0 and the starting weights alpha0."""
     X, a0 = active_samples(support_q, alpha, noise, k, explore)
     y, _ = label_capsule_box(arm, X, arm.radius, boxes_lo, boxes_hi, want_clearance=False)
-    F0, _ = fk_score(arm, support_q, alpha, gamma, X, want_label=False)
+    S = support_q.shape[0]
+    active_relabel(y, a0, S)
+    F0, _ = fk_score(arm, support_q, a0[:S], gamma, X, want_label=False)
+    alpha0 = a0.clone()
     out = train_points(fk_points(arm, X), y, gamma, beta=beta, iter_max=iter_max, s_max=s_max, alpha=a0, F=F0)
-    out.update(X=X, y=y, F0=F0)
+    out.update(X=X, y=y, F0=F0, alpha0=alpha0)
     return out
 
 
@@ -503,10 +517,11 @@ class Batch:
             nat.lib().fastron_batch_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # No library calls while the interpreter shuts down (the HIP runtime may be tearing down too); the
-        # process releases the device memory anyway.
-        if sys.is_finalizing():
+        # process releases the device memory anyway. The check is bound at definition time because module
+        # globals such as `sys` may already be cleared when a late destructor runs.
+        if _finalizing():
             return
         try:
             self.close()
@@ -540,6 +555,14 @@ class MLP:
         sd = torch.empty(self.d_in, dtype=torch.float32, device=device)
         check(nat.lib().fastron_mlp_get_params(self._h, _ptr(p), _ptr(g), _ptr(mu), _ptr(sd), _stream()))
         return p, g, mu, sd
+
+    def adam_state(self, device):
+        """(m, v, step): the optimiser's moments and its step count."""
+        m = torch.empty(self.n_params, dtype=torch.float32, device=device)
+        v = torch.empty(self.n_params, dtype=torch.float32, device=device)
+        step = ctypes.c_int64(0)
+        check(nat.lib().fastron_mlp_get_adam_state(self._h, _ptr(m), _ptr(v), ctypes.byref(step), _stream()))
+        return m, v, int(step.value)
 
     def _points(self, P):
         _dev(P, torch.float32, "P")
@@ -602,10 +625,11 @@ class MLP:
             nat.lib().fastron_mlp_destroy(self._h)
             self._h = None
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # No library calls while the interpreter shuts down (the HIP runtime may be tearing down too); the
-        # process releases the device memory anyway.
-        if sys.is_finalizing():
+        # process releases the device memory anyway. The check is bound at definition time because module
+        # globals such as `sys` may already be cleared when a late destructor runs.
+        if _finalizing():
             return
         try:
             self.close()

@@ -31,6 +31,15 @@ __global__ void __launch_bounds__(256) k_active_samples(const float* __restrict_
     if (alpha_out) alpha_out[r] = 0.f;
   }
 }
+
+// Supports whose new label disagrees with the sign of their weight: weight 0.
+__global__ void __launch_bounds__(256) k_active_relabel(const int8_t* __restrict__ y, int64_t S,
+                                                         float* __restrict__ alpha) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= S) return;
+  const float a = alpha[r];
+  if ((y[r] > 0 && a < 0.f) || (y[r] < 0 && a > 0.f)) alpha[r] = 0.f;
+}
 }  // namespace fastron
 
 using namespace fastron;
@@ -52,6 +61,18 @@ extern "C" fastron_status fastron_active_samples(const float* support_q, const f
   FASTRON_CHECK(blocks <= INT32_MAX, "too many rows");
   hipLaunchKernelGGL(k_active_samples, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), support_q, alpha, S,
                      (int)n, noise, (int)k, explore, E, X_out, alpha_out);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+extern "C" fastron_status fastron_active_relabel(const int8_t* y, int64_t S, float* alpha, void* stream) {
+  clear_error();
+  FASTRON_CHECK(S >= 0, "S < 0");
+  if (S == 0) return FASTRON_OK;
+  FASTRON_CHECK(y && alpha, "y and alpha must be non-NULL");
+  const int64_t blocks = (S + 255) / 256;
+  FASTRON_CHECK(blocks <= INT32_MAX, "S too large");
+  hipLaunchKernelGGL(k_active_relabel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), y, S, alpha);
   FASTRON_HIP(hipGetLastError());
   return FASTRON_OK;
 }

@@ -1,6 +1,7 @@
 """Parity of the model update after two-stage active learning (Section III-B) with the FP64 oracle: the
 device assembles the new training set (supports, samples near each support point, uniform samples), labels
-every row, starts from F = the current model's score of every row and runs Algorithm 1.
+every row, zeroes the weights of supports whose label flipped, starts from F = the current model's score of
+every row and runs Algorithm 1.
 
 The assembled rows must be bit-identical (the perturbation is one float32 addition on both sides), the
 labels identical, F0 within the FP32 bound of the score tests, and the updated FP32 model is judged by
@@ -44,8 +45,13 @@ def test_active_update_matches_oracle(oracle_mod, dev, arm_name, k, E):
     yg = out["y"].cpu().numpy()
     near_zero = np.abs(ref["clearance"]) < 1e-9
     np.testing.assert_array_equal(yg[~near_zero], ref["y"][~near_zero])
+    # supports whose label flipped start from weight 0 on both sides (identical labels decide it)
+    S = len(sup)
+    if not near_zero[:S].any():
+        np.testing.assert_array_equal(out["alpha0"].cpu().numpy().astype(np.float64), ref["alpha0"])
+    assert len(ref["relabelled"]) > 0
     PX = oracle_mod.control_points(dh, arm.frames, X.astype(np.float64))
-    tol = error_bound(PX[: len(sup)], al, gamma, PX)
+    tol = error_bound(PX[:S], ref["alpha0"][:S].astype(np.float32), gamma, PX)
     assert np.all(np.abs(out["F0"].cpu().numpy() - ref["F0"]) <= tol)
     assert out["converged"] and ref["converged"]
     alpha = out["alpha"].cpu().numpy()
@@ -55,7 +61,8 @@ def test_active_update_matches_oracle(oracle_mod, dev, arm_name, k, E):
     F_oracle = oracle_mod.score_points(P32[s2], alpha[s2].astype(np.float64), gamma, P32)
     margins = ref["y"] * F_oracle
     non_positive = assert_claim2(ref["y"], F_oracle, out["F"].cpu().numpy())
-    print(dict(rows=X.shape[0], gpu_support=int(s2.shape[0]), oracle_support=int(ref["support"].shape[0]),
+    print(dict(rows=X.shape[0], relabelled=int(len(ref["relabelled"])), gpu_support=int(s2.shape[0]),
+               oracle_support=int(ref["support"].shape[0]),
                gpu_updates=out["updates"], oracle_updates=ref["updates"], min_margin=float(margins.min()),
                non_positive_fp64_margins=non_positive))
     assert abs(s2.shape[0] - ref["support"].shape[0]) <= 0.05 * ref["support"].shape[0] + 5

@@ -191,7 +191,15 @@ def test_active_update(oracle_mod):
     np.testing.assert_array_equal(X[S:3 * S], (np.repeat(sq, 2, axis=0) + noise).astype(np.float32))
     np.testing.assert_array_equal(X[3 * S:], explore)
     Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64)).astype(np.float32).astype(np.float64)
-    np.testing.assert_allclose(out["F0"][:S], oracle_mod.gram(Ps, 10.0) @ al, rtol=0, atol=1e-12)
+    # supports whose label flipped with the move start from weight 0, the others keep theirs
+    y_new, _ = oracle_mod.capsule_box_labels(dh, sq.astype(np.float64), arm.radius, lo2, hi2)
+    flipped = np.sign(al) != y_new
+    assert flipped.any() and not flipped.all()
+    np.testing.assert_array_equal(out["relabelled"], np.nonzero(flipped)[0])
+    a_kept = np.where(flipped, 0.0, al)
+    np.testing.assert_array_equal(out["alpha0"][:S], a_kept)
+    np.testing.assert_array_equal(out["alpha0"][S:], 0.0)
+    np.testing.assert_allclose(out["F0"][:S], oracle_mod.gram(Ps, 10.0) @ a_kept, rtol=0, atol=1e-12)
     assert out["converged"]
     PX = oracle_mod.control_points(dh, arm.frames, X.astype(np.float64)).astype(np.float32).astype(np.float64)
     K = oracle_mod.gram(PX, 10.0)
