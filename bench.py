@@ -26,12 +26,27 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# Derived ALU ceiling of the FP32 fused score, in control-point kernel
-# evaluations (cp-evals) per second: the instructions one (support, query) pair
-# with Mm moving points needs, priced at the published rates (FP32 MFMA and
-# vector FMA 128 lanes/clk/CU, the 157.3 TFLOP/s figure; transcendentals 32
-# lanes/clk/CU) with the matrix and vector units not overlapping. In units of
-# 1/128 CU clock per pair:
+# Roofline of the FP32 fused score against the published FP32 peak
+# (157.3 TFLOP/s: 256 CUs x 2.4 GHz x 256 FLOP/clk/CU, the vector and the
+# matrix unit alike). Algorithmic work per control-point evaluation (cp-eval,
+# one K_RQ): the squared distance and t = 1 + gamma/2 d^2 as a 3-term dot
+# product plus the norms, 8 FLOP, and the square-and-accumulate of 1/t^2,
+# 2 FLOP (the reciprocal itself is a transcendental, not counted); per
+# (support, query) pair the alpha/M weighting adds 2 FLOP. Fixed base-frame
+# points add exactly 1/M per pair and are folded into a constant, so only the
+# Mm moving points count.
+FP32_PEAK_TFLOPS = 157.3
+
+
+def score_flops(Mm, S, N):
+    return N * S * (10.0 * Mm + 2.0)
+
+
+# Instruction-priced ALU ceiling of the same kernel, in cp-evals per second:
+# the instructions one pair with Mm moving points needs, priced at the
+# published rates (FP32 MFMA and vector FMA 128 lanes/clk/CU; transcendentals
+# 32 lanes/clk/CU) with the matrix and vector units not overlapping. In units
+# of 1/128 CU clock per pair:
 #   cross term with the norms on the matrix unit        4 Mm
 #   saturated-reciprocal sum: Mm reciprocals (4 each) + Mm FMAs + 1 weighting FMA
 #                                                      -> 9 Mm + 1 in all
@@ -41,6 +56,7 @@ sys.path.insert(0, ROOT)
 # e.g. Mm = 7: 8.60e12 (saturated) and 10.39e12 (fraction) cp-evals/s.
 def alu_peak(Mm, rational):
     return 256 * 2.4e9 * 128 * Mm / ((7 * Mm + 4) if rational else (9 * Mm + 1))
+
 
 # HBM bytes per launch of the FP32 score kernel on this workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE, KiB per dispatch), each scaled
@@ -86,9 +102,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
     ap.add_argument("--legs",
-                    default="kernels,forms,precision,dof3,train,compare,obstacles,active,batched,retrain,screen",
-                    help="comma-separated extra legs (kernels, forms, precision, dof3, train, compare, obstacles, "
-                         "active, batched, retrain, screen)")
+                    default="peaks,kernels,forms,precision,dof3,train,compare,obstacles,active,batched,retrain,screen",
+                    help="comma-separated extra legs (peaks, kernels, forms, precision, dof3, train, compare, "
+                         "obstacles, active, batched, retrain, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=10, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -99,7 +115,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "active", "batched",
+    unknown = legs - {"peaks", "kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "active", "batched",
                       "retrain", "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
@@ -178,8 +194,13 @@ def main():
     achieved = cp_per_launch / (k_ms * 1e-3)
     rational = api.score_rational(arm, gamma)
     peak = alu_peak(Mm, rational)
-    roofline = {"bound": "alu", "achieved": achieved / 1e12, "peak": peak / 1e12,
-                "unit": "Tcp-eval/s", "frac": achieved / peak, "traffic": score_traffic(Mm, S, N),
+    tflops = score_flops(Mm, S, N) / (k_ms * 1e-3) / 1e12
+    roofline = {"bound": "alu", "achieved": tflops, "peak": FP32_PEAK_TFLOPS,
+                "unit": "TFLOP/s", "frac": tflops / FP32_PEAK_TFLOPS, "traffic": score_traffic(Mm, S, N),
+                "flops_per_launch": score_flops(Mm, S, N),
+                "flops_per_unit": "10 per cp-eval (dot product + t: 8, square-accumulate: 2) + 2 per pair",
+                "cp_evals_per_s": achieved, "instruction_ceiling_cp_evals_per_s": peak,
+                "frac_of_instruction_ceiling": achieved / peak,
                 "sum_form": "running fraction" if rational else "saturated reciprocal",
                 "traffic_unit": "HBM bytes per launch",
                 # queries (n floats each) + the FP32 part of the packed support set (256 B header,
@@ -193,6 +214,10 @@ def main():
 
     extras = {}
     checks = []  # GPU results queued for the FP64 comparison of the CPU leg
+    if "peaks" in legs:
+        log("[bench] issue-rate probes and device copy")
+        extras["peaks"] = peaks_run(dev)
+        roofline["measured_ceiling"] = measured_ceiling(extras["peaks"], Mm, rational, achieved)
     if "kernels" in legs:
         log("[bench] FK, Gram-column and labeller kernels on 4,194,304 configurations")
         extras["kernels"] = kernels_run(api, wl, arm, dev)
@@ -268,6 +293,90 @@ def main():
             v.pop("labels", None)
         out["extras"] = extras
     print(json.dumps(out), flush=True)
+
+
+def peaks_run(dev, copy_bytes=256 << 20):
+    """Issue rates measured on this device (probe/peaks.hip): each instruction kind alone in independent
+    chains, at 2, 4 and 8 waves per SIMD, in SIMD cycles per wave64 instruction at the clock the kernel ran
+    (shader clock counter against the 100 MHz constant clock); mixed rounds of one matrix instruction and 8
+    vector multiplies; and a plain device copy of copy_bytes."""
+    import ctypes
+
+    import torch
+
+    from paper_1910_06451_amd import build as hb
+
+    lib = ctypes.CDLL(hb.PROBE_LIB)
+    names = ["v_mul_f32", "v_fma_f32", "v_rcp_f32", "v_mfma_f32_16x16x4_f32", "v_mfma_f32_16x16x32_bf16",
+             "mfma_f32+8 v_mul_f32", "mfma_bf16+8 v_mul_f32", "8 v_mul_f32+v_rcp_f32"]
+    iters = [4000, 4000, 1200, 600, 1200, 500, 600, 3000]
+    out = {}
+    for kind, name in enumerate(names):
+        vo, mo = ctypes.c_int(0), ctypes.c_int(0)
+        lib.probe_ops_per_iter(kind, ctypes.byref(vo), ctypes.byref(mo))
+        rows = {}
+        for wps in (2, 4, 8):
+            ms, cyc, tck, ncu = ctypes.c_double(0), ctypes.c_ulonglong(0), ctypes.c_ulonglong(0), ctypes.c_int(0)
+            rc = lib.probe_run(kind, wps, iters[kind], ctypes.byref(ms), ctypes.byref(cyc), ctypes.byref(tck),
+                               ctypes.byref(ncu))
+            if rc != 0:
+                raise RuntimeError(f"probe {name} failed ({rc})")
+            ghz = cyc.value / (tck.value / 100e6) / 1e9 if tck.value else float("nan")
+            simd_cycles = ms.value * 1e-3 * ghz * 1e9          # cycles each SIMD spent on its waves
+            rounds = wps * iters[kind]                          # loop iterations per SIMD
+            row = {"ms": ms.value, "clock_ghz": ghz}
+            if mo.value and vo.value:
+                row["cycles_per_round"] = simd_cycles / rounds / (mo.value // 8 or 1) / 8
+                row["cycles_per_vector_op_beyond_matrix"] = None
+            elif mo.value:
+                row["cycles_per_instruction"] = simd_cycles / (rounds * mo.value)
+            else:
+                row["cycles_per_instruction"] = simd_cycles / (rounds * vo.value)
+            rows[f"{wps}_waves_per_simd"] = row
+        out[name] = rows
+    # mixed rounds: cost of each vector multiply beyond the matrix instruction's own cycles
+    for mixed, alone in (("mfma_f32+8 v_mul_f32", "v_mfma_f32_16x16x4_f32"),
+                         ("mfma_bf16+8 v_mul_f32", "v_mfma_f32_16x16x32_bf16")):
+        for key, row in out[mixed].items():
+            row["cycles_per_vector_op_beyond_matrix"] = (row["cycles_per_round"]
+                                                         - out[alone][key]["cycles_per_instruction"]) / 8
+    src = torch.ones(copy_bytes // 4, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    ms = ctypes.c_double(0)
+    if lib.probe_copy(ctypes.c_void_p(src.data_ptr()), ctypes.c_void_p(dst.data_ptr()), copy_bytes, 10,
+                      ctypes.byref(ms)) != 0:
+        raise RuntimeError("probe copy failed")
+    out["device_copy"] = {"bytes": copy_bytes, "ms": ms.value, "GB_per_s": 2 * copy_bytes / (ms.value * 1e-3) / 1e9,
+                          "frac_of_8TBps": 2 * copy_bytes / (ms.value * 1e-3) / 8e12}
+    del src, dst
+    return out
+
+
+def measured_ceiling(peaks, Mm, rational, achieved_cp):
+    """Ceiling of the FP32 fused score from the measured issue rates (4 waves per SIMD), each converted to time
+    at the clock its own probe ran (the part clocks down under dense vector work), the matrix and vector
+    units not overlapping: per (support, query) pair Mm matrix instructions cover 256 pairs each; the running
+    fraction takes 3 Mm vector instructions and one reciprocal per pair (the saturated form Mm reciprocals and
+    Mm + 1 FMAs), 64 pairs per wave64 instruction. Also the same with the vector multiplies at the rate
+    measured beside matrix work (mixed stream, at that probe's clock)."""
+    key = "4_waves_per_simd"
+    row = lambda name: peaks[name][key]
+    c_mfma, f_mfma = row("v_mfma_f32_16x16x4_f32")["cycles_per_instruction"], row("v_mfma_f32_16x16x4_f32")["clock_ghz"]
+    c_mul, f_mul = row("v_mul_f32")["cycles_per_instruction"], row("v_mul_f32")["clock_ghz"]
+    c_rcp, f_rcp = row("v_rcp_f32")["cycles_per_instruction"], row("v_rcp_f32")["clock_ghz"]
+    mix = row("mfma_f32+8 v_mul_f32")
+    c_mix, f_mix = mix["cycles_per_vector_op_beyond_matrix"], mix["clock_ghz"]
+    vec, rcp = (3 * Mm, 1) if rational else (Mm + 1, Mm)
+    simds = 1024
+    ns_iso = (Mm * c_mfma / 256 / f_mfma + vec * c_mul / 64 / f_mul + rcp * c_rcp / 64 / f_rcp)  # ns per pair
+    ns_mix = (Mm * c_mfma / 256 + vec * c_mix / 64) / f_mix + rcp * c_rcp / 64 / f_rcp
+    out = {}
+    for name, ns in (("isolated_rates", ns_iso), ("mixed_stream_rates", ns_mix)):
+        ceil = simds * Mm / (ns * 1e-9)
+        out[name] = {"cp_evals_per_s": ceil, "frac": achieved_cp / ceil}
+    out["clock_ghz"] = {"mfma_f32": f_mfma, "v_mul_f32": f_mul, "v_rcp_f32": f_rcp, "mixed": f_mix}
+    out["cycles"] = {"mfma_f32": c_mfma, "v_mul_f32": c_mul, "v_rcp_f32": c_rcp, "v_mul_f32_beside_mfma": c_mix}
+    return out
 
 
 # Kernel width for training on geometric labels of the 7-DOF arm, picked by a
@@ -589,7 +698,8 @@ def active_run(api, wl, arm, dev, steps=10, n_init=20_000, k=2, sigma=0.1, n_exp
             else:
                 X, a0 = api.active_samples(sq, sa, noise, k, explore)
                 yX, _ = api.label_capsule_box(arm, X, arm.radius, lo2, hi2, want_clearance=False)
-                F0, _ = api.rbf_score(sq, sa, gam, X, want_label=False)
+                api.active_relabel(yX, a0, S)
+                F0, _ = api.rbf_score(sq, a0[:S].contiguous(), gam, X, want_label=False)
                 o = api.rbf_train(X, yX, gam, alpha=a0, F=F0)
             torch.cuda.synchronize()
             t_upd = time.perf_counter() - t0
@@ -833,6 +943,7 @@ def cpu_baseline(arm, sq, al, q, gamma, f_gpu, lab_gpu, seconds, extras, checks)
     for name, form in extras.get("forms", {}).items():
         form["sign_agreement_vs_fp64"] = float(np.mean(form["labels"][idx] == sign_ref))
     cpu = {"value": n / dt, "unit": "checks/s", "cores": oracle.num_threads(), "kind": "oracle",
+           "build": oracle.BUILD_FLAGS,
            "sample": f"{n} evenly spaced queries of the same workload (S={sq.shape[0]}), {dt:.1f} s",
            "logical_cpus": os.cpu_count(), "physical_cores": _physical_cores(), "cpu_model": _cpu_model()}
     # one thread on a 10,000-query subset (the paper's thread count is not stated)

@@ -11,6 +11,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libfastron_fk.so")
+PROBE_SRC = os.path.join(HERE, "probe", "peaks.hip")
+PROBE_LIB = os.path.join(HERE, "libfastron_probe.so")
 OBJDIR = os.path.join(HERE, "_build")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -39,9 +41,15 @@ def _compile(src):
 
 
 def build(jobs: int = 8, verbose: bool = False) -> str:
+    """Builds libfastron_fk.so (every csrc/*.hip) and the issue-rate probe library libfastron_probe.so
+    (probe/peaks.hip, used only by the benchmark's roofline leg)."""
     os.makedirs(OBJDIR, exist_ok=True)
     with ThreadPoolExecutor(max_workers=jobs) as ex:
-        results = list(ex.map(_compile, sources()))
+        results = list(ex.map(_compile, sources() + [PROBE_SRC]))
+    probe_obj = results.pop()[0]
+    tmp = PROBE_LIB + ".tmp"
+    subprocess.run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, probe_obj], check=True)
+    os.replace(tmp, PROBE_LIB)
     for obj, err in results:
         if verbose and err.strip():
             print(err, file=sys.stderr)
