@@ -739,7 +739,17 @@ def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
     b.prepare(sq, al)
     f = torch.empty(N_tot, dtype=torch.float32, device=dev)
     lab = torch.empty(N_tot, dtype=torch.int8, device=dev)
+    t0 = time.perf_counter()
     tq = b.autotune(q, (f, lab))
+    t_tune = time.perf_counter() - t0
+    tuned = b.shape
+    b2 = api.Batch(arm, envs.support_counts, envs.query_counts, gamma)  # same kind: takes the cached shape
+    b2.prepare(sq, al)
+    t0 = time.perf_counter()
+    b2.autotune(q, (f, lab))
+    t_cached = time.perf_counter() - t0
+    cached = b2.shape
+    b2.close()
     side = torch.cuda.Stream()
     with torch.cuda.stream(side):
         b.capture(q, (f, lab))
@@ -773,7 +783,9 @@ def batched_run(api, wl, arm, gamma, dev, checks, reps=5):
     same = bool(torch.equal(f, fp) and torch.equal(lab, lp))
     kevals = float(np.sum(envs.support_counts.astype(np.float64) * envs.query_counts))
     Mm = int(np.sum(arm.frames > 0))
-    res = {"E": envs.E, "queries": N_tot, "supports": S_tot, "tile_queries": tq, "ms_graph_replay": ms_batch,
+    res = {"E": envs.E, "queries": N_tot, "supports": S_tot, "tile_queries": tq, "shape": tuned,
+           "autotune_s": t_tune, "autotune_cached_s": t_cached, "cached_shape_reused": bool(cached["from_cache"]),
+           "ms_graph_replay": ms_batch,
            "checks_per_s": N_tot / (ms_batch * 1e-3), "kernel_evals_per_s": kevals / (ms_batch * 1e-3),
            "frac_alu": kevals * Mm / (ms_batch * 1e-3) / alu_peak(Mm, api.score_rational(arm, gamma)),
            "ms_plain_per_env_launches": ms_plain, "speedup_vs_plain": ms_plain / ms_batch,

@@ -269,9 +269,21 @@ fastron_status fastron_train_batch(const float* P, const int8_t* y, int32_t E, c
  *   fastron_batch_score     scores q [N_total][n] into f / label [N_total] in
  *                           ONE persistent launch (work items claimed in
  *                           longest-first order from a device counter)
- *   fastron_batch_autotune  times the work-item shapes (16, 32, 64 queries)
- *                           on these arguments and keeps the fastest; syncs.
- *                           It discards a graph captured before it.
+ *   fastron_batch_autotune  times the launch shapes on these arguments and
+ *                           keeps the fastest: queries per work item (16, 32,
+ *                           64), waves per workgroup (4, 8), interleaved MFMAs
+ *                           of two query blocks (off/on, 32 or 64 queries) and
+ *                           the share of the resident capacity the grid takes
+ *                           (100 or 75 %); syncs. The result is remembered per
+ *                           (moving points, log2 of the mean support-set size,
+ *                           precision, device architecture and CU count), and a
+ *                           later batch of the same kind takes it without
+ *                           timing (tuning key "batch.shape_cache" = 0 times
+ *                           every call). It discards a graph captured before it.
+ *   fastron_batch_get_shape / fastron_batch_set_shape  read the shape in use
+ *                           (from_cache = 1 when the last autotune reused one)
+ *                           or pick one of the candidates directly; every shape
+ *                           gives the same results bit for bit.
  *   fastron_batch_capture   records {counter reset, scoring launch} with these
  *                           pointers into a HIP graph on `stream` (non-null)
  *   fastron_batch_replay    launches the captured graph; FASTRON_EINVAL when
@@ -288,6 +300,10 @@ fastron_status fastron_batch_autotune(fastron_batch* batch, const float* q, floa
 fastron_status fastron_batch_capture(fastron_batch* batch, const float* q, float* f, int8_t* label, void* stream);
 fastron_status fastron_batch_replay(fastron_batch* batch, void* stream);
 int32_t fastron_batch_tile_queries(const fastron_batch* batch);
+fastron_status fastron_batch_get_shape(const fastron_batch* batch, int32_t* queries_per_item, int32_t* waves_per_group,
+                                       int32_t* paired, int32_t* grid_pct, int32_t* from_cache);
+fastron_status fastron_batch_set_shape(fastron_batch* batch, int32_t queries_per_item, int32_t waves_per_group,
+                                       int32_t paired, int32_t grid_pct, void* stream);
 void fastron_batch_destroy(fastron_batch* batch);
 
 /* ---- a8: learned screening ---------------------------------------------
@@ -416,6 +432,9 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *   "score.bf16_blocks" query blocks of 16 whose BF16 operands the BF16 score
  *                       kernel keeps resident per pass: 4 (default) or 2
  *                       (fewer registers, more waves; same results)
+ *   "batch.shape_cache" 1 (default): fastron_batch_autotune reuses a shape
+ *                       tuned earlier in the process for a batch of the same
+ *                       kind; 0: it times the candidates on every call
  * Keys take effect at the next launch (a captured batch graph keeps the
  * kernel it was captured with). fastron_tune_get returns -1 for an unknown
  * key.                                                                      */

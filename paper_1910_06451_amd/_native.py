@@ -41,7 +41,7 @@ EXPORTED = [
     "fastron_mlp_fit_standardisation", "fastron_mlp_forward", "fastron_mlp_gradients", "fastron_mlp_train_epoch",
     "fastron_mlp_screen", "fastron_mlp_screen_workspace_bytes", "fastron_rbf_score", "fastron_rbf_train",
     "fastron_rbf_train_f64", "fastron_active_samples", "fastron_fk_score_noalloc", "fastron_mlp_get_adam_state",
-    "fastron_active_relabel",
+    "fastron_active_relabel", "fastron_batch_get_shape", "fastron_batch_set_shape",
 ]
 
 
@@ -87,6 +87,7 @@ def lib():
     vp, i64, i32, f32, f64 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float, ctypes.c_double
     ch, cp, md = ctypes.POINTER(Chain), ctypes.POINTER(CPoints), ctypes.POINTER(Model)
     pi64 = ctypes.POINTER(ctypes.c_int64)
+    pi32 = ctypes.POINTER(ctypes.c_int32)
     sig = {
         "fastron_control_point_frames": ([ch, i32, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)],
                                          i32),
@@ -115,6 +116,8 @@ def lib():
         "fastron_batch_capture": ([vp, vp, vp, vp, vp], i32),
         "fastron_batch_replay": ([vp, vp], i32),
         "fastron_batch_tile_queries": ([vp], i32),
+        "fastron_batch_get_shape": ([vp, pi32, pi32, pi32, pi32, pi32], i32),
+        "fastron_batch_set_shape": ([vp, i32, i32, i32, i32, vp], i32),
         "fastron_batch_destroy": ([vp], None),
         "fastron_mlp_create": ([i32, i32, i64, ctypes.POINTER(vp)], i32),
         "fastron_mlp_destroy": ([vp], None),

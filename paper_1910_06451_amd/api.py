@@ -503,6 +503,19 @@ class Batch:
     def tile_queries(self) -> int:
         return int(nat.lib().fastron_batch_tile_queries(self._h))
 
+    @property
+    def shape(self) -> dict:
+        """The launch shape in use: queries per work item, waves per workgroup, paired MFMAs, grid share (%) and
+        whether the last autotune reused a cached shape."""
+        v = [ctypes.c_int32(0) for _ in range(5)]
+        check(nat.lib().fastron_batch_get_shape(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("queries_per_item", "waves_per_group", "paired", "grid_pct", "from_cache"),
+                        (int(x.value) for x in v)))
+
+    def set_shape(self, queries_per_item: int, waves_per_group: int, paired: int, grid_pct: int):
+        check(nat.lib().fastron_batch_set_shape(self._h, int(queries_per_item), int(waves_per_group), int(paired),
+                                                int(grid_pct), _stream()))
+
     def capture(self, q: torch.Tensor, out):
         """Record {counter reset, scoring launch} for these exact buffers on the current (non-default) stream."""
         f, lab = self._io(q, out)

@@ -11,12 +11,21 @@
 // capacity of the device, so waves never wait for a dispatch slot, and the
 // loop ends for every wave once the counter passes the last item.
 //
-// The tile shape (QB) is chosen by timing the candidates on the actual batch
-// (fastron_batch_autotune). A round of queries can be captured once into a
-// HIP graph (counter reset by a kernel, then the scoring launch) and replayed.
+// The launch shape -- queries per work item (16, 32 or 64), waves per
+// workgroup (4 or 8), whether a wave interleaves the MFMAs of two query
+// blocks, and the share of the resident capacity the persistent grid takes
+// (all or three quarters) -- is chosen by timing the candidates on the actual
+// batch (fastron_batch_autotune) and remembered per (moving points, support
+// size bucket, precision, device) for later batches of the same kind. A round
+// of queries can be captured once into a HIP graph (counter reset by a kernel,
+// then the scoring launch) and replayed.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
 #include <vector>
 
 #include "score_device.h"
@@ -35,15 +44,15 @@ __global__ void k_reset_counter(unsigned long long* counter) {
   if (threadIdx.x == 0) *counter = 0ull;
 }
 
-template <int MM, typename R, int QB, bool RAT>
-__global__ void __launch_bounds__(256) k_score_batched(ChainArgs c, const float* __restrict__ q,
-                                                        const BatchItem* __restrict__ items, int64_t n_items,
-                                                        unsigned long long* __restrict__ counter,
-                                                        const float* __restrict__ tiles,
-                                                        const int64_t* __restrict__ tile_off,
-                                                        const float* __restrict__ f_const, int Mp, float gamma,
-                                                        float* __restrict__ f, int8_t* __restrict__ label) {
-  __shared__ f4 lds[kWavesPerBlock][64][MM];
+template <int MM, typename R, int QB, bool RAT, bool PAIRED, int W>
+__global__ void __launch_bounds__(64 * W) k_score_batched(ChainArgs c, const float* __restrict__ q,
+                                                           const BatchItem* __restrict__ items, int64_t n_items,
+                                                           unsigned long long* __restrict__ counter,
+                                                           const float* __restrict__ tiles,
+                                                           const int64_t* __restrict__ tile_off,
+                                                           const float* __restrict__ f_const, int Mp, float gamma,
+                                                           float* __restrict__ f, int8_t* __restrict__ label) {
+  __shared__ f4 lds[W][64][MM];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (;;) {
     unsigned long long idx = 0ull;
@@ -61,29 +70,40 @@ __global__ void __launch_bounds__(256) k_score_batched(ChainArgs c, const float*
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     const int64_t t0 = tile_off[it.env];
     const int64_t nt = tile_off[it.env + 1] - t0;
-    wave_score_fp32<MM, QB, RAT, false>(lds[wave], tiles + t0 * tile_floats(Mp), nt, Mp, f_const[it.env], it.q0, qend, f,
-                            label);
+    wave_score_fp32<MM, QB, RAT, PAIRED>(lds[wave], tiles + t0 * tile_floats(Mp), nt, Mp, f_const[it.env], it.q0,
+                                         qend, f, label);
   }
 }
 
-template <int MM, typename R, bool RAT>
-static const void* batched_kernel_q(int qb) {
-  switch (qb) {
-    case 1: return reinterpret_cast<const void*>(k_score_batched<MM, R, 1, RAT>);
-    case 2: return reinterpret_cast<const void*>(k_score_batched<MM, R, 2, RAT>);
-    default: return reinterpret_cast<const void*>(k_score_batched<MM, R, 4, RAT>);
-  }
+// Launch shape of the batched kernel.
+struct BatchShape {
+  int qb = 4;        // query blocks of 16 per work item
+  int waves = 4;     // waves per workgroup (4 or 8)
+  int paired = 0;    // interleave two query blocks' MFMAs (qb >= 2)
+  int occ_pct = 100; // share of the resident capacity the persistent grid takes (75 or 100)
+};
+
+template <int MM, typename R, bool RAT, int W>
+static const void* batched_kernel_w(int qb, int paired) {
+  if (qb == 1) return reinterpret_cast<const void*>(k_score_batched<MM, R, 1, RAT, false, W>);
+  if (qb == 2)
+    return paired ? reinterpret_cast<const void*>(k_score_batched<MM, R, 2, RAT, true, W>)
+                  : reinterpret_cast<const void*>(k_score_batched<MM, R, 2, RAT, false, W>);
+  return paired ? reinterpret_cast<const void*>(k_score_batched<MM, R, 4, RAT, true, W>)
+                : reinterpret_cast<const void*>(k_score_batched<MM, R, 4, RAT, false, W>);
 }
 
 template <int MM, typename R>
-static const void* batched_kernel_r(int qb, bool rat) {
-  return rat ? batched_kernel_q<MM, R, true>(qb) : batched_kernel_q<MM, R, false>(qb);
+static const void* batched_kernel_r(const BatchShape& sh, bool rat) {
+  if (sh.waves == 8)
+    return rat ? batched_kernel_w<MM, R, true, 8>(sh.qb, sh.paired) : batched_kernel_w<MM, R, false, 8>(sh.qb, sh.paired);
+  return rat ? batched_kernel_w<MM, R, true, 4>(sh.qb, sh.paired) : batched_kernel_w<MM, R, false, 4>(sh.qb, sh.paired);
 }
 
 template <typename R>
-static const void* batched_kernel_m(int mm, int qb, bool rat) {
+static const void* batched_kernel_m(int mm, const BatchShape& sh, bool rat) {
 #define FASTRON_BMM(K) \
-  case K: return batched_kernel_r<K, R>(qb, rat);
+  case K: return batched_kernel_r<K, R>(sh, rat);
   switch (mm) {
     FASTRON_BMM(1) FASTRON_BMM(2) FASTRON_BMM(3) FASTRON_BMM(4) FASTRON_BMM(5) FASTRON_BMM(6) FASTRON_BMM(7)
     FASTRON_BMM(8) FASTRON_BMM(9) FASTRON_BMM(10) FASTRON_BMM(11) FASTRON_BMM(12) FASTRON_BMM(13)
@@ -102,7 +122,8 @@ struct fastron_batch {
   int E = 0;
   float gamma = 0.f;
   int Mp = 4;
-  int qb = 4;
+  BatchShape shape;
+  int shape_from_cache = 0;
   int device = 0;
   int64_t S_total = 0, N_total = 0, total_tiles = 0;
   std::vector<int64_t> support_off, query_off, tile_off;
@@ -145,10 +166,29 @@ void drop_graph(fastron_batch* b) {
   b->graph = nullptr;
 }
 
-// Work items for tile shape qb, longest first.
-fastron_status build_items(fastron_batch* b, int qb, hipStream_t s) {
+// Tuned shapes, per (moving points, support-size bucket, precision, device
+// architecture and CU count).
+typedef std::tuple<int, int, int, std::string, int> ShapeKey;
+std::mutex g_shape_mu;
+std::map<ShapeKey, BatchShape>& shape_cache() {
+  static std::map<ShapeKey, BatchShape> m;
+  return m;
+}
+
+fastron_status shape_key(const fastron_batch* b, ShapeKey* key) {
+  hipDeviceProp_t prop;
+  FASTRON_HIP(hipGetDeviceProperties(&prop, b->device));
+  // support bucket: log2 of the mean support-set size per environment
+  const double mean_s = b->E > 0 ? (double)b->S_total / b->E : 0.0;
+  const int bucket = mean_s >= 1.0 ? (int)std::floor(std::log2(mean_s)) : 0;
+  *key = ShapeKey(b->c.Mm, bucket, (int)FASTRON_SCORE_FP32, std::string(prop.gcnArchName), prop.multiProcessorCount);
+  return FASTRON_OK;
+}
+
+// Work items for the shape's query blocks, longest first.
+fastron_status build_items(fastron_batch* b, const BatchShape& shape, hipStream_t s) {
   drop_graph(b);
-  const int per = 16 * qb;
+  const int per = 16 * shape.qb;
   std::vector<BatchItem> items;
   for (int e = 0; e < b->E; ++e) {
     const int64_t q0 = b->query_off[e], q1 = b->query_off[e + 1];
@@ -164,7 +204,7 @@ fastron_status build_items(fastron_batch* b, int qb, hipStream_t s) {
   if (b->n_items > 0)
     FASTRON_HIP(hipMemcpyAsync(b->d_items, items.data(), items.size() * sizeof(BatchItem), hipMemcpyHostToDevice, s));
   FASTRON_HIP(hipStreamSynchronize(s));  // the host vector dies at return
-  b->qb = qb;
+  b->shape = shape;
   return FASTRON_OK;
 }
 
@@ -174,15 +214,18 @@ fastron_status launch_batch(fastron_batch* b, const float* q, float* f, int8_t* 
   FASTRON_HIP(hipGetLastError());
   if (b->n_items == 0) return FASTRON_OK;
   const bool rat = rational_sum_ok(c, b->gamma);
-  const void* kfn = c.n >= kFp64Joints ? batched_kernel_m<double>(c.Mm, b->qb, rat)
-                                       : batched_kernel_m<float>(c.Mm, b->qb, rat);
+  const BatchShape& sh = b->shape;
+  const void* kfn = c.n >= kFp64Joints ? batched_kernel_m<double>(c.Mm, sh, rat)
+                                       : batched_kernel_m<float>(c.Mm, sh, rat);
   if (!kfn) return fail(FASTRON_EUNSUPPORTED, "batched scoring needs 1..16 moving control points");
+  const int threads = 64 * sh.waves;
   int ncu = 0, per_cu = 0;
   FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, b->device));
-  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 256, 0));
+  FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, 0));
   if (per_cu < 1) per_cu = 1;
-  int64_t blocks = (int64_t)ncu * per_cu;
-  const int64_t need = (b->n_items + kWavesPerBlock - 1) / kWavesPerBlock;
+  int64_t blocks = ((int64_t)ncu * per_cu * sh.occ_pct + 99) / 100;
+  if (blocks < 1) blocks = 1;
+  const int64_t need = (b->n_items + sh.waves - 1) / sh.waves;
   if (blocks > need) blocks = need;
   int Mp = b->Mp;
   float gamma = b->gamma;
@@ -194,8 +237,13 @@ fastron_status launch_batch(fastron_batch* b, const float* q, float* f, int8_t* 
   unsigned long long* counter = b->d_counter;
   void* args[] = {const_cast<ChainArgs*>(&c), &q, &items, &n_items, &counter, &tiles, &tile_off, &fconst, &Mp,
                   &gamma, &f, &label};
-  FASTRON_HIP(hipLaunchKernel(kfn, dim3((unsigned)blocks), dim3(256), args, 0, s));
+  FASTRON_HIP(hipLaunchKernel(kfn, dim3((unsigned)blocks), dim3((unsigned)threads), args, 0, s));
   return FASTRON_OK;
+}
+
+bool valid_shape(const BatchShape& sh) {
+  return (sh.qb == 1 || sh.qb == 2 || sh.qb == 4) && (sh.waves == 4 || sh.waves == 8) &&
+         (sh.paired == 0 || (sh.paired == 1 && sh.qb >= 2)) && (sh.occ_pct == 75 || sh.occ_pct == 100);
 }
 
 }  // namespace
@@ -255,7 +303,7 @@ fastron_status fastron_batch_create(const fastron_chain* chain, const fastron_cp
     return fail(err == hipErrorOutOfMemory ? FASTRON_ENOMEM : FASTRON_EHIP, "batch allocation failed: %s",
                 hipGetErrorString(err));
   }
-  st = build_items(b, 4, nullptr);
+  st = build_items(b, BatchShape(), nullptr);
   if (st != FASTRON_OK) {
     free_batch(b);
     return st;
@@ -290,37 +338,97 @@ fastron_status fastron_batch_autotune(fastron_batch* b, const float* q, float* f
   FASTRON_CHECK(b->N_total == 0 || q != nullptr, "q is NULL");
   FASTRON_CHECK(b->N_total == 0 || f != nullptr || label != nullptr, "f and label are both NULL");
   hipStream_t s = as_stream(stream);
+  ShapeKey key;
+  fastron_status st = shape_key(b, &key);
+  if (st != FASTRON_OK) return st;
+  if (tune_get("batch.shape_cache") == 1) {
+    BatchShape cached;
+    bool hit = false;
+    {
+      std::lock_guard<std::mutex> lk(g_shape_mu);
+      auto it = shape_cache().find(key);
+      if (it != shape_cache().end()) {
+        cached = it->second;
+        hit = true;
+      }
+    }
+    if (hit) {
+      b->shape_from_cache = 1;
+      return build_items(b, cached, s);
+    }
+  }
   hipEvent_t e0, e1;
   FASTRON_HIP(hipEventCreate(&e0));
   FASTRON_HIP(hipEventCreate(&e1));
-  int best_qb = 4;
-  float best = 1e30f;
-  fastron_status st = FASTRON_OK;
-  for (int qb : {1, 2, 4}) {
-    st = build_items(b, qb, s);
-    if (st != FASTRON_OK) break;
-    st = launch_batch(b, q, f, label, s);  // warm-up
-    if (st != FASTRON_OK) break;
-    hipError_t e = hipEventRecord(e0, s);
-    for (int r = 0; r < 3 && st == FASTRON_OK && e == hipSuccess; ++r) st = launch_batch(b, q, f, label, s);
-    if (e == hipSuccess) e = hipEventRecord(e1, s);
-    if (e == hipSuccess) e = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-    if (e != hipSuccess) st = fail(FASTRON_EHIP, "autotune timing failed: %s", hipGetErrorString(e));
-    if (st != FASTRON_OK) break;
-    if (ms < best) {
-      best = ms;
-      best_qb = qb;
-    }
-  }
+  BatchShape best;
+  float best_ms = 1e30f;
+  const int qbs[] = {1, 2, 4};
+  for (int qb : qbs)
+    for (int waves : {4, 8})
+      for (int paired = 0; paired <= (qb >= 2 ? 1 : 0); ++paired)
+        for (int occ : {100, 75}) {
+          if (st != FASTRON_OK) break;
+          BatchShape sh;
+          sh.qb = qb;
+          sh.waves = waves;
+          sh.paired = paired;
+          sh.occ_pct = occ;
+          st = build_items(b, sh, s);
+          if (st != FASTRON_OK) break;
+          st = launch_batch(b, q, f, label, s);  // warm-up
+          if (st != FASTRON_OK) break;
+          hipError_t e = hipEventRecord(e0, s);
+          for (int r = 0; r < 2 && st == FASTRON_OK && e == hipSuccess; ++r) st = launch_batch(b, q, f, label, s);
+          if (e == hipSuccess) e = hipEventRecord(e1, s);
+          if (e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.f;
+          if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (e != hipSuccess && st == FASTRON_OK) st = fail(FASTRON_EHIP, "autotune timing failed: %s", hipGetErrorString(e));
+          if (st == FASTRON_OK && ms < best_ms) {
+            best_ms = ms;
+            best = sh;
+          }
+        }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   if (st != FASTRON_OK) return st;
-  return build_items(b, best_qb, s);
+  {
+    std::lock_guard<std::mutex> lk(g_shape_mu);
+    shape_cache()[key] = best;
+  }
+  b->shape_from_cache = 0;
+  return build_items(b, best, s);
 }
 
-int32_t fastron_batch_tile_queries(const fastron_batch* b) { return b ? 16 * b->qb : -1; }
+fastron_status fastron_batch_get_shape(const fastron_batch* b, int32_t* queries_per_item, int32_t* waves_per_group,
+                                       int32_t* paired, int32_t* grid_pct, int32_t* from_cache) {
+  clear_error();
+  FASTRON_CHECK(b != nullptr, "batch is NULL");
+  if (queries_per_item) *queries_per_item = 16 * b->shape.qb;
+  if (waves_per_group) *waves_per_group = b->shape.waves;
+  if (paired) *paired = b->shape.paired;
+  if (grid_pct) *grid_pct = b->shape.occ_pct;
+  if (from_cache) *from_cache = b->shape_from_cache;
+  return FASTRON_OK;
+}
+
+fastron_status fastron_batch_set_shape(fastron_batch* b, int32_t queries_per_item, int32_t waves_per_group,
+                                       int32_t paired, int32_t grid_pct, void* stream) {
+  clear_error();
+  FASTRON_CHECK(b != nullptr, "batch is NULL");
+  BatchShape sh;
+  sh.qb = queries_per_item / 16;
+  sh.waves = waves_per_group;
+  sh.paired = paired;
+  sh.occ_pct = grid_pct;
+  FASTRON_CHECK(queries_per_item % 16 == 0 && valid_shape(sh),
+                "shape (%d queries, %d waves, paired %d, grid %d%%) is not one of the tuned candidates",
+                queries_per_item, waves_per_group, paired, grid_pct);
+  b->shape_from_cache = 0;
+  return build_items(b, sh, as_stream(stream));
+}
+
+int32_t fastron_batch_tile_queries(const fastron_batch* b) { return b ? 16 * b->shape.qb : -1; }
 
 fastron_status fastron_batch_capture(fastron_batch* b, const float* q, float* f, int8_t* label, void* stream) {
   clear_error();

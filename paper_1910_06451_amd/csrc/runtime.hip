@@ -25,6 +25,7 @@ std::unordered_map<std::string, Knob>& table() {
       {"train.wave_groups", {256, 1, 512, false}},  // grid cap of the single-wave kernel
       {"score.rational", {1, 0, 1, false}},        // 1 = running-fraction sum where the reach bound allows it
       {"score.bf16_blocks", {4, 2, 4, true}},      // query blocks resident per pass of the BF16 score kernel
+      {"batch.shape_cache", {1, 0, 1, false}},     // 1 = batch autotune reuses a shape tuned for the same kind
   };
   return t;
 }

@@ -132,6 +132,11 @@ def test_validation_before_device_work(lib):
                                         None) == nat.FASTRON_EINVAL
     assert lib.fastron_fk_score_noalloc(ch, cp, None, None, 0, 10.0, None, 0, None, None, 0,
                                         None) == nat.FASTRON_OK  # N = 0
+    # the batched form's launch shape: only the tuned candidates are accepted (checked before any device work)
+    assert lib.fastron_batch_set_shape(None, 32, 4, 0, 100, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_batch_get_shape(None, None, None, None, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_active_relabel(None, 0, None, None) == nat.FASTRON_OK  # S = 0
+    assert lib.fastron_active_relabel(None, 5, None, None) == nat.FASTRON_EINVAL
     # active-learning assembly
     assert lib.fastron_active_samples(None, None, 0, 7, None, 0, None, 0, None, None, None) == nat.FASTRON_OK
     assert lib.fastron_active_samples(fake, fake, 10, 7, None, 2, None, 0, fake, None, None) == nat.FASTRON_EINVAL

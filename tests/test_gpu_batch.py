@@ -135,3 +135,48 @@ def test_batch_full_scale(oracle_mod, dev):
                           oracle_mod.control_points(dh, arm.frames, q[idx].astype(np.float64)))
         check_scores(fn[idx], ln[idx], r, tol, min_agree=0.99)
     b.close()
+
+
+def test_every_launch_shape_gives_the_same_result(dev):
+    """Every launch shape the autotuner chooses from (queries per item x waves per workgroup x paired MFMAs x
+    grid share) scores each environment exactly as the single-model path; autotune keeps one of them, and a
+    second batch of the same kind (same moving points, support-size bucket and device) reuses it without
+    timing."""
+    arm = wl.arm_7dof()
+    gamma = 10.0
+    S_counts = np.array([300, 17, 1200, 0, 64, 2000, 5, 750])
+    Q_counts = np.array([700, 1, 64, 50, 0, 1000, 129, 333])
+    sq, al, q = _envs("batch_shapes", S_counts, Q_counts, 7)
+    b = api.Batch(arm, S_counts, Q_counts, gamma)
+    b.prepare(torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev))
+    q_d = torch.from_numpy(q).to(dev)
+    ref, so, qo = _per_env_reference(arm, S_counts, Q_counts, sq, al, q, gamma, dev, range(len(S_counts)))
+    shapes = [(16 * qb, w, p, occ) for qb in (1, 2, 4) for w in (4, 8) for p in ((0, 1) if qb >= 2 else (0,))
+              for occ in (100, 75)]
+    assert len(shapes) == 20
+    for sh in shapes:
+        announce(f"batch shape {sh}")
+        b.set_shape(*sh)
+        f, lab = b.score(q_d)
+        for e, (fr, lr) in ref.items():
+            assert torch.equal(f[qo[e]:qo[e + 1]], fr), (sh, e)
+            assert torch.equal(lab[qo[e]:qo[e + 1]], lr), (sh, e)
+    announce("batch autotune (timed)")
+    b.autotune(q_d)
+    first = b.shape
+    assert first["from_cache"] == 0
+    assert (first["queries_per_item"], first["waves_per_group"], first["paired"], first["grid_pct"]) in shapes
+    f, lab = b.score(q_d)
+    for e, (fr, lr) in ref.items():
+        assert torch.equal(f[qo[e]:qo[e + 1]], fr), e
+    announce("batch autotune (same kind: cached)")
+    b2 = api.Batch(arm, S_counts, Q_counts, gamma)
+    b2.prepare(torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev))
+    b2.autotune(q_d)
+    second = b2.shape
+    assert second["from_cache"] == 1
+    assert {k: v for k, v in second.items() if k != "from_cache"} == {k: v for k, v in first.items()
+                                                                       if k != "from_cache"}
+    print(dict(tuned=first))
+    b.close()
+    b2.close()
