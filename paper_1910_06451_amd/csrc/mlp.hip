@@ -601,6 +601,475 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Training step for the 3M (<= 32) -> 256 -> 256 -> 1 network: three kernels
+// per batch instead of the staged GEMM sequence.
+//   k_train_rows   one wave per 16 batch rows: standardised BF16 inputs,
+//                  layer 1 and layer 2 in transposed form (hidden units as
+//                  MFMA rows, batch rows as columns, as in the screening
+//                  kernel), head, loss, dZ2 = [Z2 > 0] dz w3, then
+//                  dH1^T = W2 dZ2^T and dZ1 = [Z1 > 0] dH1 without leaving
+//                  registers; writes X, H1, dZ2 and dZ1 unit-major (each
+//                  unit's batch rows contiguous) for the weight gradients,
+//                  and per-workgroup sums over its rows for the bias and head
+//                  gradients and the loss.
+//   k_train_wgrad  gW2 = H1^T dZ2 and gW1 = X^T dZ1, contracting over the
+//                  batch rows in split-K slices (one partial per slice).
+//   k_train_adam   sums the partials in a fixed order, applies Adam to the
+//                  FP32 masters and refreshes every BF16 operand copy.
+// Layer 2 permutes its output units like layer 1 (fragment v, row 4 g + i is
+// unit inf_unit1(v, 4 g + i)), so that lane group g holds units
+// 32 c + 8 g .. + 7 of chunk c: exactly the operand dH1^T = W2 dZ2^T needs,
+// and the order in which dH1^T comes out is that of H1 (whose nonzero entries
+// are the ReLU mask). Rounding points are those of the staged path: X, W1,
+// H1, W2, dZ2 and dZ1 in BF16, everything else FP32.
+// ---------------------------------------------------------------------------
+constexpr int kTrH = 256;        // hidden width of the training kernels
+constexpr int kTrIn = 32;        // input features, zero-padded
+constexpr int kTrWaves = 4;      // waves (16-row blocks) per workgroup of k_train_rows
+constexpr int kTrRows = 16 * kTrWaves;
+constexpr int kTrVec = 3 * kTrH + 2;  // per-workgroup sums: gb1, gb2, gw3, gb3, loss
+constexpr int kTrSplitsMax = 32;      // split-K slices of the weight-gradient kernel
+
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+  const b2m h = __builtin_convertvector((f2m){a, b}, b2m);
+  return __builtin_bit_cast(uint32_t, h);
+}
+__device__ __forceinline__ uint16_t bf16_at(const u4m& v, int j) {
+  return (uint16_t)((v[j >> 1] >> (16 * (j & 1))) & 0xffffu);
+}
+// Sum over the 16 batch rows of a wave (the 16 lanes of a row of the wave,
+// lane / 16 equal, hold the same hidden units of different batch rows); every
+// lane of the 16 gets it. Four DPP adds in a fixed order: quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror.
+__device__ __forceinline__ float dpp_add(float v, int ctrl_sel) {
+  int o;
+  switch (ctrl_sel) {
+    case 0: o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false); break;
+    case 1: o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false); break;
+    case 2: o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false); break;
+    default: o = __builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false); break;
+  }
+  return v + __int_as_float(o);
+}
+__device__ __forceinline__ float rows_sum(float v) {
+  v = dpp_add(v, 0);
+  v = dpp_add(v, 1);
+  v = dpp_add(v, 2);
+  return dpp_add(v, 3);
+}
+
+// Writes a wave's 16 batch rows x 256 units of BF16 values (lane (g, col)
+// holding units 32 c + 8 g .. + 7 of row col in u4m v[c]) unit-major to
+// T[unit][row0 + row] through the wave's LDS area `st` ([unit][24] halfwords:
+// 16 rows and a pad that spreads the four lane groups over the banks), so
+// that each lane stores 16 bytes (8 rows of one unit) at a time.
+constexpr int kTrStageStride = 24;
+static_assert(kTrWaves * kTrH * kTrStageStride <= kTrH * kTrH, "the store staging areas fit the operand area");
+__device__ __forceinline__ void store_unit_major(const u4m* v, uint16_t* st, uint16_t* __restrict__ T, int64_t ldT,
+                                                 int64_t row0, int lane) {
+  const int g = lane >> 4, col = lane & 15;
+#pragma unroll
+  for (int c = 0; c < 8; ++c)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) st[(32 * c + 8 * g + j) * kTrStageStride + col] = bf16_at(v[c], j);
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const int chunk = q * 64 + lane;  // 512 chunks: unit = chunk / 2, rows 8 (chunk % 2) .. + 7
+    const int unit = chunk >> 1, h = chunk & 1;
+    const u8m val = *reinterpret_cast<const u8m*>(&st[unit * kTrStageStride + 8 * h]);
+    *reinterpret_cast<u8m*>(&T[(int64_t)unit * ldT + row0 + 8 * h]) = val;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+struct TrainRowsArgs {
+  const float* P;
+  const int32_t* order;
+  const int8_t* y;
+  int64_t row0;      // first entry of `order` (or row of P) of this batch
+  int rows;          // rows in the batch
+  int64_t n_rows;    // rows of P
+  int d_in;
+  const float* mu;
+  const float* sd;
+  const uint16_t* tw1;   // layer-1 operands [16 v][64 lane][8]
+  const float* b1;
+  const uint16_t* tw2f;  // layer-2 operands [16 v][8 c][64 lane][8] (W2^T, output units permuted)
+  const float* b2;
+  const float* w3;
+  const float* b3;
+  const uint16_t* tw2d;  // dH1 operands [16 v][8 c][64 lane][8] (W2, output units permuted)
+  int64_t ldT;           // row stride of the unit-major arrays
+  uint16_t* XT;          // [kTrIn][ldT]
+  uint16_t* H1T;         // [kTrH][ldT]
+  uint16_t* dZ2T;        // [kTrH][ldT]
+  uint16_t* dZ1T;        // [kTrH][ldT]
+  float* wg_sums;        // [workgroups][kTrVec]
+  float* z_out;          // optional logits [rows]
+  int* bad;
+};
+
+// Copies one 128 KB operand set (kTrH x kTrH bf16) into LDS with a 256-thread
+// workgroup, each thread's loads issued 16 at a time.
+__device__ __forceinline__ void stage_operands(const uint16_t* __restrict__ g, uint16_t* lds, int tid) {
+  const u8m* src = reinterpret_cast<const u8m*>(g);
+  u8m* dst = reinterpret_cast<u8m*>(lds);
+  constexpr int kPer = kTrH * kTrH / 8 / 256;  // 32 vectors of 16 bytes per thread
+#pragma unroll
+  for (int b = 0; b < kPer; b += 16) {
+    u8m buf[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) buf[q] = src[(b + q) * 256 + tid];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) dst[(b + q) * 256 + tid] = buf[q];
+  }
+}
+
+__global__ void __launch_bounds__(256) k_train_rows(TrainRowsArgs a) {
+  __shared__ __align__(16) uint16_t w2s[kTrH * kTrH];
+  __shared__ __align__(16) float b1s[kTrH], b2s[kTrH], w3s[kTrH];
+  __shared__ float sums[kTrWaves][kTrVec];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, col = lane & 15;
+  stage_operands(a.tw2f, w2s, tid);
+  b1s[tid] = a.b1[tid];
+  b2s[tid] = a.b2[tid];
+  w3s[tid] = a.w3[tid];
+  __syncthreads();
+  float* my = sums[wave];
+  const int64_t r = (int64_t)blockIdx.x * kTrRows + 16 * wave + col;  // this lane's batch row
+  const bool in_batch = r < a.rows;
+  int64_t src = -1;
+  if (in_batch) {
+    const int64_t s = a.order ? (int64_t)a.order[a.row0 + r] : a.row0 + r;
+    if (s >= 0 && s < a.n_rows) src = s;
+    else if (g == 0) *a.bad = 1;
+  }
+  const bool live = src >= 0;
+  // 1. inputs: features 8 g .. 8 g + 7 of row r (the B operand of layer 1)
+  u8m xu;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int f = 8 * g + j;
+    const float v = (live && f < a.d_in) ? (a.P[src * a.d_in + f] - a.mu[f]) / a.sd[f] : 0.f;
+    xu[j] = to_bf16(v);
+    a.XT[(int64_t)f * a.ldT + r] = xu[j];
+  }
+  const bf8m xb = __builtin_bit_cast(bf8m, xu);
+  // 2. layer 1: H1^T = W1^T X^T + b1, ReLU, BF16
+  u4m h1[8];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(a.tw1)[v * 64 + lane]);
+    const f4m bias = *reinterpret_cast<const f4m*>(&b1s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
+    const f4m d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, xb, bias, 0, 0, 0);
+    h1[v >> 1][2 * (v & 1)] = relu_bf16x2(d[0], d[1]);
+    h1[v >> 1][2 * (v & 1) + 1] = relu_bf16x2(d[2], d[3]);
+  }
+  // 3. layer 2: Z2^T = W2^T H1^T + b2 (output units permuted like layer 1)
+  f4m z2[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) z2[v] = *reinterpret_cast<const f4m*>(&b2s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const bf8m hb = __builtin_bit_cast(bf8m, h1[c]);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(w2s)[(v * 8 + c) * 64 + lane]);
+      z2[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hb, z2[v], 0, 0, 0);
+    }
+  }
+  // 4. head and loss (the four lane groups hold disjoint units of the same row)
+  float lp = 0.f;
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const f4m hw = *reinterpret_cast<const f4m*>(&w3s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) lp = fmaf(fmaxf(z2[v][i], 0.f), hw[i], lp);
+  }
+  lp += __shfl_xor(lp, 16);
+  lp += __shfl_xor(lp, 32);
+  const float z = lp + a.b3[0];
+  float dz = 0.f, loss = 0.f;
+  if (live) {
+    const float t = a.y[src] > 0 ? 1.f : 0.f;
+    loss = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z;
+    dz = (1.f / (1.f + expf(-z)) - t) / (float)a.rows;
+    if (a.z_out && g == 0) a.z_out[r] = z;
+  }
+  // 5. dZ2 = [Z2 > 0] dz w3 (FP32), row sums for gb2 and gw3, BF16 copy
+  u4m d2[8];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int u0 = 32 * (v >> 1) + 8 * g + 4 * (v & 1);
+    const f4m hw = *reinterpret_cast<const f4m*>(&w3s[u0]);
+    f4m dv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dv[i] = z2[v][i] > 0.f ? dz * hw[i] : 0.f;
+      const float sb = rows_sum(dv[i]);
+      const float sw = rows_sum(fmaxf(z2[v][i], 0.f) * dz);
+      if (col == 0) {
+        my[kTrH + u0 + i] = sb;
+        my[2 * kTrH + u0 + i] = sw;
+      }
+    }
+    d2[v >> 1][2 * (v & 1)] = pack_bf16x2(dv[0], dv[1]);
+    d2[v >> 1][2 * (v & 1) + 1] = pack_bf16x2(dv[2], dv[3]);
+  }
+  // 6. dH1^T = W2 dZ2^T (output units permuted like layer 1), dZ1 = [H1 > 0] dH1; the workgroup's LDS now
+  //    takes the dH1 operands in place of the layer-2 ones (every wave has finished layer 2)
+  __syncthreads();
+  stage_operands(a.tw2d, w2s, tid);
+  __syncthreads();
+  f4m dh[16];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) dh[v] = (f4m){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    const bf8m db = __builtin_bit_cast(bf8m, d2[c]);
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(w2s)[(v * 8 + c) * 64 + lane]);
+      dh[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, db, dh[v], 0, 0, 0);
+    }
+  }
+  u4m d1[8];
+#pragma unroll
+  for (int v = 0; v < 16; ++v) {
+    const int u0 = 32 * (v >> 1) + 8 * g + 4 * (v & 1);
+    f4m dv;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      dv[i] = bf16_at(h1[v >> 1], 4 * (v & 1) + i) != 0 ? dh[v][i] : 0.f;
+      const float sb = rows_sum(dv[i]);
+      if (col == 0) my[u0 + i] = sb;
+    }
+    d1[v >> 1][2 * (v & 1)] = pack_bf16x2(dv[0], dv[1]);
+    d1[v >> 1][2 * (v & 1) + 1] = pack_bf16x2(dv[2], dv[3]);
+  }
+  // 7. row sums of dz (gb3) and of the loss
+  {
+    const float sdz = rows_sum(g == 0 ? dz : 0.f);
+    const float sl = rows_sum(g == 0 ? loss : 0.f);
+    if (lane == 0) {
+      my[3 * kTrH] = sdz;
+      my[3 * kTrH + 1] = sl;
+    }
+  }
+  __syncthreads();  // every wave is done with the dH1 operands: the LDS area now stages the unit-major stores
+  {
+    const int64_t row0 = (int64_t)blockIdx.x * kTrRows + 16 * wave;
+    uint16_t* st = w2s + wave * (kTrH * kTrStageStride);
+    store_unit_major(h1, st, a.H1T, a.ldT, row0, lane);
+    store_unit_major(d2, st, a.dZ2T, a.ldT, row0, lane);
+    store_unit_major(d1, st, a.dZ1T, a.ldT, row0, lane);
+  }
+  // workgroup sums in wave order
+  for (int k = tid; k < kTrVec; k += 256) {
+    float s = 0.f;
+#pragma unroll
+    for (int w = 0; w < kTrWaves; ++w) s += sums[w][k];
+    a.wg_sums[(int64_t)blockIdx.x * kTrVec + k] = s;
+  }
+}
+
+// gW2 = H1^T dZ2 (tiles 0..31, 32 x 64 outputs) and gW1 = X^T dZ1 (tiles
+// 32..35, 32 x 64 outputs), over batch rows [kchunk * split, + kchunk) of the
+// unit-major arrays, in groups of 8 row steps of 32 whose operands are all
+// loaded before the group's products. One wave per (tile, split); partial
+// written to part[split][W1 (kTrIn x kTrH) | W2 (kTrH x kTrH)]. Blocks past
+// the tiles (split 0 only) sum the per-workgroup vectors of k_train_rows in
+// workgroup order into red[kTrVec] (the loss sum in FP64 into red_loss).
+constexpr int kTrWgradTiles = 36;
+constexpr int kTrRedBlocks = (kTrVec + 63) / 64;
+__global__ void __launch_bounds__(64) k_train_wgrad(const uint16_t* __restrict__ XT, const uint16_t* __restrict__ H1T,
+                                                     const uint16_t* __restrict__ dZ2T,
+                                                     const uint16_t* __restrict__ dZ1T, int64_t ldT, int64_t krows,
+                                                     int64_t kchunk, float* __restrict__ part,
+                                                     const float* __restrict__ wg_sums, int n_wg,
+                                                     float* __restrict__ red, double* __restrict__ red_loss) {
+  const int lane = threadIdx.x, g = lane >> 4, col = lane & 15;
+  const int tile = blockIdx.x, split = blockIdx.y;
+  if (tile >= kTrWgradTiles) {
+    if (split != 0) return;
+    const int k = (tile - kTrWgradTiles) * 64 + lane;
+    if (k >= kTrVec) return;
+    double sd = 0.0;
+    float sf = 0.f;
+    for (int w0 = 0; w0 < n_wg; w0 += 16) {
+      float buf[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) buf[q] = w0 + q < n_wg ? wg_sums[(int64_t)(w0 + q) * kTrVec + k] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        sf += buf[q];
+        sd += (double)buf[q];
+      }
+    }
+    red[k] = sf;
+    if (k == 3 * kTrH + 1) *red_loss = sd;
+    return;
+  }
+  const bool w2 = tile < 32;
+  const uint16_t* A = w2 ? H1T : XT;
+  const uint16_t* Bm = w2 ? dZ2T : dZ1T;
+  const int m0 = w2 ? 32 * (tile >> 2) : 0;
+  const int n0 = w2 ? 64 * (tile & 3) : 64 * (tile - 32);
+  f4m acc[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) acc[i][j] = (f4m){0.f, 0.f, 0.f, 0.f};
+  const int64_t k0 = (int64_t)split * kchunk;
+  const int64_t k1 = k0 + kchunk < krows ? k0 + kchunk : krows;
+  const u8m* ap[2];
+  const u8m* bp[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) ap[i] = reinterpret_cast<const u8m*>(&A[(int64_t)(m0 + 16 * i + col) * ldT + 8 * g]);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) bp[j] = reinterpret_cast<const u8m*>(&Bm[(int64_t)(n0 + 16 * j + col) * ldT + 8 * g]);
+  constexpr int kSteps = 8;
+  for (int64_t kg = k0; kg < k1; kg += 32 * kSteps) {
+    u8m an[kSteps][2], bn[kSteps][4];
+#pragma unroll
+    for (int t = 0; t < kSteps; ++t) {
+      const int64_t k = kg + 32 * t;
+      if (k < k1) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) an[t][i] = ap[i][k / 8];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bn[t][j] = bp[j][k / 8];
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kSteps; ++t)
+      if (kg + 32 * t < k1)
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8m, an[t][i]),
+                                                                __builtin_bit_cast(bf8m, bn[t][j]), acc[i][j], 0, 0, 0);
+  }
+  float* out = part + (int64_t)split * (kTrIn + kTrH) * kTrH + (w2 ? (int64_t)kTrIn * kTrH : 0);
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int rr = 0; rr < 4; ++rr)
+        out[(int64_t)(m0 + 16 * i + 4 * g + rr) * kTrH + n0 + 16 * j + col] = acc[i][j][rr];
+}
+
+struct TrainAdamArgs {
+  const float* part;     // [splits][(kTrIn + kTrH) * kTrH]
+  int splits;
+  const float* red;      // [kTrVec] workgroup sums reduced by k_train_wgrad
+  const double* red_loss;
+  int d_in;
+  int64_t n_params;
+  float* params;
+  float* grads;
+  float* m;
+  float* v;
+  int apply;             // 0: gradients only
+  float lr, b1, b2, eps, c1, c2;
+  uint16_t* tw1;
+  uint16_t* tw2f;
+  uint16_t* tw2d;
+  uint16_t* w1b;         // staged-path copies [kin_pad][H], [H][H]
+  uint16_t* w2b;
+  double* loss_acc;
+};
+
+// Position of hidden unit u in the permuted MFMA row order (inverse of inf_unit1).
+__device__ __forceinline__ void unit_slot(int u, int* v, int* row) {
+  *v = 2 * (u >> 5) + ((u & 7) >> 2);
+  *row = 4 * ((u & 31) >> 3) + (u & 3);
+}
+
+__global__ void __launch_bounds__(256) k_train_adam(TrainAdamArgs a) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (e == 0 && a.loss_acc) *a.loss_acc += *a.red_loss;
+  if (e >= a.n_params) return;
+  const int64_t nW1 = (int64_t)a.d_in * kTrH;
+  const int64_t oW2 = nW1 + kTrH, oB2 = oW2 + (int64_t)kTrH * kTrH, oW3 = oB2 + kTrH, oB3 = oW3 + kTrH;
+  const int64_t pstride = (int64_t)(kTrIn + kTrH) * kTrH;
+  float gsum = 0.f;
+  int kind;  // 0 W1, 1 b1, 2 W2, 3 b2, 4 w3, 5 b3
+  int64_t idx;
+  if (e < nW1) { kind = 0; idx = e; }
+  else if (e < oW2) { kind = 1; idx = e - nW1; }
+  else if (e < oB2) { kind = 2; idx = e - oW2; }
+  else if (e < oW3) { kind = 3; idx = e - oB2; }
+  else if (e < oB3) { kind = 4; idx = e - oW3; }
+  else { kind = 5; idx = 0; }
+  if (kind == 0 || kind == 2) {
+    // split partials in a fixed order, their loads issued 16 at a time
+    const float* base = a.part + (kind == 0 ? idx : (int64_t)kTrIn * kTrH + idx);
+    for (int s0 = 0; s0 < a.splits; s0 += 16) {
+      float buf[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) buf[q] = s0 + q < a.splits ? base[(int64_t)(s0 + q) * pstride] : 0.f;
+#pragma unroll
+      for (int q = 0; q < 16; ++q)
+        if (s0 + q < a.splits) gsum += buf[q];
+    }
+  } else {
+    gsum = a.red[kind == 1 ? idx : kind == 3 ? kTrH + idx : kind == 4 ? 2 * kTrH + idx : 3 * kTrH];
+  }
+  a.grads[e] = gsum;
+  if (!a.apply) return;
+  const float mi = a.b1 * a.m[e] + (1.f - a.b1) * gsum;
+  const float vi = a.b2 * a.v[e] + (1.f - a.b2) * gsum * gsum;
+  a.m[e] = mi;
+  a.v[e] = vi;
+  const float p = a.params[e] - a.lr * (mi * a.c1) / (sqrtf(vi * a.c2) + a.eps);
+  a.params[e] = p;
+  const uint16_t pb = to_bf16(p);
+  if (kind == 0) {
+    const int f = (int)(idx / kTrH), u = (int)(idx % kTrH);
+    int v, row;
+    unit_slot(u, &v, &row);
+    a.tw1[((int64_t)v * 64 + 16 * (f >> 3) + row) * 8 + (f & 7)] = pb;
+    a.w1b[idx] = pb;
+  } else if (kind == 2) {
+    const int u1 = (int)(idx / kTrH), u2 = (int)(idx % kTrH);
+    int v, row;
+    unit_slot(u2, &v, &row);  // forward operand: rows = u2 (permuted), k = u1
+    a.tw2f[(((int64_t)v * 8 + (u1 >> 5)) * 64 + 16 * ((u1 & 31) >> 3) + row) * 8 + (u1 & 7)] = pb;
+    unit_slot(u1, &v, &row);  // backward operand: rows = u1 (permuted), k = u2
+    a.tw2d[(((int64_t)v * 8 + (u2 >> 5)) * 64 + 16 * ((u2 & 31) >> 3) + row) * 8 + (u2 & 7)] = pb;
+    a.w2b[idx] = pb;
+  }
+}
+
+// Packs all training operands from the FP32 masters (after set_params).
+__global__ void __launch_bounds__(256) k_train_pack(const float* __restrict__ w1, const float* __restrict__ w2, int d_in,
+                                                     uint16_t* __restrict__ tw1, uint16_t* __restrict__ tw2f,
+                                                     uint16_t* __restrict__ tw2d) {
+  const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  constexpr int64_t n1 = 16 * 64 * 8, n2 = (int64_t)kTrH * kTrH;
+  if (e < n1) {
+    const int j = (int)(e & 7), lane = (int)((e >> 3) & 63), v = (int)(e >> 9);
+    const int k = 8 * (lane >> 4) + j;
+    tw1[e] = k < d_in ? to_bf16(w1[(int64_t)k * kTrH + inf_unit1(v, lane & 15)]) : (uint16_t)0;
+  } else if (e < n1 + n2) {
+    const int64_t f = e - n1;
+    const int j = (int)(f & 7), lane = (int)((f >> 3) & 63), c = (int)((f >> 9) & 7), v = (int)(f >> 12);
+    const int k = 32 * c + 8 * (lane >> 4) + j;
+    const int mrow = inf_unit1(v, lane & 15);
+    tw2f[f] = to_bf16(w2[(int64_t)k * kTrH + mrow]);
+    tw2d[f] = to_bf16(w2[(int64_t)mrow * kTrH + k]);
+  }
+}
+
 static inline unsigned nblk(int64_t n) { return (unsigned)((n + 255) / 256); }
 
 }  // namespace fastron
@@ -625,6 +1094,21 @@ struct fastron_mlp {
   uint16_t* w1p = nullptr;  // fused-inference operand order (H == 256, d_in <= 24 only)
   uint16_t* w2p = nullptr;
   float* isd = nullptr;     // 1 / sd for the fused pass
+  // three-kernel training step (H == 256, d_in <= 32)
+  bool fast = false;
+  int64_t ldT = 0;          // row stride of the unit-major activation arrays
+  uint16_t* tw1 = nullptr;
+  uint16_t* tw2f = nullptr;
+  uint16_t* tw2d = nullptr;
+  uint16_t* XT = nullptr;
+  uint16_t* H1T = nullptr;
+  uint16_t* dZ2T = nullptr;
+  uint16_t* dZ1T = nullptr;
+  float* wg_sums = nullptr;
+  float* wpart = nullptr;
+  float* red = nullptr;       // [kTrVec] reduced workgroup sums
+  double* red_loss = nullptr;
+  double* loss_acc = nullptr;
   float* splitbuf = nullptr;  // split-K partial products of the weight-gradient GEMMs
   int64_t step = 0;
   // activations for a batch of cap_rows
@@ -660,7 +1144,8 @@ void free_mlp(fastron_mlp* n) {
   if (!n) return;
   void* ps[] = {n->params, n->grads, n->adam_m, n->adam_v, n->mu, n->sd, n->w1b, n->w2b, n->Xb, n->Z1, n->H1b,
                 n->Z2, n->partial, n->z, n->dz, n->dZ2, n->dZ2b, n->dH1, n->dZ1, n->dZ1b, n->colpart, n->loss_part,
-                n->hbuf, n->bad, n->w1p, n->w2p, n->isd, n->splitbuf};
+                n->hbuf, n->bad, n->w1p, n->w2p, n->isd, n->splitbuf, n->tw1, n->tw2f, n->tw2d, n->XT,
+                n->H1T, n->dZ2T, n->dZ1T, n->wg_sums, n->wpart, n->loss_acc, n->red, n->red_loss};
   for (void* p : ps) (void)hipFree(p);
   delete n;
 }
@@ -774,7 +1259,90 @@ fastron_status refresh_bf16(fastron_mlp* n, hipStream_t s) {
   hipLaunchKernelGGL(k_weights_bf16, dim3(nblk(tot)), dim3(256), 0, s, n->w1(), n->w2(), n->d_in, n->kin_pad, n->H,
                      n->w1b, n->w2b);
   FASTRON_HIP(hipGetLastError());
+  if (n->fast) {
+    hipLaunchKernelGGL(k_train_pack, dim3(nblk(16 * 64 * 8 + (int64_t)kTrH * kTrH)), dim3(256), 0, s, n->w1(), n->w2(),
+                       n->d_in, n->tw1, n->tw2f, n->tw2d);
+    FASTRON_HIP(hipGetLastError());
+  }
   return FASTRON_OK;
+}
+
+// One batch of the three-kernel step on rows row0 .. row0 + rows - 1 of
+// `order` (or of P): gradients into n->grads and, with apply, an Adam step
+// that also refreshes every BF16 operand copy. The batch's loss sum is added
+// to n->loss_acc.
+fastron_status fast_step(fastron_mlp* n, const float* P, const int8_t* y, const int32_t* order, int64_t row0,
+                         int64_t rows, int64_t n_rows, bool apply, float lr, float* z_out, hipStream_t s) {
+  const int nwg = (int)((rows + kTrRows - 1) / kTrRows);
+  TrainRowsArgs a;
+  a.P = P;
+  a.order = order;
+  a.y = y;
+  a.row0 = row0;
+  a.rows = (int)rows;
+  a.n_rows = n_rows;
+  a.d_in = n->d_in;
+  a.mu = n->mu;
+  a.sd = n->sd;
+  a.tw1 = n->tw1;
+  a.b1 = n->b1();
+  a.tw2f = n->tw2f;
+  a.b2 = n->b2();
+  a.w3 = n->w3();
+  a.b3 = n->b3();
+  a.tw2d = n->tw2d;
+  a.ldT = n->ldT;
+  a.XT = n->XT;
+  a.H1T = n->H1T;
+  a.dZ2T = n->dZ2T;
+  a.dZ1T = n->dZ1T;
+  a.wg_sums = n->wg_sums;
+  a.z_out = z_out;
+  a.bad = n->bad;
+  hipLaunchKernelGGL(k_train_rows, dim3((unsigned)nwg), dim3(256), 0, s, a);
+  FASTRON_HIP(hipGetLastError());
+  const int64_t krows = (int64_t)nwg * kTrRows;
+  int64_t splits = krows / 256;  // about 8 row steps of 32 per wave
+  if (splits < 1) splits = 1;
+  if (splits > kTrSplitsMax) splits = kTrSplitsMax;
+  int64_t kchunk = (krows / 32 + splits - 1) / splits * 32;
+  splits = (krows + kchunk - 1) / kchunk;
+  hipLaunchKernelGGL(k_train_wgrad, dim3(kTrWgradTiles + kTrRedBlocks, (unsigned)splits), dim3(64), 0, s, n->XT,
+                     n->H1T, n->dZ2T, n->dZ1T, n->ldT, krows, kchunk, n->wpart, n->wg_sums, nwg, n->red,
+                     n->red_loss);
+  FASTRON_HIP(hipGetLastError());
+  TrainAdamArgs m;
+  m.part = n->wpart;
+  m.splits = (int)splits;
+  m.red = n->red;
+  m.red_loss = n->red_loss;
+  m.d_in = n->d_in;
+  m.n_params = n->n_params;
+  m.params = n->params;
+  m.grads = n->grads;
+  m.m = n->adam_m;
+  m.v = n->adam_v;
+  m.apply = apply ? 1 : 0;
+  m.lr = lr;
+  m.b1 = 0.9f;
+  m.b2 = 0.999f;
+  m.eps = 1e-8f;
+  if (apply) n->step += 1;
+  m.c1 = apply ? (float)(1.0 / (1.0 - std::pow((double)m.b1, (double)n->step))) : 0.f;
+  m.c2 = apply ? (float)(1.0 / (1.0 - std::pow((double)m.b2, (double)n->step))) : 0.f;
+  m.tw1 = n->tw1;
+  m.tw2f = n->tw2f;
+  m.tw2d = n->tw2d;
+  m.w1b = n->w1b;
+  m.w2b = n->w2b;
+  m.loss_acc = n->loss_acc;
+  hipLaunchKernelGGL(k_train_adam, dim3(nblk(n->n_params)), dim3(256), 0, s, m);
+  FASTRON_HIP(hipGetLastError());
+  return FASTRON_OK;
+}
+
+__global__ void k_zero_f64(double* p) {
+  if (threadIdx.x == 0) *p = 0.0;
 }
 
 fastron_status stage_points(fastron_mlp* n, const float* P, const int32_t* order, int64_t row0, int64_t rows,
@@ -883,6 +1451,22 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
     alloc(&n->w2p, (int64_t)kInfH * kInfH, 2);
     alloc(&n->isd, d_in, 4);
   }
+  if (hidden == kTrH && d_in <= kTrIn) {
+    n->fast = true;
+    n->ldT = (R + kTrRows - 1) / kTrRows * kTrRows;
+    alloc(&n->tw1, 16 * 64 * 8, 2);
+    alloc(&n->tw2f, (int64_t)kTrH * kTrH, 2);
+    alloc(&n->tw2d, (int64_t)kTrH * kTrH, 2);
+    alloc(&n->XT, (int64_t)kTrIn * n->ldT, 2);
+    alloc(&n->H1T, (int64_t)kTrH * n->ldT, 2);
+    alloc(&n->dZ2T, (int64_t)kTrH * n->ldT, 2);
+    alloc(&n->dZ1T, (int64_t)kTrH * n->ldT, 2);
+    alloc(&n->wg_sums, (n->ldT / kTrRows) * kTrVec, 4);
+    alloc(&n->wpart, (int64_t)kTrSplitsMax * (kTrIn + kTrH) * kTrH, 4);
+    alloc(&n->loss_acc, 1, 8);
+    alloc(&n->red, kTrVec, 4);
+    alloc(&n->red_loss, 1, 8);
+  }
   if (e == hipSuccess) e = hipMemset(n->adam_m, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->adam_v, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->bad, 0, sizeof(int));
@@ -965,6 +1549,18 @@ fastron_status fastron_mlp_gradients(fastron_mlp* n, const float* P, const int8_
   FASTRON_CHECK(n && P && y, "network, P and y must be non-NULL");
   FASTRON_CHECK(N >= 1 && N <= n->cap_rows, "N = %lld outside [1, max_rows]", (long long)N);
   hipStream_t s = as_stream(stream);
+  if (n->fast) {
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, n->loss_acc);
+    FASTRON_HIP(hipGetLastError());
+    TRY(fast_step(n, P, y, nullptr, 0, N, N, false, 0.f, nullptr, s));
+    if (loss) {
+      double acc = 0.0;
+      FASTRON_HIP(hipMemcpyAsync(&acc, n->loss_acc, sizeof(double), hipMemcpyDeviceToHost, s));
+      FASTRON_HIP(hipStreamSynchronize(s));
+      *loss = (float)(acc / (double)N);
+    }
+    return FASTRON_OK;
+  }
   TRY(stage_points(n, P, nullptr, 0, N, N, s));
   TRY(forward_staged(n, N, true, s));
   TRY(backward(n, N, y, nullptr, 0, N, s));
@@ -989,6 +1585,25 @@ fastron_status fastron_mlp_train_epoch(fastron_mlp* n, const float* P, const int
   hipStream_t s = as_stream(stream);
   const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
   FASTRON_HIP(hipMemsetAsync(n->bad, 0, sizeof(int), s));
+  if (n->fast) {
+    // three kernels per batch, the loss summed on the device; one synchronisation per epoch
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(64), 0, s, n->loss_acc);
+    FASTRON_HIP(hipGetLastError());
+    for (int64_t r0 = 0; r0 < N; r0 += batch) {
+      const int64_t rows = N - r0 < batch ? N - r0 : batch;
+      TRY(fast_step(n, P, y, order, r0, rows, N, true, lr, nullptr, s));
+    }
+    struct {
+      double loss;
+      int bad;
+    } h{0.0, 0};
+    FASTRON_HIP(hipMemcpyAsync(&h.loss, n->loss_acc, sizeof(double), hipMemcpyDeviceToHost, s));
+    FASTRON_HIP(hipMemcpyAsync(&h.bad, n->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    FASTRON_HIP(hipStreamSynchronize(s));
+    if (h.bad) return fail(FASTRON_EINVAL, "order holds a row index outside [0, N)");
+    if (mean_loss) *mean_loss = (float)(h.loss / (double)N);
+    return FASTRON_OK;
+  }
   std::vector<float> lp;
   double loss_acc = 0.0;
   for (int64_t r0 = 0; r0 < N; r0 += batch) {

@@ -23,23 +23,23 @@ def _data(oracle_mod, N, name, n_cubes=20):
     return arm, q, P, y.astype(np.int8)
 
 
-def _grad_setup(oracle_mod, dev, N, name, max_rows):
+def _grad_setup(oracle_mod, dev, N, name, max_rows, H=256):
     arm, q, P, y = _data(oracle_mod, N, name)
     d_in = 24
-    params = wl.mlp_init(d_in, 256, name=f"{name}_init")
+    params = wl.mlp_init(d_in, H, name=f"{name}_init")
     g = wl.rng(f"{name}/biases")
-    params[d_in * 256:d_in * 256 + 256] = g.normal(0, 0.1, 256)           # b1
-    o2 = d_in * 256 + 256 + 256 * 256
-    params[o2:o2 + 256] = g.normal(0, 0.1, 256)                           # b2
+    params[d_in * H:d_in * H + H] = g.normal(0, 0.1, H)                   # b1
+    o2 = d_in * H + H + H * H
+    params[o2:o2 + H] = g.normal(0, 0.1, H)                               # b2
     params[-1] = 0.2                                                      # b3
     X = P.reshape(-1, d_in).astype(np.float64)
     mu = X.mean(axis=0)
     sd = X.std(axis=0)
     sd[sd < 1e-6] = 1.0
     mu32, sd32 = mu.astype(np.float32), sd.astype(np.float32)
-    net = api.MLP(d_in, 256, max_rows=max_rows)
+    net = api.MLP(d_in, H, max_rows=max_rows)
     net.set_params(torch.from_numpy(params).to(dev), torch.from_numpy(mu32).to(dev), torch.from_numpy(sd32).to(dev))
-    ps = [p_.astype(np.float64) for p_ in wl.split_mlp_params(params, d_in)]
+    ps = [p_.astype(np.float64) for p_ in wl.split_mlp_params(params, d_in, H)]
     return net, P, X, y, params, ps, mu32.astype(np.float64), sd32.astype(np.float64)
 
 
@@ -62,13 +62,15 @@ def ADAM_F32(lr):
     return dict(lr=f(lr), beta1=f(0.9), beta2=f(0.999), eps=f(1e-8))
 
 
-def test_forward_and_gradients_match_oracle(oracle_mod, dev):
+@pytest.mark.parametrize("H", [256, 128])
+def test_forward_and_gradients_match_oracle(oracle_mod, dev, H):
     """Forward logits, loss and all six gradients of one batch against the oracle, element by element: the
     oracle's BF16 forms round to bfloat16 where the device does, and every difference must lie within the bound
     propagated from the device's FP32 arithmetic, the bfloat16 roundings that this arithmetic can tip and the
     ReLU decisions it can flip (tests/mlp_bounds.py). Nonzero biases, so that every bias path carries weight.
-    Also reported: the relative L2 distance to the unrounded FP64 network."""
-    net, P, X, y, params, ps, mu, sd = _grad_setup(oracle_mod, dev, 700, "mlp_grad", 1024)
+    Also reported: the relative L2 distance to the unrounded FP64 network. Hidden width 256 runs the
+    three-kernel training step, 128 the staged GEMM path."""
+    net, P, X, y, params, ps, mu, sd = _grad_setup(oracle_mod, dev, 700, "mlp_grad", 1024, H)
     P_d = torch.from_numpy(P).to(dev)
     announce("mlp forward")
     z = net.forward(P_d).cpu().numpy().astype(np.float64)
@@ -86,7 +88,7 @@ def test_forward_and_gradients_match_oracle(oracle_mod, dev):
     z64, c64 = mo.forward(ps, X, mu, sd)
     g64 = mo.backward(ps, c64, z64, y)
     report["logits_rel_l2_vs_fp64"] = float(np.linalg.norm(z - z64) / np.linalg.norm(z64))
-    gs = wl.split_mlp_params(g, 24)
+    gs = wl.split_mlp_params(g, 24, H)
     for k, (a, b, e) in enumerate(zip(gs, g_ref, Eg)):
         err = np.abs(np.ravel(a) - np.ravel(b))
         e = np.ravel(e)
@@ -100,11 +102,12 @@ def test_forward_and_gradients_match_oracle(oracle_mod, dev):
     net.close()
 
 
-def test_adam_first_step_matches_oracle(oracle_mod, dev):
+@pytest.mark.parametrize("H", [256, 128])
+def test_adam_first_step_matches_oracle(oracle_mod, dev, H):
     """One batch of train_epoch (a fixed row order, lr = 1e-3) against the oracle's forward -> backward ->
     adam_step, element by element: at step 1, m = (1 - beta1) g, v = (1 - beta2) g^2 and the update is
     lr g / (|g| + eps), so each bound follows from the gradient's bound."""
-    net, P, X, y, params, ps, mu, sd = _grad_setup(oracle_mod, dev, 1000, "mlp_adam1", 1024)
+    net, P, X, y, params, ps, mu, sd = _grad_setup(oracle_mod, dev, 1000, "mlp_adam1", 1024, H)
     order = wl.rng("mlp_adam1/order").permutation(1000).astype(np.int32)
     lr = 1e-3
     announce("mlp one Adam step")

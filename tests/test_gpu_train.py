@@ -272,3 +272,62 @@ def test_configuration_forms_match_points_forms(oracle_mod, dev):
         k2 = api.gram_update_points(P, 10.0, i, da, F=F2)
         assert torch.equal(k1, k2) and torch.equal(F1, F2)
         assert float(k1[i]) == 1.0
+
+
+@pytest.mark.parametrize("arm_name,N,gamma", [("3dof", 2000, 10.0), ("7dof", 4000, 30.0)])
+def test_train_fp32_first_divergence(oracle_mod, dev, arm_name, N, gamma):
+    """FP32 Algorithm 1 against the FP64 oracle's trajectory (3-DOF workload: 2,000 labelled samples,
+    gamma = 10; 7-DOF: 4,000 samples against 20 cubes, gamma = 30): reports the first update at which the two
+    take a different action or index. Up to there the trajectories agree by definition; at that update the
+    device's choice must be one that FP32 rounding can explain -- within twice the F drift bound of the
+    oracle's own choice under the oracle's FP64 state (a near-tie of two margins, or a margin or a removal
+    value within that distance of the threshold 0)."""
+    from conftest import FP32_F_DRIFT
+
+    if arm_name == "3dof":
+        arm = wl.arm_3dof()
+        dh = oracle_dh(oracle_mod, arm)
+        for seed in range(wl.MASTER_SEED, wl.MASTER_SEED + 200):
+            q = wl.configs("train3", N, arm.n, seed=seed)
+            lo, hi = wl.cubes("train3/cubes", 5, 0.15, None, seed=seed)
+            y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+            if 0.1 <= np.mean(y == 1) <= 0.9:
+                break
+    else:
+        arm = wl.arm_7dof()
+        dh = oracle_dh(oracle_mod, arm)
+        q = wl.configs("diverge7", N, arm.n)
+        lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+        y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
+    y = y.astype(np.int8)
+    P32 = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
+    P64 = P32.astype(np.float64)
+    ref = oracle_mod.fastron_update(P64, y, gamma, trace=True)
+    cap = ref["updates"] + 1000
+    announce(f"fp32 first divergence: train N={N} {arm_name}")
+    out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), gamma, trace_cap=cap)
+    ta, ti = out["trace_action"].cpu().numpy(), out["trace_index"].cpu().numpy()
+    ra, ri = ref["trace_action"], ref["trace_index"]
+    n = min(len(ta), len(ra))
+    diff = np.flatnonzero((ta[:n] != ra[:n]) | (ti[:n] != ri[:n]))
+    k = int(diff[0]) if diff.size else (n if len(ta) != len(ra) else None)
+    info = dict(first_divergence=k, device_updates=int(out["updates"]), oracle_updates=int(ref["updates"]),
+                device_support=int(out["support"].numel()), oracle_support=int(ref["support"].size))
+    print(info)
+    if k is None:
+        return
+    # the oracle's FP64 state just before update k
+    st = oracle_mod.fastron_update(P64, y, gamma, iter_max=k)
+    F, a = st["F"], st["alpha"]
+    m = y * F
+    v = np.where(a != 0, y * (F - a), -np.inf)
+    tol = 2 * FP32_F_DRIFT
+    dev_act = int(ta[k]) if k < len(ta) else 0  # 0: the device stopped
+    dev_idx = int(ti[k]) if k < len(ti) else -1
+    m_min = m.min()
+    if dev_act == 1:      # the device corrected point dev_idx: a smallest margin, and <= 0, within tolerance
+        assert m[dev_idx] <= m_min + tol and m[dev_idx] <= tol, (info, m[dev_idx], m_min)
+    elif dev_act == 2:    # the device pruned dev_idx: no margin clearly <= 0, and a largest removal value > 0
+        assert m_min > -tol and v[dev_idx] >= v.max() - tol and v[dev_idx] > -tol, (info, m_min, v[dev_idx])
+    else:                 # the device stopped: no margin clearly <= 0 and no removal value clearly > 0
+        assert m_min > -tol and v.max() < tol, (info, m_min, v.max())
