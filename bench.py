@@ -102,9 +102,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extras", action="store_true", help="only the main metric (for profiling runs)")
     ap.add_argument("--legs",
-                    default="peaks,kernels,forms,precision,dof3,train,compare,obstacles,active,batched,retrain,screen",
+                    default="peaks,kernels,forms,precision,dof3,train,compare,obstacles,active,batched,retrain,mlp,"
+                            "screen",
                     help="comma-separated extra legs (peaks, kernels, forms, precision, dof3, train, compare, "
-                         "obstacles, active, batched, retrain, screen)")
+                         "obstacles, active, batched, retrain, mlp, screen)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="target CPU time of the oracle sample")
     ap.add_argument("--mlp-epochs", type=int, default=10, help="epochs of the screening network in the extras")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -115,7 +116,7 @@ def main():
               file=sys.stderr)
         sys.exit(2)
     legs = set() if args.no_extras else {x.strip() for x in args.legs.split(",") if x.strip()}
-    unknown = legs - {"peaks", "kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "active", "batched",
+    unknown = legs - {"peaks", "mlp", "kernels", "forms", "precision", "dof3", "train", "compare", "obstacles", "active", "batched",
                       "retrain", "screen"}
     if unknown:
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
@@ -254,6 +255,9 @@ def main():
     if "retrain" in legs:
         log("[bench] re-training 16 environments after their cubes move")
         extras["retrain16"] = retrain_run(api, wl, arm, dev)
+    if "mlp" in legs:
+        log("[bench] screening network training step")
+        extras["mlp_train"] = mlp_run(api, wl, arm, dev)
     if "screen" in legs:
         log("[bench] learned screening (MLP + tau fallback)")
         extras["screen"] = screen_run(api, wl, arm, dev, epochs=args.mlp_epochs)
@@ -853,6 +857,49 @@ def retrain_run(api, wl, arm, dev, n_env=16, N=20_000):
             "one_launch": {"first_ms": (t1 - t0) * 1e3, "warm_ms": (t2 - t1) * 1e3,
                            "warm_speedup_vs_one_after_another": sum(r["warm_ms"] for r in rows) / ((t2 - t1) * 1e3),
                            "converged": bool(b0["converged"] and b1["converged"]), "identical": bool(same)}}
+
+
+BF16_PEAK_TFLOPS = 2500.0
+
+
+def mlp_train_flops(d_in, H):
+    """Algorithmic FLOP to train the screening network on one sample: forward (both layers and the head, bias
+    adds included) 2 (d_in H + H H + H), dH1 2 H H, and the two weight gradients 2 H H + 2 d_in H."""
+    return 2 * (d_in * H + H * H + H) + 2 * H * H + 2 * H * H + 2 * d_in * H
+
+
+def mlp_run(api, wl, arm, dev, epochs=3, n_train=1_900_000):
+    """The screening network's training step alone (no Fastron training in this leg): epochs over n_train
+    labelled configurations of the 20-cube environment, batch 8,192, each epoch timed with HIP events; FLOP per
+    epoch from mlp_train_flops against the dense BF16 peak."""
+    import torch
+
+    lo, hi = wl.cubes("bench7/cubes", 20, 0.1, 0.25)
+    q_tr = torch.from_numpy(wl.configs("bench7/screen_train", n_train, arm.n)).to(dev)
+    y_tr, _ = api.label_capsule_box(arm, q_tr, arm.radius, lo, hi, want_clearance=False)
+    P_tr = api.fk_points(arm, q_tr)
+    del q_tr
+    d_in = 3 * arm.M
+    net = api.MLP(d_in, 256, max_rows=8192)
+    net.set_params(torch.from_numpy(wl.mlp_init(d_in, 256, name="bench7/mlp_init")).to(dev))
+    net.fit_standardisation(P_tr)
+    perms = [torch.from_numpy(wl.rng(f"bench7/mlp_perm{ep}").permutation(n_train).astype(np.int32)).to(dev)
+             for ep in range(epochs)]
+    ms, losses = [], []
+    for ep in range(epochs):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        losses.append(net.train_epoch(P_tr, y_tr, perms[ep], batch=8192, lr=1e-3))
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    net.close()
+    flops = mlp_train_flops(d_in, 256) * n_train
+    best = float(np.median(ms))
+    return {"samples": n_train, "batch": 8192, "epochs": epochs, "epoch_ms": ms, "epoch_ms_median": best,
+            "samples_per_s": n_train / (best * 1e-3), "flop_per_epoch": flops,
+            "tflops": flops / (best * 1e-3) / 1e12, "frac_bf16_peak": flops / (best * 1e-3) / 1e12 / BF16_PEAK_TFLOPS,
+            "losses": losses}
 
 
 def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304, taus=(0.0, 0.5, 1.0, 2.0, 4.0)):
