@@ -416,12 +416,24 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
 
 /* ---- tuning ----------------------------------------------------------------
  * Process-wide launch parameters (host side):
- *   "train.kernel"      1 (default): single-wave workgroups, no workgroup
- *                       barriers; 0: multi-wave workgroups (also used when
- *                       the single-wave grid would exceed its limits)
- *   "train.wave_groups" grid cap of the single-wave kernel, 1..512 (256)
- *   "train.blocks"      workgroups of the multi-wave grid, 0 = automatic
- *   "train.threads"     threads per multi-wave workgroup: 256, 512 or 1024
+ *   "train.kernel"      1 (default): the wave form of Algorithm 1 (one
+ *                       wave per workgroup exchanges the workgroup's record;
+ *                       no barrier inside the exchange); 0: the slice kernel
+ *                       (also used when the wave form's grid would exceed
+ *                       its limits)
+ *   "train.waves"       waves per workgroup of the wave form: 1, 2, 4, 8
+ *                       (default) or 16; with p points per lane at most
+ *                       16 / p (single-wave workgroups take over when the
+ *                       multi-wave grid would exceed 256 workgroups, 128 in
+ *                       FP64)
+ *   "train.wave_groups" grid cap of the wave form, 1..512 (128): the points
+ *                       per lane double until the grid fits
+ *   "train.poll_delay"  sleeps of 64 clocks before the first poll of each
+ *                       record exchange, 0..64, or -1 (default): adapted by
+ *                       each workgroup to how often its first poll came too
+ *                       early. Timing only; results do not depend on it.
+ *   "train.blocks"      workgroups of the slice kernel, 0 = automatic
+ *   "train.threads"     threads per slice-kernel workgroup: 256, 512 or 1024
  *   "score.rational"    1 (default): the scoring kernels (FP32 MFMA and
  *                       VALU, BF16, batched) sum a pair's 1/t^2 terms as one
  *                       running fraction (one reciprocal per pair) when a

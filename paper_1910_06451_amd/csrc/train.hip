@@ -68,6 +68,7 @@ struct TrainState {
   int D;               // coordinates per point: 3 for control points, n for joint vectors
   int chunk;           // training points per workgroup
   long long timeout;    // wait limit for the record exchange, in constant-clock ticks
+  int poll_delay;       // wave form: sleeps (64 clocks each) before the first poll; -1 = adaptive
   int p_in_lds;         // the slice's control points are staged in LDS
   // several independent training sets in one launch (single-wave kernel only):
   // workgroup w trains set env_of[w], whose workgroups are env_wg0[e] ..
@@ -260,81 +261,94 @@ __device__ __forceinline__ void point_record(Rec<T>& r, int64_t j, T yj, T Fj, T
   rec_merge(r, c);
 }
 
-// Record exchange without a central barrier: each record is published as
-// 64-bit words, each holding 32 payload bits and the 32-bit sequence number of
-// the iteration. A word is stored and loaded with single-copy-atomic,
-// device-coherent 64-bit accesses, so a reader that sees the current
-// sequence number in every word of a record has the whole record; no fence
-// or read-modify-write is needed. Records are double-buffered by iteration
-// parity (a workgroup cannot publish iteration it + 2 before every workgroup
+// Record exchange without a central barrier: a record is published as K
+// 64-bit words, each holding 56 payload bits under an 8-bit tag, the low
+// byte of the iteration number + 1. A word is stored and loaded with
+// single-copy-atomic, device-coherent 64-bit accesses, so a reader that sees
+// the current tag in every word of a record has the whole record; no fence or
+// read-modify-write is needed. Records are double-buffered by iteration
+// parity: a workgroup cannot publish iteration it + 2 before every workgroup
 // has published iteration it + 1, which each does only after reading
-// iteration it).
+// iteration it. The slot a reader polls at iteration it therefore holds the
+// writer's word of iteration it - 2 (which this reader has already read, so
+// nothing older can come back) or of iteration it, or for it < 2 the zeros
+// written before the launch; their tags differ modulo 256.
+__device__ __forceinline__ unsigned long long rec_tag(int64_t it) {
+  return (unsigned long long)((it + 1) & 0xff) << 56;
+}
+__device__ __forceinline__ bool rec_tagged(unsigned long long w, unsigned long long tag) {
+  return (w & 0xff00000000000000ull) == tag;
+}
+
 template <typename T>
 struct RecWords;
+// FP32 record in 4 words: each word carries one of the four values (32 bits)
+// and the low 24 bits of one of the three 31-bit integers minidx + 1,
+// maxidx + 1 and count (indices and counts are below 2^31 - 1); word 3 carries
+// their top 7 bits and the label bit instead.
 template <>
 struct RecWords<float> {
-  static constexpr int K = 8;
-  __device__ static uint32_t get(const Rec<float>& r, int k) {
+  static constexpr int K = 4;
+  __device__ static unsigned long long get(const Rec<float>& r, int k) {
+    const unsigned long long mi = (uint32_t)(r.minidx + 1), xi = (uint32_t)(r.maxidx + 1), c = (uint32_t)r.count;
     switch (k) {
-      case 0: return __float_as_uint(r.minval);
-      case 1: return __float_as_uint(r.a_at_min);
-      case 2: return __float_as_uint(r.maxval);
-      case 3: return __float_as_uint(r.a_at_max);
-      case 4: return (uint32_t)r.minidx;
-      case 5: return (uint32_t)r.maxidx;
-      case 6: return (uint32_t)r.count;
-      default: return (uint32_t)r.ymin;
+      case 0: return __float_as_uint(r.minval) | ((mi & 0xffffff) << 32);
+      case 1: return __float_as_uint(r.a_at_min) | ((xi & 0xffffff) << 32);
+      case 2: return __float_as_uint(r.maxval) | ((c & 0xffffff) << 32);
+      default:
+        return __float_as_uint(r.a_at_max) |
+               (((mi >> 24) | ((xi >> 24) << 7) | ((c >> 24) << 14) | ((r.ymin > 0 ? 1ull : 0ull) << 21)) << 32);
     }
   }
-  __device__ static Rec<float> make(const uint32_t* w) {
+  __device__ static Rec<float> make(const unsigned long long* w) {
+    const uint32_t h = (uint32_t)(w[3] >> 32) & 0xffffff;
     Rec<float> r;
-    r.minval = __uint_as_float(w[0]);
-    r.a_at_min = __uint_as_float(w[1]);
-    r.maxval = __uint_as_float(w[2]);
-    r.a_at_max = __uint_as_float(w[3]);
-    r.minidx = (int32_t)w[4];
-    r.maxidx = (int32_t)w[5];
-    r.count = (int32_t)w[6];
-    r.ymin = (int32_t)w[7];
+    r.minval = __uint_as_float((uint32_t)w[0]);
+    r.a_at_min = __uint_as_float((uint32_t)w[1]);
+    r.maxval = __uint_as_float((uint32_t)w[2]);
+    r.a_at_max = __uint_as_float((uint32_t)w[3]);
+    r.minidx = (int32_t)((((uint32_t)(w[0] >> 32)) & 0xffffff) | ((h & 0x7f) << 24)) - 1;
+    r.maxidx = (int32_t)((((uint32_t)(w[1] >> 32)) & 0xffffff) | (((h >> 7) & 0x7f) << 24)) - 1;
+    r.count = (int32_t)((((uint32_t)(w[2] >> 32)) & 0xffffff) | (((h >> 14) & 0x7f) << 24));
+    r.ymin = ((h >> 21) & 1) ? 1 : -1;
     return r;
   }
 };
+// FP64 record in 7 words: words 0-3 the low 56 bits of the four values, word 4
+// their top bytes and 24 bits of minidx + 1, word 5 maxidx + 1 and 25 bits of
+// the count, word 6 the remaining bits and the label bit.
 template <>
 struct RecWords<double> {
-  static constexpr int K = 12;
-  __device__ static uint32_t half(double v, int hi) {
-    const uint64_t u = (uint64_t)__double_as_longlong(v);
-    return hi ? (uint32_t)(u >> 32) : (uint32_t)u;
-  }
-  __device__ static double join(uint32_t lo, uint32_t hi) {
-    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-  }
-  __device__ static uint32_t get(const Rec<double>& r, int k) {
+  static constexpr int K = 7;
+  static constexpr unsigned long long kLow56 = (1ull << 56) - 1;
+  __device__ static unsigned long long bits(double v) { return (unsigned long long)__double_as_longlong(v); }
+  __device__ static unsigned long long get(const Rec<double>& r, int k) {
+    const unsigned long long mi = (uint32_t)(r.minidx + 1), xi = (uint32_t)(r.maxidx + 1), c = (uint32_t)r.count;
     switch (k) {
-      case 0: return half(r.minval, 0);
-      case 1: return half(r.minval, 1);
-      case 2: return half(r.a_at_min, 0);
-      case 3: return half(r.a_at_min, 1);
-      case 4: return half(r.maxval, 0);
-      case 5: return half(r.maxval, 1);
-      case 6: return half(r.a_at_max, 0);
-      case 7: return half(r.a_at_max, 1);
-      case 8: return (uint32_t)r.minidx;
-      case 9: return (uint32_t)r.maxidx;
-      case 10: return (uint32_t)r.count;
-      default: return (uint32_t)r.ymin;
+      case 0: return bits(r.minval) & kLow56;
+      case 1: return bits(r.a_at_min) & kLow56;
+      case 2: return bits(r.maxval) & kLow56;
+      case 3: return bits(r.a_at_max) & kLow56;
+      case 4:
+        return (bits(r.minval) >> 56) | ((bits(r.a_at_min) >> 56) << 8) | ((bits(r.maxval) >> 56) << 16) |
+               ((bits(r.a_at_max) >> 56) << 24) | ((mi & 0xffffff) << 32);
+      case 5: return xi | ((c & 0x1ffffff) << 31);
+      default: return (mi >> 24) | ((c >> 25) << 7) | ((r.ymin > 0 ? 1ull : 0ull) << 13);
     }
   }
-  __device__ static Rec<double> make(const uint32_t* w) {
+  __device__ static double join(unsigned long long lo, unsigned long long top) {
+    return __longlong_as_double((long long)((lo & kLow56) | ((top & 0xff) << 56)));
+  }
+  __device__ static Rec<double> make(const unsigned long long* w) {
     Rec<double> r;
-    r.minval = join(w[0], w[1]);
-    r.a_at_min = join(w[2], w[3]);
-    r.maxval = join(w[4], w[5]);
-    r.a_at_max = join(w[6], w[7]);
-    r.minidx = (int32_t)w[8];
-    r.maxidx = (int32_t)w[9];
-    r.count = (int32_t)w[10];
-    r.ymin = (int32_t)w[11];
+    r.minval = join(w[0], w[4]);
+    r.a_at_min = join(w[1], w[4] >> 8);
+    r.maxval = join(w[2], w[4] >> 16);
+    r.a_at_max = join(w[3], w[4] >> 24);
+    r.minidx = (int32_t)(((uint32_t)(w[4] >> 32) & 0xffffff) | (((uint32_t)w[6] & 0x7f) << 24)) - 1;
+    r.maxidx = (int32_t)((uint32_t)w[5] & 0x7fffffff) - 1;
+    r.count = (int32_t)(((uint32_t)(w[5] >> 31) & 0x1ffffff) | ((((uint32_t)w[6] >> 7) & 0x3f) << 25));
+    r.ymin = (((uint32_t)w[6] >> 13) & 1) ? 1 : -1;
     return r;
   }
 };
@@ -388,17 +402,17 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
     if (wave == 0) {
       Rec<T> mine = sh[0];
       for (int w = 1; w < nw; ++w) rec_merge(mine, sh[w]);
-      const unsigned long long seq = (unsigned long long)(uint32_t)(it + 1) << 32;
+      const unsigned long long tag = rec_tag(it);
       unsigned long long* slot = words + (size_t)(it & 1) * G * K;
       if (lane < K)
-        __hip_atomic_store(slot + (size_t)blockIdx.x * K + lane, seq | RecWords<T>::get(mine, lane),
+        __hip_atomic_store(slot + (size_t)blockIdx.x * K + lane, tag | RecWords<T>::get(mine, lane),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       // gather: lane l reads records l, l + 64, ...
       Rec<T> gr = rec_empty<T>();
       bool ok = true;
       for (unsigned base = 0; base < G; base += 64) {
         const unsigned w = base + lane;
-        uint32_t pay[K];
+        unsigned long long pay[K];
         bool ready = w >= G;
         const long long t0 = wall_clock64();
         while (true) {
@@ -408,8 +422,8 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
             for (int k = 0; k < K; ++k) {
               const unsigned long long v =
                   __hip_atomic_load(slot + (size_t)w * K + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              pay[k] = (uint32_t)v;
-              ready = ready && ((v & 0xffffffff00000000ull) == seq);
+              pay[k] = v;
+              ready = ready && rec_tagged(v, tag);
             }
           }
           if (__all(ready)) break;
@@ -499,61 +513,243 @@ __global__ void __launch_bounds__(1024) k_train(TrainState<T> st) {
   }
 }
 
-// Whole-wave reduction of records with butterflies, every lane ends with the
-// result: the (value, index) pairs are compared lexicographically (lowest
-// index on ties) and the count summed; the payloads (weights, label) come
-// from the lane that holds the winning index (indices are unique across the
-// lanes' records).
-template <typename T>
-__device__ __forceinline__ Rec<T> wave_allreduce(const Rec<T>& r) {
-  T mv = r.minval, xv = r.maxval;
-  int mi = r.minidx, xi = r.maxidx, cnt = r.count;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    const T omv = __shfl_xor(mv, off), oxv = __shfl_xor(xv, off);
-    const int omi = __shfl_xor(mi, off), oxi = __shfl_xor(xi, off);
-    cnt += __shfl_xor(cnt, off);
-    const bool tmin = omi >= 0 && (mi < 0 || omv < mv || (omv == mv && omi < mi));
-    const bool tmax = oxi >= 0 && (xi < 0 || oxv > xv || (oxv == xv && oxi < xi));
-    mv = tmin ? omv : mv;
-    mi = tmin ? omi : mi;
-    xv = tmax ? oxv : xv;
-    xi = tmax ? oxi : xi;
+// Whole-wave reduction of records (or of the first row of 16 lanes, the
+// first four steps only); every lane ends with the result. The
+// (value, index) pairs are compared lexicographically (lowest index on ties)
+// and the counts summed along the DPP sequence quad_perm [1,0,3,2],
+// quad_perm [2,3,0,1], row_half_mirror, row_mirror (after which every lane of
+// a row of 16 holds its row's result), row_bcast:15 into rows 1 and 3 and
+// row_bcast:31 into rows 2 and 3, so that lane 63 holds the wave's result
+// (lane 0 the row's); no step goes through LDS. The fields are read from that
+// lane and the payloads
+// (weights, label) from the lane whose own record holds the winning index
+// (indices are unique across the lanes' records).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_keep(int v) {  // lanes outside ROWS keep their own value
+  if constexpr (ROWS == 0xf)
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);  // every lane written: no copy of v first
+  else
+    return __builtin_amdgcn_update_dpp(v, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_zero(int v) {  // lanes outside ROWS read 0
+  return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ unsigned long long dpp_keep64(unsigned long long v) {
+  const uint32_t lo = (uint32_t)dpp_keep<CTRL, ROWS>((int)(uint32_t)v);
+  const uint32_t hi = (uint32_t)dpp_keep<CTRL, ROWS>((int)(uint32_t)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ unsigned long long readlane64(unsigned long long v, int l) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+  return ((unsigned long long)hi << 32) | lo;
+}
+__device__ __forceinline__ float readlane(float v, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ double readlane(double v, int l) {
+  return __longlong_as_double((long long)readlane64((unsigned long long)__double_as_longlong(v), l));
+}
+
+// FP32 records, in two passes of single DPP-modified min / max / add
+// instructions. Pass 1 reduces the values, mapped to an unsigned
+// order-preserving form (-0 taken as +0 since the two compare equal; an empty
+// half maps to the form that never wins), and the counts; pass 2 reduces the
+// indices of the lanes whose value equals the winner (the lowest index wins a
+// tie, for the min and the max alike).
+__device__ __forceinline__ uint32_t ordered_bits(float v) {
+  const uint32_t u = v == 0.f ? 0u : __float_as_uint(v);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+// Lanes outside ROWS read the operation's identity, so each step is one
+// DPP-modified instruction.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_ident(uint32_t v, uint32_t ident) {
+  if constexpr (ROWS == 0xf)
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, CTRL, 0xf, 0xf, true);
+  else
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)ident, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void value_step(uint32_t& vmin, uint32_t& vmax, int& cnt) {
+  const uint32_t omin = dpp_ident<CTRL, ROWS>(vmin, 0xffffffffu), omax = dpp_ident<CTRL, ROWS>(vmax, 0u);
+  cnt += dpp_zero<CTRL, ROWS>(cnt);
+  vmin = omin < vmin ? omin : vmin;
+  vmax = omax > vmax ? omax : vmax;
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void index_step(uint32_t& imin, uint32_t& imax) {
+  const uint32_t omin = dpp_ident<CTRL, ROWS>(imin, 0xffffffffu), omax = dpp_ident<CTRL, ROWS>(imax, 0xffffffffu);
+  imin = omin < imin ? omin : imin;
+  imax = omax < imax ? omax : imax;
+}
+// The two passes; every lane ends with the winners' ordered values and
+// indices (kNoIndex for an empty half) and the count.
+constexpr uint32_t kNoIndex = 0x7fffffffu;
+template <int LANES>
+__device__ __forceinline__ void wave_winners(const Rec<float>& r, uint32_t& vmin, uint32_t& imin, uint32_t& vmax,
+                                             uint32_t& imax, int& cnt) {
+  static_assert(LANES == 64 || LANES == 16, "whole wave or its first row");
+  constexpr int kOut = LANES == 64 ? 63 : 0;  // the lane that ends with the result
+  const uint32_t mine_min = r.minidx < 0 ? 0xffffffffu : ordered_bits(r.minval);
+  const uint32_t mine_max = r.maxidx < 0 ? 0u : ordered_bits(r.maxval);
+  vmin = mine_min;
+  vmax = mine_max;
+  cnt = r.count;
+  value_step<0xB1, 0xf>(vmin, vmax, cnt);
+  value_step<0x4E, 0xf>(vmin, vmax, cnt);
+  value_step<0x141, 0xf>(vmin, vmax, cnt);
+  value_step<0x140, 0xf>(vmin, vmax, cnt);
+  if constexpr (LANES == 64) {
+    value_step<0x142, 0xa>(vmin, vmax, cnt);
+    value_step<0x143, 0xc>(vmin, vmax, cnt);
   }
-  Rec<T> o = rec_empty<T>();
+  vmin = (uint32_t)__builtin_amdgcn_readlane((int)vmin, kOut);
+  vmax = (uint32_t)__builtin_amdgcn_readlane((int)vmax, kOut);
+  imin = (r.minidx >= 0 && mine_min == vmin) ? (uint32_t)r.minidx : kNoIndex;
+  imax = (r.maxidx >= 0 && mine_max == vmax) ? (uint32_t)r.maxidx : kNoIndex;
+  index_step<0xB1, 0xf>(imin, imax);
+  index_step<0x4E, 0xf>(imin, imax);
+  index_step<0x141, 0xf>(imin, imax);
+  index_step<0x140, 0xf>(imin, imax);
+  if constexpr (LANES == 64) {
+    index_step<0x142, 0xa>(imin, imax);
+    index_step<0x143, 0xc>(imin, imax);
+  }
+  imin = (uint32_t)__builtin_amdgcn_readlane((int)imin, kOut);
+  imax = (uint32_t)__builtin_amdgcn_readlane((int)imax, kOut);
+  cnt = __builtin_amdgcn_readlane(cnt, kOut);
+}
+template <int LANES = 64>
+__device__ __forceinline__ Rec<float> wave_allreduce(const Rec<float>& r) {
+  uint32_t vmin, imin, vmax, imax;
+  int cnt;
+  wave_winners<LANES>(r, vmin, imin, vmax, imax, cnt);
+  Rec<float> o = rec_empty<float>();
   o.count = cnt;
-  if (mi >= 0) {
+  if (imin != kNoIndex) {
+    const int mi = (int)imin;
     const int src = __builtin_ctzll(__ballot(r.minidx == mi));
-    o.minval = mv;
     o.minidx = mi;
-    o.a_at_min = __shfl(r.a_at_min, src);
-    o.ymin = __shfl(r.ymin, src);
+    o.minval = readlane(r.minval, src);
+    o.a_at_min = readlane(r.a_at_min, src);
+    o.ymin = __builtin_amdgcn_readlane(r.ymin, src);
   }
-  if (xi >= 0) {
+  if (imax != kNoIndex) {
+    const int xi = (int)imax;
     const int src = __builtin_ctzll(__ballot(r.maxidx == xi));
-    o.maxval = xv;
     o.maxidx = xi;
-    o.a_at_max = __shfl(r.a_at_max, src);
+    o.maxval = readlane(r.maxval, src);
+    o.a_at_max = readlane(r.a_at_max, src);
   }
   return o;
 }
 
-// Single-wave form of the same algorithm: one wave per workgroup, so no
-// workgroup barrier stands between the column pass, the record exchange and
-// the decision. Each lane reads the records of workgroups lane, lane + 64, ...
-// (at most kWaveChunks x 64 workgroups), issuing the loads of all its records
-// before checking their tags.
+// Workgroup keys of FP32 records: the wave's winners as two unsigned 64-bit
+// keys whose order is the records' order (ordered value above, index below
+// for the min, 2^31 - 1 - index below for the max; the empty key never wins),
+// combined across waves with LDS atomic min / max.
+__device__ __forceinline__ unsigned long long min_key(uint32_t v, uint32_t i) {
+  return i == kNoIndex ? ~0ull : ((unsigned long long)v << 32) | i;
+}
+__device__ __forceinline__ unsigned long long max_key(uint32_t v, uint32_t i) {
+  return i == kNoIndex ? 0ull : ((unsigned long long)v << 32) | (kNoIndex - i);
+}
+__device__ __forceinline__ float from_ordered(uint32_t o) {
+  return __uint_as_float((o & 0x80000000u) ? (o & 0x7fffffffu) : ~o);
+}
+
+// FP64 records: the values compared as doubles (DPP moves of both halves).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_keep(double v) {
+  return __longlong_as_double((long long)dpp_keep64<CTRL, ROWS>((unsigned long long)__double_as_longlong(v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ void pair_step(double& mv, int& mi, double& xv, int& xi, int& cnt) {
+  const double omv = dpp_keep<CTRL, ROWS>(mv), oxv = dpp_keep<CTRL, ROWS>(xv);
+  const int omi = dpp_keep<CTRL, ROWS>(mi), oxi = dpp_keep<CTRL, ROWS>(xi);
+  cnt += dpp_zero<CTRL, ROWS>(cnt);
+  const bool tmin = omi >= 0 && (mi < 0 || omv < mv || (omv == mv && omi < mi));
+  const bool tmax = oxi >= 0 && (xi < 0 || oxv > xv || (oxv == xv && oxi < xi));
+  mv = tmin ? omv : mv;
+  mi = tmin ? omi : mi;
+  xv = tmax ? oxv : xv;
+  xi = tmax ? oxi : xi;
+}
+template <int LANES = 64>
+__device__ __forceinline__ Rec<double> wave_allreduce(const Rec<double>& r) {
+  static_assert(LANES == 64 || LANES == 16, "whole wave or its first row");
+  constexpr int kOut = LANES == 64 ? 63 : 0;
+  double mv = r.minval, xv = r.maxval;
+  int mi = r.minidx, xi = r.maxidx, cnt = r.count;
+  pair_step<0xB1, 0xf>(mv, mi, xv, xi, cnt);
+  pair_step<0x4E, 0xf>(mv, mi, xv, xi, cnt);
+  pair_step<0x141, 0xf>(mv, mi, xv, xi, cnt);
+  pair_step<0x140, 0xf>(mv, mi, xv, xi, cnt);
+  if constexpr (LANES == 64) {
+    pair_step<0x142, 0xa>(mv, mi, xv, xi, cnt);
+    pair_step<0x143, 0xc>(mv, mi, xv, xi, cnt);
+  }
+  mi = __builtin_amdgcn_readlane(mi, kOut);
+  xi = __builtin_amdgcn_readlane(xi, kOut);
+  Rec<double> o = rec_empty<double>();
+  o.count = __builtin_amdgcn_readlane(cnt, kOut);
+  if (mi >= 0) {
+    const int src = __builtin_ctzll(__ballot(r.minidx == mi));
+    o.minidx = mi;
+    o.minval = readlane(r.minval, src);
+    o.a_at_min = readlane(r.a_at_min, src);
+    o.ymin = __builtin_amdgcn_readlane(r.ymin, src);
+  }
+  if (xi >= 0) {
+    const int src = __builtin_ctzll(__ballot(r.maxidx == xi));
+    o.maxidx = xi;
+    o.maxval = readlane(r.maxval, src);
+    o.a_at_max = readlane(r.a_at_max, src);
+  }
+  return o;
+}
+
+// Wave form of the same algorithm. No workgroup barrier stands inside the
+// record exchange: one wave (wave 0) publishes the workgroup's record and
+// gathers the others, each lane reading the records of workgroups lane,
+// lane + 64, ... (issuing the loads of all its records before checking their
+// tags), and records are reduced with DPP row operations. MULTI = false: single-wave
+// workgroups (up to kWaveChunks x 64 of them). MULTI = true: workgroups of
+// blockDim.x / 64 waves (up to 16 / PT, so that a grid of a few dozen
+// workgroups covers a large training set: the exchange's cost grows with the
+// number of records every workgroup reads); the waves' records meet in LDS,
+// wave 0 exchanges their merge and broadcasts the decision, so an iteration
+// takes two workgroup barriers (up to kMultiChunks x 64 workgroups).
 constexpr int kWaveChunks = 8;
+constexpr int kMaxPollDelay = 64;  // sleeps before the first poll (about 2 us)
+template <typename T>
+constexpr int kMultiChunks = sizeof(T) == 4 ? 4 : 2;  // FP64 records take twice the registers
+constexpr int kMultiMaxPT = 4;  // points per lane of the multi-wave form (register budget at 1024 threads)
 
 // MM > 0: the chain has exactly MM control points and every lane keeps its
 // points' coordinates in registers for the whole run; MM = 0: any M, the
 // coordinates come from LDS (or global memory) in each column pass.
-template <typename T, int PT, int MM>
-__global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
+template <typename T, int PT, int MM, bool MULTI>
+__global__ void __launch_bounds__(MULTI ? 1024 / PT : 64) k_train_wave(TrainState<T> st) {
   constexpr int K = RecWords<T>::K;
+  constexpr int CH = MULTI ? kMultiChunks<T> : kWaveChunks;
+  // FP32 with several waves: the waves' records meet as LDS keys and per-lane
+  // payloads (see min_key); FP64: as whole records reduced by wave 0.
+  constexpr bool kKeys = MULTI && sizeof(T) == 4;
+  constexpr int kLanes = kKeys ? 1024 / PT : 1;
   __shared__ float pi_sh[3 * FASTRON_MAX_POINTS];
+  __shared__ Rec<T> sh[MULTI ? 16 : 1];
+  __shared__ Decision<T> dec;
+  __shared__ unsigned long long sh_kmin, sh_kmax;
+  __shared__ int sh_cnt;
+  __shared__ T sh_amin[kLanes], sh_amax[kLanes];
+  __shared__ int8_t sh_ymin[kLanes];
   extern __shared__ float pslice[];  // this slice's control points when they fit (st.p_in_lds)
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int nt = MULTI ? (int)blockDim.x : 64, nw = nt >> 6;
   // this workgroup's training set: its workgroups (G, own index me), points and records
   unsigned G = gridDim.x, me = blockIdx.x;
   int64_t set_lo = 0, set_hi = st.N;
@@ -569,11 +765,16 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
     words += (size_t)2 * K * w0;
     out += 2 * e;
   }
-  const int64_t j0 = set_lo + (int64_t)me * st.chunk;
+  const int64_t j0 = set_lo + (int64_t)me * st.chunk;  // chunk = nt * PT
   const int64_t j1 = (j0 + st.chunk < set_hi) ? j0 + st.chunk : set_hi;
   const int M = st.M, W = M * st.D;  // floats per training point
   if (st.p_in_lds)
-    for (int64_t e = lane; e < (j1 - j0) * W; e += 64) pslice[e] = st.P[j0 * W + e];
+    for (int64_t e = threadIdx.x; e < (j1 - j0) * W; e += nt) pslice[e] = st.P[j0 * W + e];
+  if (threadIdx.x == 0) {
+    sh_kmin = ~0ull;
+    sh_kmax = 0ull;
+    sh_cnt = 0;
+  }
   __syncthreads();
 
   T y[PT], F[PT], a[PT];
@@ -583,7 +784,7 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
   Rec<T> r = rec_empty<T>();
 #pragma unroll
   for (int k = 0; k < PT; ++k) {
-    jj[k] = j0 + lane + (int64_t)k * 64;
+    jj[k] = j0 + threadIdx.x + (int64_t)k * nt;
 #pragma unroll
     for (int e = 0; e < kReg; ++e) pjr[k][e] = 0.f;
     if (jj[k] < j1) {
@@ -601,83 +802,158 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
       a[k] = 0;
     }
   }
-  r = wave_allreduce(r);
+  if constexpr (!kKeys) r = wave_allreduce(r);
 
   int64_t updates = 0;
   int64_t status = 1;
+  // Sleeps before the first poll of an exchange. A poll that finds a record
+  // missing costs a whole memory round trip, and right after publishing the
+  // other workgroups' records are rarely all visible yet, so the first poll
+  // waits. Adaptive (poll_delay < 0): two more sleeps after an exchange whose
+  // first poll came too early, one fewer after four in a row that did not,
+  // which settles where about nine first polls in ten find every record.
+  int delay = st.poll_delay < 0 ? 8 : st.poll_delay, early_ok = 0;
   for (int64_t it = 0;; ++it) {
-    const unsigned long long seq = (unsigned long long)(uint32_t)(it + 1) << 32;
-    unsigned long long* slot = words + (size_t)(it & 1) * G * K;
-    if (lane < K)
-      __hip_atomic_store(slot + (size_t)me * K + lane, seq | RecWords<T>::get(r, lane), __ATOMIC_RELAXED,
-                         __HIP_MEMORY_SCOPE_AGENT);
-    uint32_t pay[kWaveChunks][K];
-    bool ready[kWaveChunks];
-#pragma unroll
-    for (int c = 0; c < kWaveChunks; ++c) ready[c] = c * 64 + lane >= (int)G;
-    bool ok = true;
-    const long long t0 = wall_clock64();
-    while (true) {
-      bool all = true;
-#pragma unroll
-      for (int c = 0; c < kWaveChunks; ++c) {
-        if (!ready[c]) {
-          const unsigned long long* rw = slot + (size_t)(c * 64 + lane) * K;
-          bool rd = true;
-#pragma unroll
-          for (int k = 0; k < K; ++k) {
-            const unsigned long long v = __hip_atomic_load(rw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            pay[c][k] = (uint32_t)v;
-            rd = rd && ((v & 0xffffffff00000000ull) == seq);
-          }
-          ready[c] = rd;
+    if constexpr (kKeys) {
+      // r is this lane's record: payload to LDS, the wave's keys into the workgroup's
+      if constexpr (sizeof(T) == 4) {
+        sh_amin[threadIdx.x] = r.a_at_min;
+        sh_amax[threadIdx.x] = r.a_at_max;
+        sh_ymin[threadIdx.x] = (int8_t)r.ymin;
+        uint32_t vmin, imin, vmax, imax;
+        int cnt;
+        wave_winners<64>(r, vmin, imin, vmax, imax, cnt);
+        if (lane == 0) {
+          atomicMin(&sh_kmin, min_key(vmin, imin));
+          atomicMax(&sh_kmax, max_key(vmax, imax));
+          atomicAdd(&sh_cnt, cnt);
         }
-        all = all && ready[c];
       }
-      if (__all(all)) break;
-      __builtin_amdgcn_s_sleep(1);
-      if (wall_clock64() - t0 > st.timeout) {
-        ok = false;
-        break;
-      }
-    }
-    Rec<T> gr = rec_empty<T>();
-    if (ok) {
-#pragma unroll
-      for (int c = 0; c < kWaveChunks; ++c)
-        if (c * 64 + lane < (int)G) rec_merge(gr, RecWords<T>::make(pay[c]));
-      gr = wave_allreduce(gr);
+      __syncthreads();  // the workgroup's keys are complete; every wave is done with pi_sh and dec
+    } else if constexpr (MULTI) {
+      if (lane == 0) sh[wave] = r;
+      __syncthreads();  // the waves' records are in LDS; every wave is done with pi_sh and dec
     }
     Decision<T> d;
-    d.action = 0;
-    d.i = -1;
-    d.dalpha = 0;
-    if (!ok) {
-      d.action = 4;
-    } else if (updates >= st.iter_max) {
-      d.action = 3;
-    } else if (gr.minidx >= 0 && gr.minval <= (T)0 && ((int64_t)gr.count < st.s_max || gr.a_at_min != (T)0)) {
-      d.i = gr.minidx;
-      const T yi = (T)gr.ymin;
-      const T Fi = yi * gr.minval;          // y = +-1: y (y F) = F exactly
-      const T bi = yi > 0 ? st.beta : (T)1;  // b_i = beta^(0.5 (y_i + 1)), Eq. 5
-      d.dalpha = sub_rn(bi * yi, Fi);        // Eq. 6
-      d.action = 1;
-    } else if (gr.maxidx >= 0 && gr.maxval > (T)0) {
-      d.i = gr.maxidx;
-      d.dalpha = -gr.a_at_max;
-      d.action = 2;
+    if (!MULTI || wave == 0) {
+      Rec<T> mine = r;
+      if constexpr (kKeys) {
+        // the winners' payloads sit at their lanes: index j is held by thread (j - j0) mod nt
+        const unsigned long long kmin = sh_kmin, kmax = sh_kmax;
+        mine = rec_empty<T>();
+        mine.count = sh_cnt;
+        if (kmin != ~0ull) {
+          const int mi = (int)(uint32_t)kmin;
+          const int pos = (int)((mi - j0) & (nt - 1));
+          mine.minidx = mi;
+          mine.minval = from_ordered((uint32_t)(kmin >> 32));
+          mine.a_at_min = sh_amin[pos];
+          mine.ymin = sh_ymin[pos];
+        }
+        if (kmax != 0ull) {
+          const int xi = (int)(kNoIndex - (uint32_t)kmax);
+          const int pos = (int)((xi - j0) & (nt - 1));
+          mine.maxidx = xi;
+          mine.maxval = from_ordered((uint32_t)(kmax >> 32));
+          mine.a_at_max = sh_amax[pos];
+        }
+        if (lane == 0) {  // after this wave's reads; the next atomics follow the second barrier
+          sh_kmin = ~0ull;
+          sh_kmax = 0ull;
+          sh_cnt = 0;
+        }
+      } else if constexpr (MULTI) {
+        mine = wave_allreduce<16>(lane < nw ? sh[lane] : rec_empty<T>());
+      }
+      const unsigned long long tag = rec_tag(it);
+      unsigned long long* slot = words + (size_t)(it & 1) * G * K;
+      if (lane < K)
+        __hip_atomic_store(slot + (size_t)me * K + lane, tag | RecWords<T>::get(mine, lane), __ATOMIC_RELAXED,
+                           __HIP_MEMORY_SCOPE_AGENT);
+      unsigned long long pay[CH][K];
+      bool ready[CH];
+#pragma unroll
+      for (int c = 0; c < CH; ++c) ready[c] = c * 64 + lane >= (int)G;
+      bool ok = true;
+      for (int q = 0; q < delay; ++q) __builtin_amdgcn_s_sleep(1);
+      int polls = 0;
+      const long long t0 = wall_clock64();
+      while (true) {
+        ++polls;
+        bool all = true;
+#pragma unroll
+        for (int c = 0; c < CH; ++c) {
+          if (!ready[c]) {
+            const unsigned long long* rw = slot + (size_t)(c * 64 + lane) * K;
+            bool rd = true;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+              pay[c][k] = __hip_atomic_load(rw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+              rd = rd && rec_tagged(pay[c][k], tag);
+            }
+            ready[c] = rd;
+          }
+          all = all && ready[c];
+        }
+        if (__all(all)) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > st.timeout) {
+          ok = false;
+          break;
+        }
+      }
+      if (st.poll_delay < 0) {
+        if (polls > 1) {
+          delay = delay + 2 < kMaxPollDelay ? delay + 2 : kMaxPollDelay;
+          early_ok = 0;
+        } else if (++early_ok == 4) {
+          delay = delay > 0 ? delay - 1 : 0;
+          early_ok = 0;
+        }
+      }
+      Rec<T> gr = rec_empty<T>();
+      if (ok) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c)
+          if (c * 64 < (int)G && c * 64 + lane < (int)G) rec_merge(gr, RecWords<T>::make(pay[c]));
+        gr = wave_allreduce(gr);
+      }
+      d.action = 0;
+      d.i = -1;
+      d.dalpha = 0;
+      if (!ok) {
+        d.action = 4;
+      } else if (updates >= st.iter_max) {
+        d.action = 3;
+      } else if (gr.minidx >= 0 && gr.minval <= (T)0 && ((int64_t)gr.count < st.s_max || gr.a_at_min != (T)0)) {
+        d.i = gr.minidx;
+        const T yi = (T)gr.ymin;
+        const T Fi = yi * gr.minval;          // y = +-1: y (y F) = F exactly
+        const T bi = yi > 0 ? st.beta : (T)1;  // b_i = beta^(0.5 (y_i + 1)), Eq. 5
+        d.dalpha = sub_rn(bi * yi, Fi);        // Eq. 6
+        d.action = 1;
+      } else if (gr.maxidx >= 0 && gr.maxval > (T)0) {
+        d.i = gr.maxidx;
+        d.dalpha = -gr.a_at_max;
+        d.action = 2;
+      }
+      if (d.action == 1 || d.action == 2) {
+        if (lane < W) pi_sh[lane] = st.P[d.i * (int64_t)W + lane];
+        if (me == 0 && lane == 0 && updates < st.trace_cap) {
+          st.trace_act[updates] = d.action;
+          st.trace_idx[updates] = (int32_t)d.i;
+        }
+      }
+      if constexpr (MULTI) {
+        if (lane == 0) dec = d;
+      }
     }
+    __syncthreads();  // orders the LDS writes of pi_sh (and dec) before the reads below
+    if constexpr (MULTI) d = dec;
     if (d.action != 1 && d.action != 2) {
       status = d.action == 0 ? 0 : (d.action == 3 ? 1 : -5);
       break;
     }
-    if (lane < W) pi_sh[lane] = st.P[d.i * (int64_t)W + lane];
-    if (me == 0 && lane == 0 && updates < st.trace_cap) {
-      st.trace_act[updates] = d.action;
-      st.trace_idx[updates] = (int32_t)d.i;
-    }
-    __syncthreads();  // one wave: orders the LDS writes of pi_sh before the reads below
     ++updates;
     r = rec_empty<T>();
     float pir[kReg];
@@ -700,8 +976,8 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
         point_record(r, jj[k], y[k], F[k], a[k]);
       }
     }
-    r = wave_allreduce(r);
-    __syncthreads();  // pi_sh is rewritten in the next iteration
+    if constexpr (!kKeys) r = wave_allreduce(r);
+    if constexpr (!MULTI) __syncthreads();  // pi_sh is rewritten in the next iteration
   }
 #pragma unroll
   for (int k = 0; k < PT; ++k)
@@ -709,7 +985,7 @@ __global__ void __launch_bounds__(64) k_train_wave(TrainState<T> st) {
       st.F[jj[k]] = F[k];
       st.alpha[jj[k]] = a[k];
     }
-  if (me == 0 && lane == 0) {
+  if (me == 0 && threadIdx.x == 0) {
     out[0] = updates;
     out[1] = status;
   }
@@ -755,22 +1031,64 @@ __global__ void __launch_bounds__(1024) k_compact(const T* __restrict__ alpha, i
   if (threadIdx.x == 0) *count = base;
 }
 
-template <typename T, int MM>
+template <typename T, int MM, bool MULTI>
 static const void* wave_kernel_mm(int PT) {
-  switch (PT) {
-    case 1: return reinterpret_cast<const void*>(k_train_wave<T, 1, MM>);
-    case 2: return reinterpret_cast<const void*>(k_train_wave<T, 2, MM>);
-    case 4: return reinterpret_cast<const void*>(k_train_wave<T, 4, MM>);
-    case 8: return reinterpret_cast<const void*>(k_train_wave<T, 8, MM>);
-    default: return reinterpret_cast<const void*>(k_train_wave<T, 16, MM>);
+  if constexpr (MULTI) {
+    switch (PT) {
+      case 1: return reinterpret_cast<const void*>(k_train_wave<T, 1, MM, true>);
+      case 2: return reinterpret_cast<const void*>(k_train_wave<T, 2, MM, true>);
+      default: return reinterpret_cast<const void*>(k_train_wave<T, kMultiMaxPT, MM, true>);
+    }
+  } else {
+    switch (PT) {
+      case 1: return reinterpret_cast<const void*>(k_train_wave<T, 1, MM, false>);
+      case 2: return reinterpret_cast<const void*>(k_train_wave<T, 2, MM, false>);
+      case 4: return reinterpret_cast<const void*>(k_train_wave<T, 4, MM, false>);
+      case 8: return reinterpret_cast<const void*>(k_train_wave<T, 8, MM, false>);
+      default: return reinterpret_cast<const void*>(k_train_wave<T, 16, MM, false>);
+    }
   }
 }
 
 template <typename T>
-static const void* wave_kernel(int PT, int mm) {
-  if (mm == 4) return wave_kernel_mm<T, 4>(PT);
-  if (mm == 8) return wave_kernel_mm<T, 8>(PT);
-  return wave_kernel_mm<T, 0>(PT);
+static const void* wave_kernel(int PT, int mm, bool multi) {
+  if (multi) {
+    if (mm == 4) return wave_kernel_mm<T, 4, true>(PT);
+    if (mm == 8) return wave_kernel_mm<T, 8, true>(PT);
+    return wave_kernel_mm<T, 0, true>(PT);
+  }
+  if (mm == 4) return wave_kernel_mm<T, 4, false>(PT);
+  if (mm == 8) return wave_kernel_mm<T, 8, false>(PT);
+  return wave_kernel_mm<T, 0, false>(PT);
+}
+
+// Launch shape of the wave form for one training set of N points: PT points
+// per lane, the smallest power of two that keeps the grid within `cap`
+// workgroups (at most kMultiMaxPT with several waves), and nw waves per
+// workgroup (at most 16 / PT); the control points in registers for chains of
+// 4 or 8 points (up to 4 points per lane), else in LDS
+// when the slice fits in 48 KB. Returns false when the grid exceeds the form's
+// limits or is not resident.
+template <typename T>
+static bool wave_shape(int64_t N, int M, int D, int nw, int64_t cap, int ncu, const void** kfn, int64_t* G,
+                       int64_t* chunk, size_t* lds_bytes, int* threads) {
+  const bool multi = nw > 1;
+  const int pt_max = multi ? kMultiMaxPT : 16;
+  auto waves = [&](int pt) { return multi ? (nw < 16 / pt ? nw : 16 / pt) : 1; };
+  int PT = 1;
+  while (PT < pt_max && (N + 64ll * waves(PT) * PT - 1) / (64ll * waves(PT) * PT) > cap) PT *= 2;
+  const int nt = 64 * waves(PT);
+  *chunk = (int64_t)nt * PT;
+  *G = (N + *chunk - 1) / *chunk;
+  if (*G > (int64_t)(multi ? kMultiChunks<T> : kWaveChunks) * 64) return false;
+  const int mm = (D == 3 && PT <= 4 && (M == 4 || M == 8)) ? M : 0;
+  *kfn = wave_kernel<T>(PT, mm, multi);
+  *lds_bytes = mm ? 0 : (size_t)*chunk * M * D * sizeof(float);
+  if (*lds_bytes > 48 * 1024) *lds_bytes = 0;
+  *threads = nt;
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, *kfn, nt, *lds_bytes) != hipSuccess) return false;
+  return per_cu >= 1 && *G <= (int64_t)per_cu * ncu;
 }
 
 // Host validation shared by the points and configuration forms (before any HIP call).
@@ -811,11 +1129,11 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   FASTRON_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (!coop) return fail(FASTRON_EUNSUPPORTED, "device does not support cooperative launches");
-  // Launch shape. Default: the single-wave kernel, PT points per lane with PT
-  // the smallest power of two that keeps the grid within "train.wave_groups"
-  // workgroups (at most kWaveChunks x 64 and all co-resident). Otherwise, or
-  // with "train.kernel" = 0: the multi-wave kernel, a slice per workgroup and
-  // at most one workgroup per CU, each thread holding PT points.
+  // Launch shape. Default: the wave form with "train.waves" waves per
+  // workgroup and at most "train.wave_groups" workgroups (see wave_shape),
+  // falling back to single-wave workgroups when that grid does not fit.
+  // Otherwise, or with "train.kernel" = 0: the multi-wave kernel, a slice per
+  // workgroup and at most one workgroup per CU, each thread holding PT points.
   int threads = 64;
   int64_t G = 0, chunk = 0;
   int PT = 1;
@@ -824,19 +1142,10 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   int per_cu = 0;
   if (tune_get("train.kernel") == 1) {
     const int64_t cap = tune_get("train.wave_groups");
-    while (PT < 16 && (N + 64 * PT - 1) / (64 * PT) > cap) PT *= 2;
-    chunk = 64 * (int64_t)PT;
-    G = (N + chunk - 1) / chunk;
-    if (G <= kWaveChunks * 64) {
-      // chains with 4 or 8 control points keep each lane's coordinates in
-      // registers (up to 4 points per lane)
-      const int mm = (D == 3 && PT <= 4 && (M == 4 || M == 8)) ? M : 0;
-      kfn = wave_kernel<T>(PT, mm);
-      lds_bytes = mm ? 0 : (size_t)chunk * M * D * sizeof(float);
-      if (lds_bytes > 48 * 1024) lds_bytes = 0;
-      FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, threads, lds_bytes));
-      if (per_cu < 1 || G > (int64_t)per_cu * ncu) kfn = nullptr;
-    }
+    const int nw = (int)tune_get("train.waves");
+    if (!wave_shape<T>(N, M, D, nw, cap, ncu, &kfn, &G, &chunk, &lds_bytes, &threads) &&
+        (nw == 1 || !wave_shape<T>(N, M, D, 1, cap, ncu, &kfn, &G, &chunk, &lds_bytes, &threads)))
+      kfn = nullptr;
   }
   if (kfn == nullptr) {
     threads = (int)tune_get("train.threads");
@@ -894,6 +1203,7 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
     st.D = D;
     st.chunk = (int)chunk;
     st.timeout = 400000000ll;  // 4 s at 100 MHz
+    st.poll_delay = (int)tune_get("train.poll_delay");
     st.p_in_lds = lds_bytes > 0 ? 1 : 0;
     st.env_of = nullptr;
     st.env_wg0 = nullptr;
@@ -964,7 +1274,7 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
     if (largest > cap && PT < 16) continue;
     if (largest > kWaveChunks * 64) continue;
     const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
-    kfn = wave_kernel<float>(PT, mm);
+    kfn = wave_kernel<float>(PT, mm, false);
     lds_bytes = mm ? 0 : (size_t)64 * PT * 3 * M * sizeof(float);
     if (lds_bytes > 48 * 1024) lds_bytes = 0;
     int per_cu = 0;
@@ -1022,6 +1332,7 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
     st.D = 3;
     st.chunk = (int)chunk;
     st.timeout = 400000000ll;  // 4 s at 100 MHz
+    st.poll_delay = (int)tune_get("train.poll_delay");
     st.p_in_lds = lds_bytes > 0 ? 1 : 0;
     st.env_of = d_env_of;
     st.env_wg0 = d_env_wg0;

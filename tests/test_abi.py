@@ -62,6 +62,15 @@ def test_host_only_entry_points(lib):
     assert lib.fastron_tune_set(b"no.such.key", 1) == nat.FASTRON_EINVAL
     assert "no.such.key" in nat.last_error()
     assert lib.fastron_tune_set(b"train.threads", 300) == nat.FASTRON_EINVAL
+    # wave form of Algorithm 1: waves per workgroup (power of two up to 16), first-poll delay (-1 adaptive)
+    assert lib.fastron_tune_get(b"train.waves") == 8
+    assert lib.fastron_tune_get(b"train.poll_delay") == -1
+    assert lib.fastron_tune_set(b"train.waves", 6) == nat.FASTRON_EINVAL
+    assert lib.fastron_tune_set(b"train.waves", 32) == nat.FASTRON_EINVAL
+    assert lib.fastron_tune_set(b"train.poll_delay", -2) == nat.FASTRON_EINVAL
+    assert lib.fastron_tune_set(b"train.poll_delay", 65) == nat.FASTRON_EINVAL
+    assert lib.fastron_tune_set(b"train.poll_delay", 12) == nat.FASTRON_OK
+    assert lib.fastron_tune_set(b"train.poll_delay", -1) == nat.FASTRON_OK
     assert lib.fastron_model_bytes(-1, 8) == -1
     assert lib.fastron_model_bytes(4000, 17) == -1
     assert lib.fastron_model_bytes(4000, 8) > 4000 * 8 * 4

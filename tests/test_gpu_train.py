@@ -49,15 +49,43 @@ def test_gram_update_parity(oracle_mod, dev):
     np.testing.assert_allclose(F.cpu().numpy(), F0 - 0.75 * ref, atol=2e-6)
 
 
+TRAIN_KEYS = ("train.kernel", "train.waves", "train.wave_groups", "train.poll_delay")
+
+
+class launch_shape:
+    """Sets the Algorithm 1 launch knobs for a block and restores them afterwards."""
+
+    def __init__(self, **kw):
+        self.kw = {k.replace("_", ".", 1): v for k, v in kw.items()}
+
+    def __enter__(self):
+        self.saved = {k: api.tune_get(k) for k in TRAIN_KEYS}
+        for k, v in self.kw.items():
+            api.tune_set(k, v)
+
+    def __exit__(self, *exc):
+        for k, v in self.saved.items():
+            api.tune_set(k, v)
+
+
+# (waves per workgroup, workgroup cap): the default multi-wave shape, single-wave workgroups with 1 and with
+# 16 points per lane (the latter with the coordinates outside registers), and several waves with 4 points
+# per lane
+SHAPES = [(8, 128), (1, 256), (1, 2), (16, 1)]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"waves{s[0]}-cap{s[1]}")
 @pytest.mark.parametrize("beta", [1.0, 2.0])
-def test_train_fp64_step_exact(oracle_mod, dev, beta):
-    """3-DOF arm, 2,000 labelled configurations, gamma = 10: FP64 device trajectory == oracle trajectory."""
+def test_train_fp64_step_exact(oracle_mod, dev, beta, shape):
+    """3-DOF arm, 2,000 labelled configurations, gamma = 10: FP64 device trajectory == oracle trajectory, in
+    every launch shape of the wave form."""
     arm = wl.arm_3dof()
     q, P32, y = labelled_set(oracle_mod, arm, "train3", 2000, 5, 0.15)
     ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 10.0, beta=beta, trace=True)
-    announce(f"train_f64 3dof N=2000 beta={beta}")
-    out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, beta=beta, fp64=True,
-                    trace_cap=ref["updates"] + 10)
+    announce(f"train_f64 3dof N=2000 beta={beta} waves={shape[0]} cap={shape[1]}")
+    with launch_shape(train_waves=shape[0], train_wave_groups=shape[1]):
+        out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 10.0, beta=beta,
+                               fp64=True, trace_cap=ref["updates"] + 10)
     assert out["converged"] == ref["converged"]
     assert out["updates"] == ref["updates"]
     np.testing.assert_array_equal(out["trace_action"].cpu().numpy(), ref["trace_action"])
@@ -65,6 +93,31 @@ def test_train_fp64_step_exact(oracle_mod, dev, beta):
     np.testing.assert_array_equal(out["alpha"].cpu().numpy(), ref["alpha"])
     np.testing.assert_array_equal(out["F"].cpu().numpy(), ref["F"])
     np.testing.assert_array_equal(out["support"].cpu().numpy(), ref["support"])
+
+
+def test_train_fp32_every_launch_shape_agrees(oracle_mod, dev):
+    """7-DOF arm, 5,000 labelled configurations: every launch shape of the wave form (single-wave and
+    multi-wave workgroups, 1 to 16 points per lane, coordinates in registers or not), every first-poll
+    delay and the multi-wave slice kernel give bit-identical weights and scores: the record reductions are
+    exact (min / max with the lowest index on ties, integer counts) and each point's score is updated in
+    the same order whatever the shape."""
+    arm = wl.arm_7dof()
+    q, P32, y = labelled_set(oracle_mod, arm, "train7s", 5000, 20, 0.1, 0.25)
+    P, yd = torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev)
+    runs = {}
+    for kernel, waves, cap, delay in [(1, 8, 128, -1), (1, 8, 128, 0), (1, 8, 128, 12), (1, 1, 256, -1),
+                                      (1, 1, 2, -1), (1, 4, 128, -1), (1, 16, 1, -1), (1, 2, 16, -1),
+                                      (0, 8, 128, -1)]:
+        announce(f"train fp32 7dof N=5000 kernel={kernel} waves={waves} cap={cap} delay={delay}")
+        with launch_shape(train_kernel=kernel, train_waves=waves, train_wave_groups=cap, train_poll_delay=delay):
+            out = api.train_points(P, yd, 10.0)
+        runs[(kernel, waves, cap, delay)] = out
+    first = runs[(1, 8, 128, -1)]
+    assert first["converged"]
+    for key, out in runs.items():
+        assert out["updates"] == first["updates"], key
+        assert torch.equal(out["alpha"], first["alpha"]), key
+        assert torch.equal(out["F"], first["F"]), key
 
 
 def test_train_fp64_warm_start_and_caps(oracle_mod, dev):
