@@ -1230,9 +1230,9 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   return rs;
 }
 
-// Several independent training sets in one cooperative launch of the
-// single-wave kernel: set e gets ceil(N_e / (64 PT)) workgroups, its own
-// records and its own exchange, so the sets advance concurrently.
+// Several independent training sets in one cooperative launch of the wave
+// form: set e gets ceil(N_e / chunk) workgroups, its own records and its own
+// exchange, so the sets advance concurrently.
 static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t E, const int64_t* offsets, int32_t M,
                                        float gamma, float beta, int64_t iter_max, int64_t s_max, float* alpha, float* F,
                                        int32_t* support_idx, int64_t* n_support, int64_t* updates, void* stream) {
@@ -1257,34 +1257,45 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
   FASTRON_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
   FASTRON_HIP(hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev));
   if (!coop) return fail(FASTRON_EUNSUPPORTED, "device does not support cooperative launches");
-  // smallest PT whose grid fits the cap per set and the resident capacity in total
+  // Launch shape: the smallest PT whose grid fits the cap per set and the
+  // resident capacity in total, first with "train.waves" waves per workgroup
+  // (at most 16 / PT, PT <= kMultiMaxPT), then with single-wave workgroups.
   const int64_t cap = tune_get("train.wave_groups");
-  int PT = 1;
+  const int nw_tune = (int)tune_get("train.waves");
+  int PT = 1, threads = 64;
   const void* kfn = nullptr;
   int64_t G = 0;
   size_t lds_bytes = 0;
-  for (;; PT *= 2) {
-    if (PT > 16) return fail(FASTRON_EUNSUPPORTED, "training sets too large for one resident launch");
-    int64_t total = 0, largest = 0;
-    for (int e = 0; e < E; ++e) {
-      const int64_t ge = (offsets[e + 1] - offsets[e] + 64 * PT - 1) / (64 * PT);
-      total += ge;
-      largest = ge > largest ? ge : largest;
-    }
-    if (largest > cap && PT < 16) continue;
-    if (largest > kWaveChunks * 64) continue;
-    const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
-    kfn = wave_kernel<float>(PT, mm, false);
-    lds_bytes = mm ? 0 : (size_t)64 * PT * 3 * M * sizeof(float);
-    if (lds_bytes > 48 * 1024) lds_bytes = 0;
-    int per_cu = 0;
-    FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, 64, lds_bytes));
-    if (per_cu >= 1 && total <= (int64_t)per_cu * ncu) {
-      G = total;
-      break;
+  for (int multi = nw_tune > 1 ? 1 : 0; multi >= 0 && kfn == nullptr; --multi) {
+    const int pt_max = multi ? kMultiMaxPT : 16;
+    for (PT = 1; PT <= pt_max; PT *= 2) {
+      const int nw = multi ? (nw_tune < 16 / PT ? nw_tune : 16 / PT) : 1;
+      const int64_t chunk_try = 64ll * nw * PT;
+      int64_t total = 0, largest = 0;
+      for (int e = 0; e < E; ++e) {
+        const int64_t ge = (offsets[e + 1] - offsets[e] + chunk_try - 1) / chunk_try;
+        total += ge;
+        largest = ge > largest ? ge : largest;
+      }
+      if (largest > cap && PT < pt_max) continue;
+      if (largest > (int64_t)(multi ? kMultiChunks<float> : kWaveChunks) * 64) continue;
+      const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
+      const void* fn = wave_kernel<float>(PT, mm, multi == 1);
+      size_t lds = mm ? 0 : (size_t)chunk_try * 3 * M * sizeof(float);
+      if (lds > 48 * 1024) lds = 0;
+      int per_cu = 0;
+      FASTRON_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 64 * nw, lds));
+      if (per_cu >= 1 && total <= (int64_t)per_cu * ncu) {
+        kfn = fn;
+        G = total;
+        lds_bytes = lds;
+        threads = 64 * nw;
+        break;
+      }
     }
   }
-  const int64_t chunk = 64 * (int64_t)PT;
+  if (kfn == nullptr) return fail(FASTRON_EUNSUPPORTED, "training sets too large for one resident launch");
+  const int64_t chunk = (int64_t)threads * PT;
   std::vector<int32_t> env_of((size_t)G), env_wg0((size_t)E + 1);
   env_wg0[0] = 0;
   for (int e = 0; e < E; ++e) {
@@ -1338,7 +1349,7 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
     st.env_wg0 = d_env_wg0;
     st.env_off = d_env_off;
     void* args[] = {&st};
-    e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3(64), args, lds_bytes, s);
+    e = hipLaunchCooperativeKernel(kfn, dim3((unsigned)G), dim3((unsigned)threads), args, lds_bytes, s);
   }
   for (int k = 0; k < E && e == hipSuccess; ++k) {
     hipLaunchKernelGGL(k_compact<float>, dim3(1), dim3(1024), 0, s, alpha + offsets[k], offsets[k + 1] - offsets[k],
