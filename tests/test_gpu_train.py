@@ -95,6 +95,26 @@ def test_train_fp64_step_exact(oracle_mod, dev, beta, shape):
     np.testing.assert_array_equal(out["support"].cpu().numpy(), ref["support"])
 
 
+@pytest.mark.parametrize("shape", [(8, 128), (1, 256), (4, 2)], ids=lambda s: f"waves{s[0]}-cap{s[1]}")
+def test_train_fp64_step_exact_7dof(oracle_mod, dev, shape):
+    """7-DOF arm (8 control points, kept in registers by the kernel), 2,500 labelled configurations, 20 cubes,
+    gamma = 30: the FP64 device trajectory equals the oracle's in the default multi-wave shape (1 point per
+    lane), with single-wave workgroups and with 4 waves of 4 points per lane."""
+    arm = wl.arm_7dof()
+    q, P32, y = labelled_set(oracle_mod, arm, "train7x", 2500, 20, 0.1, 0.25)
+    ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 30.0, trace=True)
+    announce(f"train_f64 7dof N=2500 waves={shape[0]} cap={shape[1]}")
+    with launch_shape(train_waves=shape[0], train_wave_groups=shape[1]):
+        out = api.train_points(torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev), 30.0, fp64=True,
+                               trace_cap=ref["updates"] + 10)
+    assert out["converged"] == ref["converged"]
+    assert out["updates"] == ref["updates"]
+    np.testing.assert_array_equal(out["trace_action"].cpu().numpy(), ref["trace_action"])
+    np.testing.assert_array_equal(out["trace_index"].cpu().numpy(), ref["trace_index"])
+    np.testing.assert_array_equal(out["alpha"].cpu().numpy(), ref["alpha"])
+    np.testing.assert_array_equal(out["F"].cpu().numpy(), ref["F"])
+
+
 def test_train_fp32_every_launch_shape_agrees(oracle_mod, dev):
     """7-DOF arm, 5,000 labelled configurations: every launch shape of the wave form (single-wave and
     multi-wave workgroups, 1 to 16 points per lane, coordinates in registers or not), every first-poll
