@@ -132,6 +132,30 @@ bool rational_sum_ok(const ChainArgs& c, float gamma, double t_limit) {
 // on its own row in LDS. Dynamic LDS: 256 (n + 3M) floats (at most 64 KB).
 // Serves chains below 7 joints (FP32 chain); longer chains run
 // k_fk_points_fixed below.
+// Block copies between global memory and LDS for the FK kernels: 16 bytes per
+// lane when both ends are 16-byte aligned (a block's rows start at a multiple
+// of 256 rows, so they are whenever the caller's buffer is), else 4.
+__device__ __forceinline__ void copy_in(float* __restrict__ dst, const float* __restrict__ src, int count) {
+  if ((((uintptr_t)src) & 15) == 0) {
+    const int n4 = count >> 2;
+    for (int e = threadIdx.x; e < n4; e += 256)
+      reinterpret_cast<float4*>(dst)[e] = reinterpret_cast<const float4*>(src)[e];
+    for (int e = 4 * n4 + threadIdx.x; e < count; e += 256) dst[e] = src[e];
+  } else {
+    for (int e = threadIdx.x; e < count; e += 256) dst[e] = src[e];
+  }
+}
+__device__ __forceinline__ void copy_out(float* __restrict__ dst, const float* __restrict__ src, int count) {
+  if ((((uintptr_t)dst) & 15) == 0) {
+    const int n4 = count >> 2;
+    for (int e = threadIdx.x; e < n4; e += 256)
+      reinterpret_cast<float4*>(dst)[e] = reinterpret_cast<const float4*>(src)[e];
+    for (int e = 4 * n4 + threadIdx.x; e < count; e += 256) dst[e] = src[e];
+  } else {
+    for (int e = threadIdx.x; e < count; e += 256) dst[e] = src[e];
+  }
+}
+
 template <typename R>
 __global__ void __launch_bounds__(256) k_fk_points(ChainArgs c, const float* __restrict__ q, int64_t N,
                                                     float* __restrict__ P) {
@@ -141,7 +165,7 @@ __global__ void __launch_bounds__(256) k_fk_points(ChainArgs c, const float* __r
   float* ps = rows + 256 * n;    // [256][w]
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int nrow = (int)(N - j0 < 256 ? N - j0 : 256);
-  for (int e = threadIdx.x; e < nrow * n; e += 256) qs[e] = q[j0 * n + e];
+  copy_in(qs, q + j0 * n, nrow * n);
   __syncthreads();
   if ((int)threadIdx.x < nrow) {
     float qv[FASTRON_MAX_JOINTS];
@@ -156,7 +180,7 @@ __global__ void __launch_bounds__(256) k_fk_points(ChainArgs c, const float* __r
     });
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nrow * w; e += 256) P[j0 * w + e] = ps[e];
+  copy_out(P + j0 * w, ps, nrow * w);
 }
 
 // ---------------------------------------------------------------------------
@@ -408,7 +432,7 @@ __global__ void __launch_bounds__(256) k_fk_points_fixed(ChainArgs c, const floa
   float* ps = rows + 256 * NJ;   // [256][w]
   const int64_t j0 = (int64_t)blockIdx.x * 256;
   const int nrow = (int)(N - j0 < 256 ? N - j0 : 256);
-  for (int e = threadIdx.x; e < nrow * NJ; e += 256) qs[e] = q[j0 * NJ + e];
+  copy_in(qs, q + j0 * NJ, nrow * NJ);
   __syncthreads();
   if ((int)threadIdx.x < nrow) {
     double st[NJ], ct[NJ], dd[NJ];
@@ -464,7 +488,7 @@ __global__ void __launch_bounds__(256) k_fk_points_fixed(ChainArgs c, const floa
     }
   }
   __syncthreads();
-  for (int e = threadIdx.x; e < nrow * w; e += 256) P[j0 * w + e] = ps[e];
+  copy_out(P + j0 * w, ps, nrow * w);
 }
 
 }  // namespace fastron
