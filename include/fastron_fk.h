@@ -421,13 +421,14 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *                       no barrier inside the exchange); 0: the slice kernel
  *                       (also used when the wave form's grid would exceed
  *                       its limits)
- *   "train.waves"       waves per workgroup of the wave form: 1, 2, 4, 8
- *                       (default) or 16; with p points per lane at most
- *                       16 / p (single-wave workgroups take over when the
- *                       multi-wave grid would exceed 256 workgroups, 128 in
- *                       FP64)
- *   "train.wave_groups" grid cap of the wave form, 1..512 (128): the points
- *                       per lane double until the grid fits
+ *   "train.waves"       waves per workgroup the wave form starts from: 1, 2,
+ *                       4, 8 (default) or 16; 1 keeps single-wave workgroups
+ *                       (which also take over when the multi-wave grid would
+ *                       exceed 256 workgroups, 128 in FP64)
+ *   "train.wave_groups" grid cap of the wave form, 1..512 (64): the waves per
+ *                       workgroup double up to 16 (single-wave workgroups:
+ *                       the points per lane double up to 16) while the grid
+ *                       exceeds it
  *   "train.poll_delay"  sleeps of 64 clocks before the first poll of each
  *                       record exchange, 0..64, or -1 (default): adapted by
  *                       each workgroup to how often its first poll came too

@@ -22,7 +22,7 @@ std::unordered_map<std::string, Knob>& table() {
       {"train.blocks", {0, 0, 4096, false}},    // 0 = automatic
       {"train.threads", {512, 256, 1024, true}},
       {"train.kernel", {1, 0, 1, false}},         // 1 = the wave form, 0 = the multi-wave slice kernel
-      {"train.wave_groups", {128, 1, 512, false}},  // grid cap of the wave form
+      {"train.wave_groups", {64, 1, 512, false}},   // grid cap of the wave form
       {"train.waves", {8, 1, 16, true}},            // waves per workgroup of the wave form
       {"train.poll_delay", {-1, -1, 64, false}},    // sleeps before an exchange's first poll, -1 = adaptive
       {"score.rational", {1, 0, 1, false}},        // 1 = running-fraction sum where the reach bound allows it

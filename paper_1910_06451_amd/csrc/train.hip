@@ -727,7 +727,7 @@ constexpr int kWaveChunks = 8;
 constexpr int kMaxPollDelay = 64;  // sleeps before the first poll (about 2 us)
 template <typename T>
 constexpr int kMultiChunks = sizeof(T) == 4 ? 4 : 2;  // FP64 records take twice the registers
-constexpr int kMultiMaxPT = 4;  // points per lane of the multi-wave form (register budget at 1024 threads)
+constexpr int kMultiMaxPT = 4;  // points per lane of multi-wave workgroups in multi-set launches (FP32)
 
 // MM > 0: the chain has exactly MM control points and every lane keeps its
 // points' coordinates in registers for the whole run; MM = 0: any M, the
@@ -1033,7 +1033,9 @@ __global__ void __launch_bounds__(1024) k_compact(const T* __restrict__ alpha, i
 
 template <typename T, int MM, bool MULTI>
 static const void* wave_kernel_mm(int PT) {
-  if constexpr (MULTI) {
+  if constexpr (MULTI && sizeof(T) == 8) {
+    return reinterpret_cast<const void*>(k_train_wave<T, 1, MM, true>);  // FP64: one point per lane only
+  } else if constexpr (MULTI) {
     switch (PT) {
       case 1: return reinterpret_cast<const void*>(k_train_wave<T, 1, MM, true>);
       case 2: return reinterpret_cast<const void*>(k_train_wave<T, 2, MM, true>);
@@ -1062,22 +1064,28 @@ static const void* wave_kernel(int PT, int mm, bool multi) {
   return wave_kernel_mm<T, 0, false>(PT);
 }
 
-// Launch shape of the wave form for one training set of N points: PT points
-// per lane, the smallest power of two that keeps the grid within `cap`
-// workgroups (at most kMultiMaxPT with several waves), and nw waves per
-// workgroup (at most 16 / PT); the control points in registers for chains of
-// 4 or 8 points (up to 4 points per lane), else in LDS
-// when the slice fits in 48 KB. Returns false when the grid exceeds the form's
-// limits or is not resident.
+// Launch shape of the wave form for one training set of N points. Several
+// waves per workgroup (nw > 1): one point per lane, the waves doubling from nw
+// up to 16 while the grid exceeds `cap` workgroups (more waves spread a
+// workgroup's column over its CU's SIMDs; a workgroup holds at most 1,024
+// points in this form whatever the split between waves and points per lane,
+// so more points per lane would only lengthen every wave's column). Single-wave
+// workgroups (nw = 1): PT points per lane, doubling up to 16 while the grid
+// exceeds `cap`. Control points in registers for chains of 4 or 8 points (up
+// to 4 points per lane), else in LDS when the slice fits in 48 KB. Returns
+// false when the grid exceeds the form's limits or is not resident.
 template <typename T>
 static bool wave_shape(int64_t N, int M, int D, int nw, int64_t cap, int ncu, const void** kfn, int64_t* G,
                        int64_t* chunk, size_t* lds_bytes, int* threads) {
   const bool multi = nw > 1;
-  const int pt_max = multi ? kMultiMaxPT : 16;
-  auto waves = [&](int pt) { return multi ? (nw < 16 / pt ? nw : 16 / pt) : 1; };
-  int PT = 1;
-  while (PT < pt_max && (N + 64ll * waves(PT) * PT - 1) / (64ll * waves(PT) * PT) > cap) PT *= 2;
-  const int nt = 64 * waves(PT);
+  auto groups = [&](int w, int pt) { return (N + 64ll * w * pt - 1) / (64ll * w * pt); };
+  int PT = 1, waves = multi ? nw : 1;
+  if (multi) {
+    while (waves < 16 && groups(waves, PT) > cap) waves *= 2;
+  } else {
+    while (PT < 16 && groups(waves, PT) > cap) PT *= 2;
+  }
+  const int nt = 64 * waves;
   *chunk = (int64_t)nt * PT;
   *G = (N + *chunk - 1) / *chunk;
   if (*G > (int64_t)(multi ? kMultiChunks<T> : kWaveChunks) * 64) return false;

@@ -68,10 +68,9 @@ class launch_shape:
             api.tune_set(k, v)
 
 
-# (waves per workgroup, workgroup cap): the default multi-wave shape, single-wave workgroups with 1 and with
-# 16 points per lane (the latter with the coordinates outside registers), and several waves with 4 points
-# per lane
-SHAPES = [(8, 128), (1, 256), (1, 2), (16, 1)]
+# (waves per workgroup, workgroup cap): the default multi-wave shape (8 waves), single-wave workgroups with 1
+# and with 16 points per lane (the latter with the coordinates outside registers), and 16 waves
+SHAPES = [(8, 64), (1, 256), (1, 2), (16, 1)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"waves{s[0]}-cap{s[1]}")
@@ -95,11 +94,11 @@ def test_train_fp64_step_exact(oracle_mod, dev, beta, shape):
     np.testing.assert_array_equal(out["support"].cpu().numpy(), ref["support"])
 
 
-@pytest.mark.parametrize("shape", [(8, 128), (1, 256), (4, 2)], ids=lambda s: f"waves{s[0]}-cap{s[1]}")
+@pytest.mark.parametrize("shape", [(8, 64), (1, 256), (4, 2)], ids=lambda s: f"waves{s[0]}-cap{s[1]}")
 def test_train_fp64_step_exact_7dof(oracle_mod, dev, shape):
     """7-DOF arm (8 control points, kept in registers by the kernel), 2,500 labelled configurations, 20 cubes,
-    gamma = 30: the FP64 device trajectory equals the oracle's in the default multi-wave shape (1 point per
-    lane), with single-wave workgroups and with 4 waves of 4 points per lane."""
+    gamma = 30: the FP64 device trajectory equals the oracle's in the default multi-wave shape, with
+    single-wave workgroups, and with waves grown from 4 to 16 by a small grid cap."""
     arm = wl.arm_7dof()
     q, P32, y = labelled_set(oracle_mod, arm, "train7x", 2500, 20, 0.1, 0.25)
     ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 30.0, trace=True)
@@ -116,23 +115,25 @@ def test_train_fp64_step_exact_7dof(oracle_mod, dev, shape):
 
 
 def test_train_fp32_every_launch_shape_agrees(oracle_mod, dev):
-    """7-DOF arm, 5,000 labelled configurations: every launch shape of the wave form (single-wave and
-    multi-wave workgroups, 1 to 16 points per lane, coordinates in registers or not), every first-poll
-    delay and the multi-wave slice kernel give bit-identical weights and scores: the record reductions are
+    """7-DOF arm, 5,000 labelled configurations: every launch shape of the wave form (single-wave workgroups
+    with 1 to 16 points per lane, coordinates in registers or not, and 2 to 16 waves per workgroup), every
+    first-poll delay and the slice kernel give bit-identical weights and scores: the record reductions are
     exact (min / max with the lowest index on ties, integer counts) and each point's score is updated in
     the same order whatever the shape."""
     arm = wl.arm_7dof()
     q, P32, y = labelled_set(oracle_mod, arm, "train7s", 5000, 20, 0.1, 0.25)
     P, yd = torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev)
     runs = {}
-    for kernel, waves, cap, delay in [(1, 8, 128, -1), (1, 8, 128, 0), (1, 8, 128, 12), (1, 1, 256, -1),
-                                      (1, 1, 2, -1), (1, 4, 128, -1), (1, 16, 1, -1), (1, 2, 16, -1),
-                                      (0, 8, 128, -1)]:
+    # (kernel, waves, cap, delay): 8 waves (default and fixed delays), single-wave workgroups with 2 and 16
+    # points per lane, 4 and 2 waves, waves grown to 16 by a small cap, and the slice kernel
+    for kernel, waves, cap, delay in [(1, 8, 64, -1), (1, 8, 64, 0), (1, 8, 64, 12), (1, 1, 64, -1),
+                                      (1, 1, 2, -1), (1, 4, 128, -1), (1, 2, 64, -1), (1, 4, 3, -1),
+                                      (0, 8, 64, -1)]:
         announce(f"train fp32 7dof N=5000 kernel={kernel} waves={waves} cap={cap} delay={delay}")
         with launch_shape(train_kernel=kernel, train_waves=waves, train_wave_groups=cap, train_poll_delay=delay):
             out = api.train_points(P, yd, 10.0)
         runs[(kernel, waves, cap, delay)] = out
-    first = runs[(1, 8, 128, -1)]
+    first = runs[(1, 8, 64, -1)]
     assert first["converged"]
     for key, out in runs.items():
         assert out["updates"] == first["updates"], key
@@ -312,6 +313,12 @@ def test_train_batch_matches_single_sets(oracle_mod, dev):
             F_oracle = oracle_mod.score_points(P64[sup], a[sup].astype(np.float64), 30.0, P64)
             assert_claim2(yy[sl], F_oracle, b["F"][sl].cpu().numpy())
     assert b0["converged"] and b1["converged"]
+    # 4 waves x 4 points per lane (a grid cap of 2 per set) end bit-identical to the default shape
+    announce("train_batch: 5 sets, 4 waves x 4 points per lane")
+    with launch_shape(train_waves=4, train_wave_groups=2):
+        b2 = api.train_batch(P, Y0, off, 30.0, iter_max=iters, s_max=4000)
+    assert torch.equal(b2["alpha"], b0["alpha"]) and torch.equal(b2["F"], b0["F"])
+    assert list(b2["updates"]) == list(b0["updates"])
 
 
 def test_configuration_forms_match_points_forms(oracle_mod, dev):
