@@ -443,8 +443,8 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *                       reciprocal per value always. The two agree to FP32
  *                       rounding.
  *   "score.bf16_blocks" query blocks of 16 whose BF16 operands the BF16 score
- *                       kernel keeps resident per pass: 4 (default) or 2
- *                       (fewer registers, more waves; same results)
+ *                       kernel keeps resident per pass: 2 (default: fewer
+ *                       registers, 3 waves per SIMD) or 4 (same results)
  *   "batch.shape_cache" 1 (default): fastron_batch_autotune reuses a shape
  *                       tuned earlier in the process for a batch of the same
  *                       kind; 0: it times the candidates on every call

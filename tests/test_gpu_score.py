@@ -280,7 +280,7 @@ def test_bf16_resident_blocks_setting(dev):
             announce(f"bf16 split3 score.bf16_blocks={qb}")
             out[qb] = api.fk_score_prepared(arm, model, q_d, flags=api.SCORE_BF16 | api.BF16_SPLIT3)
     finally:
-        api.tune_set("score.bf16_blocks", 4)
+        api.tune_set("score.bf16_blocks", 2)
     assert torch.equal(out[2][0], out[4][0]) and torch.equal(out[2][1], out[4][1])
 
 
