@@ -13,10 +13,10 @@
 //   1. publishes one record for its slice (min margin and its index, the
 //      weight at that index, max of y(F - alpha) over alpha != 0 and its
 //      index and weight, and its count of nonzero weights), every word tagged
-//      with the iteration's sequence number;
+//      with the low byte of the iteration number;
 //   2. waits until it has read every workgroup's record of this iteration
 //      (no central barrier: a record is complete when all its words carry the
-//      current sequence number);
+//      current tag);
 //   3. reduces all records itself (identically in every workgroup, so every
 //      workgroup takes the same decision without a second exchange);
 //   4. applies the add or the removal to its slice in one pass that also
@@ -70,7 +70,7 @@ struct TrainState {
   long long timeout;    // wait limit for the record exchange, in constant-clock ticks
   int poll_delay;       // wave form: sleeps (64 clocks each) before the first poll; -1 = adaptive
   int p_in_lds;         // the slice's control points are staged in LDS
-  // several independent training sets in one launch (single-wave kernel only):
+  // several independent training sets in one launch (wave form only):
   // workgroup w trains set env_of[w], whose workgroups are env_wg0[e] ..
   // env_wg0[e + 1] - 1, whose points are env_off[e] .. env_off[e + 1] - 1, and
   // whose (updates, status) go to out[2 e], out[2 e + 1]. NULL: one set.
@@ -1140,7 +1140,7 @@ static fastron_status train_impl(const float* P, const int8_t* y, int64_t N, int
   // Launch shape. Default: the wave form with "train.waves" waves per
   // workgroup and at most "train.wave_groups" workgroups (see wave_shape),
   // falling back to single-wave workgroups when that grid does not fit.
-  // Otherwise, or with "train.kernel" = 0: the multi-wave kernel, a slice per
+  // Otherwise, or with "train.kernel" = 0: the slice kernel, a slice per
   // workgroup and at most one workgroup per CU, each thread holding PT points.
   int threads = 64;
   int64_t G = 0, chunk = 0;
