@@ -604,15 +604,21 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
 // ---------------------------------------------------------------------------
 // Training step for the 3M (<= 32) -> 256 -> 256 -> 1 network: three kernels
 // per batch instead of the staged GEMM sequence.
-//   k_train_rows   one wave per 16 batch rows: standardised BF16 inputs,
-//                  layer 1 and layer 2 in transposed form (hidden units as
-//                  MFMA rows, batch rows as columns, as in the screening
-//                  kernel), head, loss, dZ2 = [Z2 > 0] dz w3, then
-//                  dH1^T = W2 dZ2^T and dZ1 = [Z1 > 0] dH1 without leaving
-//                  registers; writes X, H1, dZ2 and dZ1 unit-major (each
-//                  unit's batch rows contiguous) for the weight gradients,
-//                  and per-workgroup sums over its rows for the bias and head
-//                  gradients and the loss.
+//   k_train_rows   per 16 batch rows, four waves that each own a quarter of
+//                  the hidden units: standardised BF16 inputs, layer 1 (all
+//                  units: the operand of layer 2) and layer 2 (own units) in
+//                  transposed form (hidden units as MFMA rows, batch rows as
+//                  columns, as in the screening kernel), the head's partial
+//                  sums over own units (added in LDS in a fixed order), loss,
+//                  dZ2 = [Z2 > 0] dz w3 (own units, shared through LDS), then
+//                  dH1^T = W2 dZ2^T and dZ1 = [Z1 > 0] dH1 for own units;
+//                  writes X, H1, dZ2 and dZ1 unit-major (each unit's batch
+//                  rows contiguous) for the weight gradients, and
+//                  per-workgroup sums over its rows for the bias and head
+//                  gradients and the loss. Splitting the units fills the
+//                  part with a batch of 8,192 rows: 256 workgroups of 8 waves
+//                  (two 16-row blocks), all sharing one staged copy of the
+//                  W2 operands, instead of one wave per 16 rows.
 //   k_train_wgrad  gW2 = H1^T dZ2 and gW1 = X^T dZ1, contracting over the
 //                  batch rows in split-K slices (one partial per slice).
 //   k_train_adam   sums the partials in a fixed order, applies Adam to the
@@ -626,8 +632,13 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
 // ---------------------------------------------------------------------------
 constexpr int kTrH = 256;        // hidden width of the training kernels
 constexpr int kTrIn = 32;        // input features, zero-padded
-constexpr int kTrWaves = 4;      // waves (16-row blocks) per workgroup of k_train_rows
-constexpr int kTrRows = 16 * kTrWaves;
+constexpr int kTrBlocks = 2;     // 16-row blocks per workgroup of k_train_rows
+constexpr int kTrSlices = 4;     // hidden-unit slices per block (one wave each)
+constexpr int kTrWaves = kTrBlocks * kTrSlices;
+constexpr int kTrThreads = 64 * kTrWaves;
+constexpr int kTrRows = 16 * kTrBlocks;
+constexpr int kTrSliceV = 16 / kTrSlices;  // layer fragments (16 units each) per slice
+constexpr int kTrSliceC = 8 / kTrSlices;   // chunks of 32 units per slice
 constexpr int kTrVec = 3 * kTrH + 2;  // per-workgroup sums: gb1, gb2, gw3, gb3, loss
 constexpr int kTrSplitsMax = 32;      // split-K slices of the weight-gradient kernel
 
@@ -659,29 +670,30 @@ __device__ __forceinline__ float rows_sum(float v) {
   return dpp_add(v, 3);
 }
 
-// Writes a wave's 16 batch rows x 256 units of BF16 values (lane (g, col)
-// holding units 32 c + 8 g .. + 7 of row col in u4m v[c]) unit-major to
-// T[unit][row0 + row] through the wave's LDS area `st` ([unit][24] halfwords:
-// 16 rows and a pad that spreads the four lane groups over the banks), so
-// that each lane stores 16 bytes (8 rows of one unit) at a time.
+// Writes a wave's 16 batch rows x 64 units (units 64 us .. + 63) of BF16
+// values (lane (g, col) holding units 64 us + 32 cc + 8 g .. + 7 of row col in
+// u4m v[cc]) unit-major to T[unit][row0 + row] through the wave's LDS area
+// `st` ([unit][24] halfwords: 16 rows and a pad that spreads the four lane
+// groups over the banks), so that each lane stores 16 bytes (8 rows of one
+// unit) at a time.
 constexpr int kTrStageStride = 24;
-static_assert(kTrWaves * kTrH * kTrStageStride <= kTrH * kTrH, "the store staging areas fit the operand area");
-__device__ __forceinline__ void store_unit_major(const u4m* v, uint16_t* st, uint16_t* __restrict__ T, int64_t ldT,
-                                                 int64_t row0, int lane) {
+__device__ __forceinline__ void store_unit_major(const u4m* v, int us, uint16_t* st, uint16_t* __restrict__ T,
+                                                 int64_t ldT, int64_t row0, int lane) {
   const int g = lane >> 4, col = lane & 15;
 #pragma unroll
-  for (int c = 0; c < 8; ++c)
+  for (int cc = 0; cc < kTrSliceC; ++cc)
 #pragma unroll
-    for (int j = 0; j < 8; ++j) st[(32 * c + 8 * g + j) * kTrStageStride + col] = bf16_at(v[c], j);
+    for (int j = 0; j < 8; ++j) st[(32 * cc + 8 * g + j) * kTrStageStride + col] = bf16_at(v[cc], j);
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  constexpr int kUnits = kTrH / kTrSlices;
 #pragma unroll
-  for (int q = 0; q < 8; ++q) {
-    const int chunk = q * 64 + lane;  // 512 chunks: unit = chunk / 2, rows 8 (chunk % 2) .. + 7
+  for (int q = 0; q < 2 * kUnits / 64; ++q) {
+    const int chunk = q * 64 + lane;  // unit = chunk / 2 of the slice, rows 8 (chunk % 2) .. + 7
     const int unit = chunk >> 1, h = chunk & 1;
     const u8m val = *reinterpret_cast<const u8m*>(&st[unit * kTrStageStride + 8 * h]);
-    *reinterpret_cast<u8m*>(&T[(int64_t)unit * ldT + row0 + 8 * h]) = val;
+    *reinterpret_cast<u8m*>(&T[(int64_t)(kUnits * us + unit) * ldT + row0 + 8 * h]) = val;
   }
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
   __builtin_amdgcn_wave_barrier();
@@ -720,35 +732,41 @@ struct TrainRowsArgs {
 __device__ __forceinline__ void stage_operands(const uint16_t* __restrict__ g, uint16_t* lds, int tid) {
   const u8m* src = reinterpret_cast<const u8m*>(g);
   u8m* dst = reinterpret_cast<u8m*>(lds);
-  constexpr int kPer = kTrH * kTrH / 8 / 256;  // 32 vectors of 16 bytes per thread
+  constexpr int kPer = kTrH * kTrH / 8 / kTrThreads;  // 16 vectors of 16 bytes per thread
+  static_assert(kPer % 16 == 0, "whole groups of 16 loads");
 #pragma unroll
   for (int b = 0; b < kPer; b += 16) {
     u8m buf[16];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) buf[q] = src[(b + q) * 256 + tid];
+    for (int q = 0; q < 16; ++q) buf[q] = src[(b + q) * kTrThreads + tid];
 #pragma unroll
-    for (int q = 0; q < 16; ++q) dst[(b + q) * 256 + tid] = buf[q];
+    for (int q = 0; q < 16; ++q) dst[(b + q) * kTrThreads + tid] = buf[q];
   }
 }
 
-__global__ void __launch_bounds__(256) k_train_rows(TrainRowsArgs a) {
+__global__ void __launch_bounds__(kTrThreads) k_train_rows(TrainRowsArgs a) {
   __shared__ __align__(16) uint16_t w2s[kTrH * kTrH];
   __shared__ __align__(16) float b1s[kTrH], b2s[kTrH], w3s[kTrH];
-  __shared__ float sums[kTrWaves][kTrVec];
+  __shared__ float sums[kTrBlocks][kTrVec];
+  __shared__ float hp[kTrBlocks][kTrSlices][16];  // the head's partial sums of each slice, per row
+  __shared__ u4m xch[kTrBlocks][8][64];           // dZ2 in operand form, chunk c of lane l
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, col = lane & 15;
+  const int rb = wave / kTrSlices, us = wave % kTrSlices;  // row block, unit slice (units 64 us .. + 63)
   stage_operands(a.tw2f, w2s, tid);
-  b1s[tid] = a.b1[tid];
-  b2s[tid] = a.b2[tid];
-  w3s[tid] = a.w3[tid];
+  if (tid < kTrH) {
+    b1s[tid] = a.b1[tid];
+    b2s[tid] = a.b2[tid];
+    w3s[tid] = a.w3[tid];
+  }
   __syncthreads();
-  float* my = sums[wave];
-  const int64_t r = (int64_t)blockIdx.x * kTrRows + 16 * wave + col;  // this lane's batch row
+  float* my = sums[rb];
+  const int64_t r = (int64_t)blockIdx.x * kTrRows + 16 * rb + col;  // this lane's batch row
   const bool in_batch = r < a.rows;
   int64_t src = -1;
   if (in_batch) {
     const int64_t s = a.order ? (int64_t)a.order[a.row0 + r] : a.row0 + r;
     if (s >= 0 && s < a.n_rows) src = s;
-    else if (g == 0) *a.bad = 1;
+    else if (g == 0 && us == 0) *a.bad = 1;
   }
   const bool live = src >= 0;
   // 1. inputs: features 8 g .. 8 g + 7 of row r (the B operand of layer 1)
@@ -758,10 +776,10 @@ __global__ void __launch_bounds__(256) k_train_rows(TrainRowsArgs a) {
     const int f = 8 * g + j;
     const float v = (live && f < a.d_in) ? (a.P[src * a.d_in + f] - a.mu[f]) / a.sd[f] : 0.f;
     xu[j] = to_bf16(v);
-    a.XT[(int64_t)f * a.ldT + r] = xu[j];
+    if (us == 0) a.XT[(int64_t)f * a.ldT + r] = xu[j];
   }
   const bf8m xb = __builtin_bit_cast(bf8m, xu);
-  // 2. layer 1: H1^T = W1^T X^T + b1, ReLU, BF16
+  // 2. layer 1: H1^T = W1^T X^T + b1, ReLU, BF16 (every unit: the operand of layer 2)
   u4m h1[8];
 #pragma unroll
   for (int v = 0; v < 16; ++v) {
@@ -771,90 +789,106 @@ __global__ void __launch_bounds__(256) k_train_rows(TrainRowsArgs a) {
     h1[v >> 1][2 * (v & 1)] = relu_bf16x2(d[0], d[1]);
     h1[v >> 1][2 * (v & 1) + 1] = relu_bf16x2(d[2], d[3]);
   }
-  // 3. layer 2: Z2^T = W2^T H1^T + b2 (output units permuted like layer 1)
-  f4m z2[16];
+  // 3. layer 2 for this slice's units: Z2^T = W2^T H1^T + b2 (output units permuted like layer 1)
+  f4m z2[kTrSliceV];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) z2[v] = *reinterpret_cast<const f4m*>(&b2s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
+  for (int vv = 0; vv < kTrSliceV; ++vv) {
+    const int v = kTrSliceV * us + vv;
+    z2[vv] = *reinterpret_cast<const f4m*>(&b2s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
+  }
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
     const bf8m hb = __builtin_bit_cast(bf8m, h1[c]);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
+    for (int vv = 0; vv < kTrSliceV; ++vv) {
+      const int v = kTrSliceV * us + vv;
       const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(w2s)[(v * 8 + c) * 64 + lane]);
-      z2[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hb, z2[v], 0, 0, 0);
+      z2[vv] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, hb, z2[vv], 0, 0, 0);
     }
   }
-  // 4. head and loss (the four lane groups hold disjoint units of the same row)
+  // 4. head: this slice's partial sum (the four lane groups hold disjoint units of the same row), the
+  //    slices' partials added in slice order
   float lp = 0.f;
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
+  for (int vv = 0; vv < kTrSliceV; ++vv) {
+    const int v = kTrSliceV * us + vv;
     const f4m hw = *reinterpret_cast<const f4m*>(&w3s[32 * (v >> 1) + 8 * g + 4 * (v & 1)]);
 #pragma unroll
-    for (int i = 0; i < 4; ++i) lp = fmaf(fmaxf(z2[v][i], 0.f), hw[i], lp);
+    for (int i = 0; i < 4; ++i) lp = fmaf(fmaxf(z2[vv][i], 0.f), hw[i], lp);
   }
   lp += __shfl_xor(lp, 16);
   lp += __shfl_xor(lp, 32);
-  const float z = lp + a.b3[0];
+  if (g == 0) hp[rb][us][col] = lp;
+  __syncthreads();  // partials visible; every wave is done with the layer-2 operands
+  float zs = hp[rb][0][col];
+#pragma unroll
+  for (int k = 1; k < kTrSlices; ++k) zs += hp[rb][k][col];
+  const float z = zs + a.b3[0];
   float dz = 0.f, loss = 0.f;
   if (live) {
     const float t = a.y[src] > 0 ? 1.f : 0.f;
     loss = fmaxf(z, 0.f) + log1pf(expf(-fabsf(z))) - t * z;
     dz = (1.f / (1.f + expf(-z)) - t) / (float)a.rows;
-    if (a.z_out && g == 0) a.z_out[r] = z;
+    if (a.z_out && g == 0 && us == 0) a.z_out[r] = z;
   }
-  // 5. dZ2 = [Z2 > 0] dz w3 (FP32), row sums for gb2 and gw3, BF16 copy
-  u4m d2[8];
+  // 5. dZ2 = [Z2 > 0] dz w3 (FP32) for this slice's units, row sums for gb2 and gw3, BF16 copy shared with
+  //    the row block's other slices
+  u4m d2[kTrSliceC];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
+  for (int vv = 0; vv < kTrSliceV; ++vv) {
+    const int v = kTrSliceV * us + vv;
     const int u0 = 32 * (v >> 1) + 8 * g + 4 * (v & 1);
     const f4m hw = *reinterpret_cast<const f4m*>(&w3s[u0]);
     f4m dv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      dv[i] = z2[v][i] > 0.f ? dz * hw[i] : 0.f;
+      dv[i] = z2[vv][i] > 0.f ? dz * hw[i] : 0.f;
       const float sb = rows_sum(dv[i]);
-      const float sw = rows_sum(fmaxf(z2[v][i], 0.f) * dz);
+      const float sw = rows_sum(fmaxf(z2[vv][i], 0.f) * dz);
       if (col == 0) {
         my[kTrH + u0 + i] = sb;
         my[2 * kTrH + u0 + i] = sw;
       }
     }
-    d2[v >> 1][2 * (v & 1)] = pack_bf16x2(dv[0], dv[1]);
-    d2[v >> 1][2 * (v & 1) + 1] = pack_bf16x2(dv[2], dv[3]);
+    d2[vv >> 1][2 * (vv & 1)] = pack_bf16x2(dv[0], dv[1]);
+    d2[vv >> 1][2 * (vv & 1) + 1] = pack_bf16x2(dv[2], dv[3]);
   }
-  // 6. dH1^T = W2 dZ2^T (output units permuted like layer 1), dZ1 = [H1 > 0] dH1; the workgroup's LDS now
-  //    takes the dH1 operands in place of the layer-2 ones (every wave has finished layer 2)
-  __syncthreads();
-  stage_operands(a.tw2d, w2s, tid);
-  __syncthreads();
-  f4m dh[16];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) dh[v] = (f4m){0.f, 0.f, 0.f, 0.f};
+  for (int cc = 0; cc < kTrSliceC; ++cc) xch[rb][kTrSliceC * us + cc][lane] = d2[cc];
+  // 6. dH1^T = W2 dZ2^T for this slice's output units (permuted like layer 1), dZ1 = [H1 > 0] dH1; the
+  //    LDS operand area now takes the dH1 operands
+  stage_operands(a.tw2d, w2s, tid);
+  __syncthreads();  // dH1 operands staged, every slice's dZ2 in LDS
+  f4m dh[kTrSliceV];
+#pragma unroll
+  for (int vv = 0; vv < kTrSliceV; ++vv) dh[vv] = (f4m){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < 8; ++c) {
-    const bf8m db = __builtin_bit_cast(bf8m, d2[c]);
+    const bf8m db = __builtin_bit_cast(bf8m, xch[rb][c][lane]);
 #pragma unroll
-    for (int v = 0; v < 16; ++v) {
+    for (int vv = 0; vv < kTrSliceV; ++vv) {
+      const int v = kTrSliceV * us + vv;
       const bf8m w = __builtin_bit_cast(bf8m, reinterpret_cast<const u8m*>(w2s)[(v * 8 + c) * 64 + lane]);
-      dh[v] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, db, dh[v], 0, 0, 0);
+      dh[vv] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, db, dh[vv], 0, 0, 0);
     }
   }
-  u4m d1[8];
+  u4m d1[kTrSliceC];
 #pragma unroll
-  for (int v = 0; v < 16; ++v) {
+  for (int vv = 0; vv < kTrSliceV; ++vv) {
+    const int v = kTrSliceV * us + vv;
     const int u0 = 32 * (v >> 1) + 8 * g + 4 * (v & 1);
     f4m dv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      dv[i] = bf16_at(h1[v >> 1], 4 * (v & 1) + i) != 0 ? dh[v][i] : 0.f;
+      dv[i] = bf16_at(h1[v >> 1], 4 * (v & 1) + i) != 0 ? dh[vv][i] : 0.f;
       const float sb = rows_sum(dv[i]);
       if (col == 0) my[u0 + i] = sb;
     }
-    d1[v >> 1][2 * (v & 1)] = pack_bf16x2(dv[0], dv[1]);
-    d1[v >> 1][2 * (v & 1) + 1] = pack_bf16x2(dv[2], dv[3]);
+    d1[vv >> 1][2 * (vv & 1)] = pack_bf16x2(dv[0], dv[1]);
+    d1[vv >> 1][2 * (vv & 1) + 1] = pack_bf16x2(dv[2], dv[3]);
   }
-  // 7. row sums of dz (gb3) and of the loss
-  {
+  // 7. row sums of dz (gb3) and of the loss (once per row block)
+  if (us == 0) {
     const float sdz = rows_sum(g == 0 ? dz : 0.f);
     const float sl = rows_sum(g == 0 ? loss : 0.f);
     if (lane == 0) {
@@ -864,17 +898,17 @@ __global__ void __launch_bounds__(256) k_train_rows(TrainRowsArgs a) {
   }
   __syncthreads();  // every wave is done with the dH1 operands: the LDS area now stages the unit-major stores
   {
-    const int64_t row0 = (int64_t)blockIdx.x * kTrRows + 16 * wave;
-    uint16_t* st = w2s + wave * (kTrH * kTrStageStride);
-    store_unit_major(h1, st, a.H1T, a.ldT, row0, lane);
-    store_unit_major(d2, st, a.dZ2T, a.ldT, row0, lane);
-    store_unit_major(d1, st, a.dZ1T, a.ldT, row0, lane);
+    const int64_t row0 = (int64_t)blockIdx.x * kTrRows + 16 * rb;
+    uint16_t* st = w2s + wave * ((kTrH / kTrSlices) * kTrStageStride);
+    store_unit_major(&h1[kTrSliceC * us], us, st, a.H1T, a.ldT, row0, lane);
+    store_unit_major(d2, us, st, a.dZ2T, a.ldT, row0, lane);
+    store_unit_major(d1, us, st, a.dZ1T, a.ldT, row0, lane);
   }
-  // workgroup sums in wave order
-  for (int k = tid; k < kTrVec; k += 256) {
+  // workgroup sums in row-block order
+  for (int k = tid; k < kTrVec; k += kTrThreads) {
     float s = 0.f;
 #pragma unroll
-    for (int w = 0; w < kTrWaves; ++w) s += sums[w][k];
+    for (int w = 0; w < kTrBlocks; ++w) s += sums[w][k];
     a.wg_sums[(int64_t)blockIdx.x * kTrVec + k] = s;
   }
 }
@@ -900,20 +934,23 @@ __global__ void __launch_bounds__(64) k_train_wgrad(const uint16_t* __restrict__
     if (split != 0) return;
     const int k = (tile - kTrWgradTiles) * 64 + lane;
     if (k >= kTrVec) return;
+    // workgroup order, 64 loads in flight per step; the loss (entry 3 H + 1) also in FP64
+    const bool is_loss = k == 3 * kTrH + 1;
     double sd = 0.0;
     float sf = 0.f;
-    for (int w0 = 0; w0 < n_wg; w0 += 16) {
-      float buf[16];
+    for (int w0 = 0; w0 < n_wg; w0 += 64) {
+      float buf[64];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) buf[q] = w0 + q < n_wg ? wg_sums[(int64_t)(w0 + q) * kTrVec + k] : 0.f;
+      for (int q = 0; q < 64; ++q) buf[q] = w0 + q < n_wg ? wg_sums[(int64_t)(w0 + q) * kTrVec + k] : 0.f;
 #pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        sf += buf[q];
-        sd += (double)buf[q];
+      for (int q = 0; q < 64; ++q) sf += buf[q];
+      if (is_loss) {
+#pragma unroll
+        for (int q = 0; q < 64; ++q) sd += (double)buf[q];
       }
     }
     red[k] = sf;
-    if (k == 3 * kTrH + 1) *red_loss = sd;
+    if (is_loss) *red_loss = sd;
     return;
   }
   const bool w2 = tile < 32;
@@ -1299,7 +1336,7 @@ fastron_status fast_step(fastron_mlp* n, const float* P, const int8_t* y, const 
   a.wg_sums = n->wg_sums;
   a.z_out = z_out;
   a.bad = n->bad;
-  hipLaunchKernelGGL(k_train_rows, dim3((unsigned)nwg), dim3(256), 0, s, a);
+  hipLaunchKernelGGL(k_train_rows, dim3((unsigned)nwg), dim3(kTrThreads), 0, s, a);
   FASTRON_HIP(hipGetLastError());
   const int64_t krows = (int64_t)nwg * kTrRows;
   int64_t splits = krows / 256;  // about 8 row steps of 32 per wave
