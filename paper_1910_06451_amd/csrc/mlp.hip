@@ -918,8 +918,9 @@ __global__ void __launch_bounds__(kTrThreads) k_train_rows(TrainRowsArgs a) {
 // unit-major arrays, in groups of 8 row steps of 32 whose operands are all
 // loaded before the group's products. One wave per (tile, split); partial
 // written to part[split][W1 (kTrIn x kTrH) | W2 (kTrH x kTrH)]. Blocks past
-// the tiles (split 0 only) sum the per-workgroup vectors of k_train_rows in
-// workgroup order into red[kTrVec] (the loss sum in FP64 into red_loss).
+// the tiles sum the per-workgroup vectors of k_train_rows over a contiguous
+// range of workgroups per split, in workgroup order, into red[split][kTrVec]
+// (the loss sum in FP64 into red_loss[split]).
 constexpr int kTrWgradTiles = 36;
 constexpr int kTrRedBlocks = (kTrVec + 63) / 64;
 __global__ void __launch_bounds__(64) k_train_wgrad(const uint16_t* __restrict__ XT, const uint16_t* __restrict__ H1T,
@@ -931,26 +932,27 @@ __global__ void __launch_bounds__(64) k_train_wgrad(const uint16_t* __restrict__
   const int lane = threadIdx.x, g = lane >> 4, col = lane & 15;
   const int tile = blockIdx.x, split = blockIdx.y;
   if (tile >= kTrWgradTiles) {
-    if (split != 0) return;
     const int k = (tile - kTrWgradTiles) * 64 + lane;
     if (k >= kTrVec) return;
-    // workgroup order, 64 loads in flight per step; the loss (entry 3 H + 1) also in FP64
+    const int per = (n_wg + (int)gridDim.y - 1) / (int)gridDim.y;
+    const int wa = split * per, wb = wa + per < n_wg ? wa + per : n_wg;
+    // workgroups wa .. wb - 1 in order, 16 loads in flight per step; the loss (entry 3 H + 1) also in FP64
     const bool is_loss = k == 3 * kTrH + 1;
     double sd = 0.0;
     float sf = 0.f;
-    for (int w0 = 0; w0 < n_wg; w0 += 64) {
-      float buf[64];
+    for (int w0 = wa; w0 < wb; w0 += 16) {
+      float buf[16];
 #pragma unroll
-      for (int q = 0; q < 64; ++q) buf[q] = w0 + q < n_wg ? wg_sums[(int64_t)(w0 + q) * kTrVec + k] : 0.f;
+      for (int q = 0; q < 16; ++q) buf[q] = w0 + q < wb ? wg_sums[(int64_t)(w0 + q) * kTrVec + k] : 0.f;
 #pragma unroll
-      for (int q = 0; q < 64; ++q) sf += buf[q];
+      for (int q = 0; q < 16; ++q) sf += buf[q];
       if (is_loss) {
 #pragma unroll
-        for (int q = 0; q < 64; ++q) sd += (double)buf[q];
+        for (int q = 0; q < 16; ++q) sd += (double)buf[q];
       }
     }
-    red[k] = sf;
-    if (is_loss) *red_loss = sd;
+    red[(int64_t)split * kTrVec + k] = sf;
+    if (is_loss) red_loss[split] = sd;
     return;
   }
   const bool w2 = tile < 32;
@@ -1007,8 +1009,8 @@ __global__ void __launch_bounds__(64) k_train_wgrad(const uint16_t* __restrict__
 struct TrainAdamArgs {
   const float* part;     // [splits][(kTrIn + kTrH) * kTrH]
   int splits;
-  const float* red;      // [kTrVec] workgroup sums reduced by k_train_wgrad
-  const double* red_loss;
+  const float* red;      // [splits][kTrVec] workgroup sums reduced by k_train_wgrad
+  const double* red_loss;  // [splits]
   int d_in;
   int64_t n_params;
   float* params;
@@ -1033,7 +1035,11 @@ __device__ __forceinline__ void unit_slot(int u, int* v, int* row) {
 
 __global__ void __launch_bounds__(256) k_train_adam(TrainAdamArgs a) {
   const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (e == 0 && a.loss_acc) *a.loss_acc += *a.red_loss;
+  if (e == 0 && a.loss_acc) {
+    double l = 0.0;
+    for (int sp = 0; sp < a.splits; ++sp) l += a.red_loss[sp];
+    *a.loss_acc += l;
+  }
   if (e >= a.n_params) return;
   const int64_t nW1 = (int64_t)a.d_in * kTrH;
   const int64_t oW2 = nW1 + kTrH, oB2 = oW2 + (int64_t)kTrH * kTrH, oW3 = oB2 + kTrH, oB3 = oW3 + kTrH;
@@ -1047,19 +1053,20 @@ __global__ void __launch_bounds__(256) k_train_adam(TrainAdamArgs a) {
   else if (e < oW3) { kind = 3; idx = e - oB2; }
   else if (e < oB3) { kind = 4; idx = e - oW3; }
   else { kind = 5; idx = 0; }
-  if (kind == 0 || kind == 2) {
+  {
     // split partials in a fixed order, their loads issued 16 at a time
-    const float* base = a.part + (kind == 0 ? idx : (int64_t)kTrIn * kTrH + idx);
+    const bool w = kind == 0 || kind == 2;
+    const float* base = w ? a.part + (kind == 0 ? idx : (int64_t)kTrIn * kTrH + idx)
+                          : a.red + (kind == 1 ? idx : kind == 3 ? kTrH + idx : kind == 4 ? 2 * kTrH + idx : 3 * kTrH);
+    const int64_t stride = w ? pstride : kTrVec;
     for (int s0 = 0; s0 < a.splits; s0 += 16) {
       float buf[16];
 #pragma unroll
-      for (int q = 0; q < 16; ++q) buf[q] = s0 + q < a.splits ? base[(int64_t)(s0 + q) * pstride] : 0.f;
+      for (int q = 0; q < 16; ++q) buf[q] = s0 + q < a.splits ? base[(int64_t)(s0 + q) * stride] : 0.f;
 #pragma unroll
       for (int q = 0; q < 16; ++q)
         if (s0 + q < a.splits) gsum += buf[q];
     }
-  } else {
-    gsum = a.red[kind == 1 ? idx : kind == 3 ? kTrH + idx : kind == 4 ? 2 * kTrH + idx : 3 * kTrH];
   }
   a.grads[e] = gsum;
   if (!a.apply) return;
@@ -1143,7 +1150,7 @@ struct fastron_mlp {
   uint16_t* dZ1T = nullptr;
   float* wg_sums = nullptr;
   float* wpart = nullptr;
-  float* red = nullptr;       // [kTrVec] reduced workgroup sums
+  float* red = nullptr;       // [kTrSplitsMax][kTrVec] reduced workgroup sums per split
   double* red_loss = nullptr;
   double* loss_acc = nullptr;
   float* splitbuf = nullptr;  // split-K partial products of the weight-gradient GEMMs
@@ -1501,8 +1508,8 @@ fastron_status fastron_mlp_create(int32_t d_in, int32_t hidden, int64_t max_rows
     alloc(&n->wg_sums, (n->ldT / kTrRows) * kTrVec, 4);
     alloc(&n->wpart, (int64_t)kTrSplitsMax * (kTrIn + kTrH) * kTrH, 4);
     alloc(&n->loss_acc, 1, 8);
-    alloc(&n->red, kTrVec, 4);
-    alloc(&n->red_loss, 1, 8);
+    alloc(&n->red, (int64_t)kTrSplitsMax * kTrVec, 4);
+    alloc(&n->red_loss, kTrSplitsMax, 8);
   }
   if (e == hipSuccess) e = hipMemset(n->adam_m, 0, n->n_params * 4);
   if (e == hipSuccess) e = hipMemset(n->adam_v, 0, n->n_params * 4);
