@@ -32,7 +32,16 @@ __device__ __forceinline__ float rcp_sat(float t) {
 //                fraction is as accurate as the direct sum; the caller takes
 //                this form only when a bound on t keeps e = prod t_m^2 inside
 //                the normal FP32 range and t away from 0 (rational_sum_ok).
-template <bool RAT>
+// CLAMP: t is first raised to at least 1, i.e. the squared distance to at
+// least 0 (K_RQ <= 1, Eq. 3), one more operation per value (v_med3_f32 with
+// 1 and 3e38: the same clamp for every t up to 3e38; IEEE-mode fmaxf would
+// cost a canonicalising max on top). The BF16 forms take it: their cross
+// term can be off by about 2^-8 gamma ||p|| ||p'||, so cancellation could
+// otherwise push t of a near-coincident pair well below 1. In the FP32 form
+// t is off by at most a few units of 2^-24 t, so the unclamped running
+// fraction stays within rounding of the clamped one and the saturated
+// reciprocal clamps at no cost.
+template <bool RAT, bool CLAMP = false>
 struct PairSum {
   float n[4] = {1.f, 1.f, 1.f, 1.f};  // RAT: numerators;   else: the sums
   float e[4] = {0.f, 0.f, 0.f, 0.f};  // RAT: denominators; else: unused
@@ -43,8 +52,9 @@ struct PairSum {
   __device__ __forceinline__ void add(int m, const f4& d) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
+      const float t = CLAMP ? __builtin_amdgcn_fmed3f(d[r], 1.0f, 3.0e38f) : d[r];
       if constexpr (RAT) {
-        const float v = d[r] * d[r];
+        const float v = t * t;
         if (m == 0) {
           e[r] = v;
         } else {
@@ -52,7 +62,7 @@ struct PairSum {
           e[r] *= v;
         }
       } else {
-        const float x = rcp_sat(d[r]);
+        const float x = CLAMP ? __builtin_amdgcn_rcpf(t) : rcp_sat(t);
         n[r] = fmaf(x, x, n[r]);
       }
     }
