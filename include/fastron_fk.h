@@ -129,7 +129,10 @@ fastron_status fastron_support_prep(const fastron_chain* chain, const fastron_cp
 #define FASTRON_SCORE_VALU 2u
 /* BF16 precision variants (OR into FASTRON_SCORE_BF16): the cross term uses
  * 1, 3 or 6 bf16 products per coordinate (hi.hi; + hi.mid + mid.hi;
- * + hi.lo + lo.hi + mid.mid), splitting each coordinate into bf16 parts.  */
+ * + hi.lo + lo.hi + mid.mid), splitting each coordinate of
+ * sqrt(gamma/2) p into bf16 parts. PLAIN also takes both squared norms from
+ * the hi parts, so its t is that of the rounded points (>= 1 up to FP32
+ * rounding); every BF16 form clamps t at 1 (Eq. 3: K_RQ <= 1).            */
 #define FASTRON_BF16_PLAIN 0x00u
 #define FASTRON_BF16_SPLIT2 0x10u
 #define FASTRON_BF16_SPLIT3 0x20u

@@ -253,14 +253,19 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
       V[slot * 4 + 0] = ax; V[slot * 4 + 1] = ay; V[slot * 4 + 2] = az; V[slot * 4 + 3] = cs;
     }
     if (B16) {
-      // bf16 cross-term operand: -gamma p' split into hi + mid + lo bf16 terms, laid out so that the query
+      // bf16 cross-term operand on the scaled point u' = sqrt(gamma/2) p' (t = 1 + ||u - u'||^2): -2 u'
+      // split into hi + mid + lo bf16 terms (exactly -2 times the parts of u'), laid out so that the query
       // side selects the precision: k0-2 hi, k3-5 hi, k6-8 mid, k9-11 hi, k12-14 lo, k15-17 mid, k18-20 = 1,
-      // k21-23 the hi/mid/lo bf16 parts of c_s (the query side puts hi/mid/lo of p against the first six
-      // groups, the three bf16 parts of c_q against the ones and ones against the parts of c_s).
+      // k21-23 the hi/mid/lo parts of ||u'||^2, k24-26 those of ||hi(u')||^2 (the query side puts hi/mid/lo
+      // of u against the first six groups, the three parts of its own norm against the ones, and ones
+      // against one of the two norms of u': the rounded one for the one-product form, so that its t is that
+      // of the rounded points, t >= 1 up to float32 rounding).
+      const float sg = sqrtf(half_g);
+      const float ux = sg * x, uy = sg * y, uz = sg * z;
       uint16_t sx[3], sy[3], sz[3];
-      bf16_split(ax, 3, sx);
-      bf16_split(ay, 3, sy);
-      bf16_split(az, 3, sz);
+      bf16_split(-2.f * ux, 3, sx);
+      bf16_split(-2.f * uy, 3, sy);
+      bf16_split(-2.f * uz, 3, sz);
       uint16_t* row = B16 + (int64_t)slot * 512;
       auto put = [&](int k, uint16_t v) { row[((k >> 3) * 16 + sl) * 8 + (k & 7)] = v; };
       auto put3 = [&](int k0, int part) { put(k0, sx[part]); put(k0 + 1, sy[part]); put(k0 + 2, sz[part]); };
@@ -268,8 +273,11 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
       const uint16_t one = 0x3f80;
       put(18, one); put(19, one); put(20, one);
       uint16_t sc[3];
-      bf16_split(cs, 3, sc);
+      bf16_split(ux * ux + uy * uy + uz * uz, 3, sc);
       put(21, sc[0]); put(22, sc[1]); put(23, sc[2]);
+      const float hx = bf16_to_f(bf16_rne(ux)), hy = bf16_to_f(bf16_rne(uy)), hz = bf16_to_f(bf16_rne(uz));
+      bf16_split(hx * hx + hy * hy + hz * hz, 3, sc);
+      put(24, sc[0]); put(25, sc[1]); put(26, sc[2]);
     }
   });
   W[sl] = alpha_s / (float)c.M;

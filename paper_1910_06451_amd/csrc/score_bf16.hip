@@ -6,18 +6,23 @@
 namespace fastron {
 
 // ---------------------------------------------------------------------------
-// BF16 MFMA form: the cross term -gamma p.p' as bf16 products on
-// v_mfma_f32_16x16x32_bf16 with FP32 accumulation. The support operand holds
-// -gamma p' as hi + mid + lo bf16 parts (prepare kernel); the query side
-// chooses the precision by which parts of p it pairs with them:
-//   variant 0 (plain) : hi(p).hi(p')
-//   variant 1 (split2): + mid(p).hi(p') + hi(p).mid(p')
-//   variant 2 (split3): + lo(p).hi(p') + hi(p).lo(p') + mid(p).mid(p')
-// c_q and c_s enter as three bf16 parts each against unit entries (exact to
-// FP32 rounding), so the accumulator input is zero and no FP32 operand block
-// has to be streamed besides the weights. Every t is clamped to t >= 1 (the
-// squared distance to >= 0) before 1/t^2, so each K_RQ stays within (0, 1]
-// whatever the cancellation in the BF16 cross term.
+// BF16 MFMA form: with u = sqrt(gamma/2) p, t = 1 + ||u||^2 + ||u'||^2 - 2 u.u',
+// the cross term -2 u.u' as bf16 products on v_mfma_f32_16x16x32_bf16 with
+// FP32 accumulation. The support operand holds -2 u' as hi + mid + lo bf16
+// parts (prepare kernel); the query side chooses the precision by which parts
+// of u it pairs with them:
+//   variant 0 (plain) : hi(u).hi(u'), with both norms taken from hi(u) and
+//                       hi(u') as well, so that t is exactly 1 + the squared
+//                       distance of the rounded points (up to float32
+//                       rounding): the bf16 error then scales with the
+//                       distance of the pair instead of with ||p|| ||p'||
+//   variant 1 (split2): + mid(u).hi(u') + hi(u).mid(u')
+//   variant 2 (split3): + lo(u).hi(u') + hi(u).lo(u') + mid(u).mid(u')
+// The norms (computed in FP32) enter as three bf16 parts each against unit
+// entries (exact to FP32 rounding), so the accumulator input is zero and no
+// FP32 operand block has to be streamed besides the weights. Every t is
+// clamped to t >= 1 (the squared distance to >= 0) before 1/t^2, so each K_RQ
+// stays within (0, 1] whatever the cancellation in the BF16 cross term.
 // ---------------------------------------------------------------------------
 __device__ __forceinline__ unsigned short bf16_rne_d(float x) {
   uint32_t u = __float_as_uint(x);
@@ -52,7 +57,8 @@ __device__ __forceinline__ unsigned short query_slot(int k, int variant, const S
     case 4: return variant >= 2 ? v.h : 0;       // against lo(p')
     case 5: return variant >= 2 ? v.m : 0;       // against mid(p')
     case 6: return comp == 0 ? cq.h : (comp == 1 ? cq.m : cq.l);  // against 1
-    case 7: return 0x3f80;                       // 1 against the three bf16 parts of c_s
+    case 7: return variant >= 1 ? 0x3f80 : 0;   // 1 against the three bf16 parts of ||u'||^2
+    case 8: return variant == 0 ? 0x3f80 : 0;   // 1 against those of ||hi(u')||^2
     default: return 0;
   }
 }
@@ -78,7 +84,8 @@ __global__ void __launch_bounds__(256) k_score_bf16(ChainArgs c, const float* __
   const int64_t S_pad = ntiles * kTile;
   const u16x8* A16 = reinterpret_cast<const u16x8*>(blob + kHeaderBytes + ntiles * tstride * 4 +
                                                     S_pad * (int64_t)Mp * 16);
-  const f4 zero = {0.f, 0.f, 0.f, 0.f};  // c_s arrives through the operands
+  const f4 zero = {0.f, 0.f, 0.f, 0.f};  // both norms arrive through the operands
+  const float sg = sqrtf(0.5f * gamma);   // the prepare kernel's scale, computed the same way
 #pragma unroll 1
   for (int h = 0; h < 4; h += QB) {
     bf8 B[QB][MM];
@@ -87,7 +94,16 @@ __global__ void __launch_bounds__(256) k_score_bf16(ChainArgs c, const float* __
 #pragma unroll
       for (int m = 0; m < MM; ++m) {
         const f4 p = lds[wave][16 * (h + b) + col][m];
-        const Split3 sx = split3(p[0]), sy = split3(p[1]), sz = split3(p[2]), sc = split3(p[3]);
+        const float ux = sg * p[0], uy = sg * p[1], uz = sg * p[2];
+        const Split3 sx = split3(ux), sy = split3(uy), sz = split3(uz);
+        float nq;
+        if (variant == 0) {
+          const float hx = bf16_f(sx.h), hy = bf16_f(sy.h), hz = bf16_f(sz.h);
+          nq = hx * hx + hy * hy + hz * hz;
+        } else {
+          nq = ux * ux + uy * uy + uz * uz;
+        }
+        const Split3 sc = split3(1.f + nq);
         u16x8 u;
 #pragma unroll
         for (int e = 0; e < 8; ++e) u[e] = query_slot(8 * g + e, variant, sx, sy, sz, sc);

@@ -48,25 +48,34 @@ U16 = 2.0 ** -8  # unit roundoff of bfloat16 (8 significant bits, round to neare
 
 def bf16_error_bound(Ps, alpha, gamma, Pq, variant, safety=1.25):
     """Per-query bound on |f_gpu - f_oracle| for the BF16 cross-term forms, from the bf16 rounding of the
-    operands. The kernel forms t = c_q + c_s + sum_k p_k g_k with g = -gamma p' (float32) and each product taken
-    from bf16 parts of p and g: PLAIN keeps hi(p) hi(g), an error of at most (2u + u^2) |p_k| |g_k| per
-    coordinate (u = 2^-8); SPLIT2 adds mid(p) hi(g) + hi(p) mid(g) and misses mid(p) mid(g) and everything
-    with a third part, at most 3.1 u^2 |p_k| |g_k|. The bf16 products are exact in the float32 accumulator,
-    whose own rounding and that of c_q, c_s and g add the float32 term of error_bound. The kernel clamps t
-    at 1 and the true t is >= 1, so a pair's K_RQ moves by at most 2 dt / max(1, t - dt)^3 and never by more
-    than 1 (both values lie in (0, 1]); the pair sum adds its float32 rounding."""
-    rel = {api.BF16_PLAIN: 2 * U16 + U16 ** 2, api.BF16_SPLIT2: 3.1 * U16 ** 2}[variant]
+    operands. With u = sqrt(gamma/2) p the kernel forms t = 1 + ||u||^2 + ||u'||^2 - 2 u.u', the cross term from
+    bf16 parts of u and u' (float32 norms).
+    PLAIN takes hi(u) and hi(u') for the cross term and for both norms, so its t is 1 + ||hi(u) - hi(u')||^2:
+    with hi(u_k) = u_k + e_k, |e_k| <= u |u_k| (u = 2^-8), the squared distance moves by
+    2 sum_k |u_k - u'_k| |e_k - e'_k| + sum_k (e_k - e'_k)^2
+      <= gamma u sum_k |p_k - p'_k| (|p_k| + |p'_k|) + gamma/2 u^2 sum_k (|p_k| + |p'_k|)^2,
+    which vanishes with the distance of the pair. SPLIT2 keeps hi.hi + mid.hi + hi.mid of 2 u_k u'_k =
+    gamma p_k p'_k and misses mid.mid and everything with a third part, at most 3.1 u^2 gamma |p_k| |p'_k|. The
+    bf16 products are exact in the float32 accumulator, whose own rounding and that of the scaling and the
+    norms add the float32 term of error_bound. The kernel clamps t at 1 and the true t is >= 1, so a pair's
+    K_RQ moves by at most 2 dt / max(1, t - dt)^3 and never by more than 1 (both values lie in (0, 1]); the
+    pair sum adds its float32 rounding."""
     M = Ps.shape[1]
     out = np.zeros(Pq.shape[0])
     aw = np.abs(alpha.astype(np.float64)) / M
     ns = np.linalg.norm(Ps, axis=2)
     for j in range(Pq.shape[0]):
-        d2 = np.sum((Ps - Pq[j][None]) ** 2, axis=2)
+        diff = Ps - Pq[j][None]
+        d2 = np.sum(diff ** 2, axis=2)
         t = 1.0 + 0.5 * gamma * d2
-        cross = gamma * np.sum(np.abs(Ps) * np.abs(Pq[j][None]), axis=2)  # sum_k |p_k| |g_k|
+        mag = np.abs(Ps) + np.abs(Pq[j][None])  # |p_k| + |p'_k|
+        if variant == api.BF16_PLAIN:
+            dt_bf = gamma * (U16 * np.sum(np.abs(diff) * mag, axis=2) + 0.5 * U16 ** 2 * np.sum(mag ** 2, axis=2))
+        else:
+            dt_bf = 3.1 * U16 ** 2 * gamma * np.sum(np.abs(Ps) * np.abs(Pq[j][None]), axis=2)
         nq = np.linalg.norm(Pq[j], axis=1)[None, :]
         terms = 1.0 + 0.5 * gamma * (nq ** 2 + ns ** 2) + gamma * nq * ns
-        dt = safety * rel * cross + 8.0 * U32 * terms
+        dt = safety * dt_bf + 8.0 * U32 * terms
         dk = np.minimum(2.0 * dt / np.maximum(1.0, t - dt) ** 3, 1.0) + 8.0 * (3 * M + 2) * U32 / t ** 2
         out[j] = np.sum(aw[:, None] * dk)
     return out
