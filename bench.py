@@ -958,7 +958,9 @@ def screen_run(api, wl, arm, dev, epochs=6, n_train=2_000_000, n_query=4_194_304
         rows.append({"tau": tau, "fallback_rate": nfb / n_query, "checks_per_s": n_query / t,
                      "accuracy": float((lab == truth).float().mean()), "speedup_vs_plain": t_plain / t})
     net.close()
+    train_tflops = mlp_train_flops(3 * arm.M, 256) * n_fit * epochs / train_s / 1e12
     return {"train_samples": n_fit, "epochs": epochs, "train_s": train_s, "losses": losses,
+            "train_tflops": train_tflops, "train_frac_bf16_peak": train_tflops / BF16_PEAK_TFLOPS,
             "heldout_accuracy_mlp_only": acc_ho, "fallback_support": int(sup.numel()),
             "fallback_converged": bool(fit["converged"]), "queries": n_query,
             "plain": {"checks_per_s": n_query / t_plain, "accuracy": acc_plain}, "screened": rows}
