@@ -366,20 +366,25 @@ def test_score_general_chains(oracle_mod, dev, case):
 def test_score_every_moving_point_count(oracle_mod, dev, Mm):
     """Every instantiation of the scoring kernels over the number of moving control points (1..16): an
     Mm-joint chain (FP32 chain below 7 joints, FP64 from 7) with a point on each moving frame and, while the
-    total stays within 16 points, one on the base frame; MFMA and VALU forms, ragged S and N."""
+    total stays within 16 points, one on the base frame; MFMA, VALU and BF16 (split3 against the FP32 bound,
+    plain against the bound from its bf16 rounding) forms, ragged S and N."""
     arm = _random_chain(f"mm{Mm}", Mm, np.arange(0 if Mm < 16 else 1, Mm + 1))
     gamma, S, N = 10.0, 37, 203
     sq, al = wl.model(f"mm{Mm}", S, arm.n)
     q = wl.configs(f"mm{Mm}/q", N, arm.n)
     dh = oracle_mod.dh_table(arm.a, arm.alpha, arm.d, arm.theta, arm.joint_type)
     ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, q.astype(np.float64))
-    tol = error_bound(oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64)), al, gamma,
-                      oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)))
+    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
+    Pq = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64))
+    tol = error_bound(Ps, al, gamma, Pq)
     model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma)
-    for flags in (api.SCORE_FP32, api.SCORE_VALU):
+    cases = ((api.SCORE_FP32, tol, 0.99), (api.SCORE_VALU, tol, 0.99),
+             (api.SCORE_BF16 | api.BF16_SPLIT3, tol, 0.99),
+             (api.SCORE_BF16 | api.BF16_PLAIN, bf16_error_bound(Ps, al, gamma, Pq, api.BF16_PLAIN), 0.8))
+    for flags, bound, agree in cases:
         announce(f"fk_score Mm={Mm} flags={flags}")
         f, lab = api.fk_score_prepared(arm, model, torch.from_numpy(q).to(dev), flags=flags)
-        check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, tol, min_agree=0.99)
+        check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, bound, min_agree=agree)
 
 
 def test_score_duplicate_supports_and_wide_gamma(oracle_mod, dev):
