@@ -206,6 +206,35 @@ __device__ __forceinline__ void bf16_split(float v, int parts, uint16_t out[3]) 
   }
 }
 
+// sum of alpha[s0..s1) by one 256-thread block in a fixed order (strided
+// partial sums, then a tree); shared by the single-model and batched forms so
+// that both produce the same bits.
+__device__ __forceinline__ float block_alpha_sum(const float* __restrict__ alpha, int64_t s0, int64_t s1,
+                                                 float* part) {
+  float acc = 0.f;
+  for (int64_t s = s0 + threadIdx.x; s < s1; s += 256) acc += alpha[s];
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
+    __syncthreads();
+  }
+  return part[0];
+}
+
+typedef unsigned short b16row8 __attribute__((ext_vector_type(8)));
+
+// Row `sl` of slot m of a tile's bf16 operand: k = 0..31 stored as [g][s][8]
+// (k = 8 g + j), so each group of 8 k values is one 16-byte store.
+__device__ __forceinline__ void put_b16_row(uint16_t* __restrict__ B16, int m, int sl, b16row8 g0, b16row8 g1,
+                                            b16row8 g2, b16row8 g3) {
+  b16row8* row = reinterpret_cast<b16row8*>(B16 + (int64_t)m * 512 + sl * 8);
+  row[0] = g0;
+  row[16] = g1;
+  row[32] = g2;
+  row[48] = g3;
+}
+
 // Writes one support configuration (or a padding row when sq_row is NULL) as
 // row `sl` of its tile T; V (VALU rows) and B16 (bf16 operand of the tile)
 // are optional.
@@ -226,12 +255,13 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
     if (V) {
       V[m * 4 + 0] = 0.f; V[m * 4 + 1] = 0.f; V[m * 4 + 2] = 0.f; V[m * 4 + 3] = 0.f;
     }
-    // bf16 A operand: row sl, k = 0..31, stored as [g][s][8] per m; the unit
-    // entries k18-20 (against the parts of c_q) are set for padding too, so
-    // that a padded row's t is c_q >= 1 as in the FP32 layout, never 0
-    if (B16)
-      for (int k = 0; k < 32; ++k)
-        B16[(int64_t)m * 512 + ((k >> 3) * 16 + sl) * 8 + (k & 7)] = (k >= 18 && k <= 20) ? 0x3f80 : 0;
+    // bf16 operand: the unit entries k18-20 (against the parts of the
+    // query's norm) are set for padding too, so that a padded row's t is
+    // 1 + ||u||^2 >= 1 as in the FP32 layout, never 0
+    if (B16) {
+      const b16row8 z = {0, 0, 0, 0, 0, 0, 0, 0};
+      put_b16_row(B16, m, sl, z, z, (b16row8){0, 0, 0x3f80, 0x3f80, 0x3f80, 0, 0, 0}, z);
+    }
   }
   W[sl] = 0.f;
   if (!sq_row) return;
@@ -266,18 +296,16 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
       bf16_split(-2.f * ux, 3, sx);
       bf16_split(-2.f * uy, 3, sy);
       bf16_split(-2.f * uz, 3, sz);
-      uint16_t* row = B16 + (int64_t)slot * 512;
-      auto put = [&](int k, uint16_t v) { row[((k >> 3) * 16 + sl) * 8 + (k & 7)] = v; };
-      auto put3 = [&](int k0, int part) { put(k0, sx[part]); put(k0 + 1, sy[part]); put(k0 + 2, sz[part]); };
-      put3(0, 0); put3(3, 0); put3(6, 1); put3(9, 0); put3(12, 2); put3(15, 1);
-      const uint16_t one = 0x3f80;
-      put(18, one); put(19, one); put(20, one);
-      uint16_t sc[3];
+      uint16_t sc[3], sr[3];
       bf16_split(ux * ux + uy * uy + uz * uz, 3, sc);
-      put(21, sc[0]); put(22, sc[1]); put(23, sc[2]);
       const float hx = bf16_to_f(bf16_rne(ux)), hy = bf16_to_f(bf16_rne(uy)), hz = bf16_to_f(bf16_rne(uz));
-      bf16_split(hx * hx + hy * hy + hz * hz, 3, sc);
-      put(24, sc[0]); put(25, sc[1]); put(26, sc[2]);
+      bf16_split(hx * hx + hy * hy + hz * hz, 3, sr);
+      const uint16_t one = 0x3f80;
+      put_b16_row(B16, slot, sl,
+                  (b16row8){sx[0], sy[0], sz[0], sx[0], sy[0], sz[0], sx[1], sy[1]},   // k0-7
+                  (b16row8){sz[1], sx[0], sy[0], sz[0], sx[2], sy[2], sz[2], sx[1]},   // k8-15
+                  (b16row8){sy[1], sz[1], one, one, one, sc[0], sc[1], sc[2]},         // k16-23
+                  (b16row8){sr[0], sr[1], sr[2], 0, 0, 0, 0, 0});                      // k24-31
     }
   });
   W[sl] = alpha_s / (float)c.M;
@@ -286,7 +314,13 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
 template <typename R>
 __global__ void __launch_bounds__(256) k_support_prep(ChainArgs c, const float* __restrict__ sq,
                                                        const float* __restrict__ alpha, int64_t S, int64_t ntiles,
-                                                       float gamma, char* __restrict__ blob) {
+                                                       float gamma, float fixed_scale, char* __restrict__ blob) {
+  if (blockIdx.x == 0) {
+    // header: f_const = fixed_scale * sum_i alpha_i (the folded base-frame points), the rest zero
+    __shared__ float part[256];
+    const float fc = fixed_scale != 0.f ? block_alpha_sum(alpha, 0, S, part) * fixed_scale : 0.f;
+    if (threadIdx.x < kHeaderBytes / 4) reinterpret_cast<float*>(blob)[threadIdx.x] = threadIdx.x == 0 ? fc : 0.f;
+  }
   const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ntiles * kTile) return;
   const int Mp = (c.M + 3) & ~3;
@@ -327,21 +361,6 @@ __global__ void __launch_bounds__(256) k_support_prep_batched(ChainArgs c, const
                   tiles + tile * tile_floats(Mp), sl, Mp, nullptr, nullptr);
 }
 
-// sum of alpha[s0..s1) by one 256-thread block in a fixed order (strided
-// partial sums, then a tree); shared by the single-model and batched forms so
-// that both produce the same bits.
-__device__ __forceinline__ float block_alpha_sum(const float* __restrict__ alpha, int64_t s0, int64_t s1,
-                                                 float* part) {
-  float acc = 0.f;
-  for (int64_t s = s0 + threadIdx.x; s < s1; s += 256) acc += alpha[s];
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
-    if ((int)threadIdx.x < w) part[threadIdx.x] += part[threadIdx.x + w];
-    __syncthreads();
-  }
-  return part[0];
-}
 
 // Per-environment fixed-point term: one block per environment.
 __global__ void __launch_bounds__(256) k_fixed_term_batched(const float* __restrict__ alpha,
@@ -373,12 +392,6 @@ fastron_status launch_prep_batched(const ChainArgs& c, const float* sq, const fl
 }
 
 // f_const = (#fixed points / M) * sum_s alpha_s.
-__global__ void __launch_bounds__(256) k_fixed_term(const float* __restrict__ alpha, int64_t S, float scale,
-                                                     float* __restrict__ header) {
-  __shared__ float part[256];
-  const float sum = block_alpha_sum(alpha, 0, S, part);
-  if (threadIdx.x == 0) header[0] = sum * scale;
-}
 
 __global__ void k_zero_header(float* header) {
   if (threadIdx.x < 64) header[threadIdx.x] = 0.f;
@@ -583,25 +596,22 @@ fastron_status fastron_support_prep(const fastron_chain* chain, const fastron_cp
   model->gamma = gamma;
   hipStream_t s = as_stream(stream);
   char* blob = static_cast<char*>(model->data);
-  hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(blob));
-  FASTRON_HIP(hipGetLastError());
   const int64_t nt = ntiles_of(S);
-  if (nt > 0) {
+  if (nt == 0) {
+    hipLaunchKernelGGL(k_zero_header, dim3(1), dim3(64), 0, s, reinterpret_cast<float*>(blob));
+  } else {
+    // one launch: the tiles, and in block 0 the header with the folded base-frame term
+    const float fixed_scale = c.Mm < c.M ? (float)(c.M - c.Mm) / (float)c.M : 0.f;
     const int64_t threads = nt * kTile;
     const unsigned blocks = (unsigned)((threads + 255) / 256);
     if (c.n >= kFp64Joints)
       hipLaunchKernelGGL(k_support_prep<double>, dim3(blocks), dim3(256), 0, s, c, support_q, alpha, S, nt, gamma,
-                         blob);
+                         fixed_scale, blob);
     else
       hipLaunchKernelGGL(k_support_prep<float>, dim3(blocks), dim3(256), 0, s, c, support_q, alpha, S, nt, gamma,
-                         blob);
-    FASTRON_HIP(hipGetLastError());
+                         fixed_scale, blob);
   }
-  if (S > 0 && c.Mm < c.M) {
-    hipLaunchKernelGGL(k_fixed_term, dim3(1), dim3(256), 0, s, alpha, S, (float)(c.M - c.Mm) / (float)c.M,
-                       reinterpret_cast<float*>(blob));
-    FASTRON_HIP(hipGetLastError());
-  }
+  FASTRON_HIP(hipGetLastError());
   return FASTRON_OK;
 }
 
