@@ -751,7 +751,9 @@ __global__ void __launch_bounds__(kTrThreads) k_train_rows(TrainRowsArgs a) {
   __shared__ float hp[kTrBlocks][kTrSlices][16];  // the head's partial sums of each slice, per row
   __shared__ u4m xch[kTrBlocks][8][64];           // dZ2 in operand form, chunk c of lane l
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, col = lane & 15;
-  const int rb = wave / kTrSlices, us = wave % kTrSlices;  // row block, unit slice (units 64 us .. + 63)
+  // row block, unit slice (units 64 us .. + 63); wave-uniform, so that the choices made on them are branches
+  const int rb = __builtin_amdgcn_readfirstlane(wave / kTrSlices);
+  const int us = __builtin_amdgcn_readfirstlane(wave % kTrSlices);
   stage_operands(a.tw2f, w2s, tid);
   if (tid < kTrH) {
     b1s[tid] = a.b1[tid];
@@ -872,6 +874,13 @@ __global__ void __launch_bounds__(kTrThreads) k_train_rows(TrainRowsArgs a) {
       dh[vv] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(w, db, dh[vv], 0, 0, 0);
     }
   }
+  // this slice's H1 chunks (the ReLU mask of dZ1, and the rows this wave stores), picked by a uniform branch
+  u4m hsl[kTrSliceC];
+#pragma unroll
+  for (int k = 0; k < kTrSlices; ++k)
+    if (us == k)
+#pragma unroll
+      for (int cc = 0; cc < kTrSliceC; ++cc) hsl[cc] = h1[kTrSliceC * k + cc];
   u4m d1[kTrSliceC];
 #pragma unroll
   for (int vv = 0; vv < kTrSliceV; ++vv) {
@@ -880,7 +889,7 @@ __global__ void __launch_bounds__(kTrThreads) k_train_rows(TrainRowsArgs a) {
     f4m dv;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      dv[i] = bf16_at(h1[v >> 1], 4 * (v & 1) + i) != 0 ? dh[vv][i] : 0.f;
+      dv[i] = bf16_at(hsl[vv >> 1], 4 * (vv & 1) + i) != 0 ? dh[vv][i] : 0.f;
       const float sb = rows_sum(dv[i]);
       if (col == 0) my[u0 + i] = sb;
     }
@@ -900,7 +909,7 @@ __global__ void __launch_bounds__(kTrThreads) k_train_rows(TrainRowsArgs a) {
   {
     const int64_t row0 = (int64_t)blockIdx.x * kTrRows + 16 * rb;
     uint16_t* st = w2s + wave * ((kTrH / kTrSlices) * kTrStageStride);
-    store_unit_major(&h1[kTrSliceC * us], us, st, a.H1T, a.ldT, row0, lane);
+    store_unit_major(hsl, us, st, a.H1T, a.ldT, row0, lane);
     store_unit_major(d2, us, st, a.dZ2T, a.ldT, row0, lane);
     store_unit_major(d1, us, st, a.dZ1T, a.ldT, row0, lane);
   }
