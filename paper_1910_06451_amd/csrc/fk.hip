@@ -296,10 +296,12 @@ __device__ __forceinline__ void prep_support(const ChainArgs& c, const float* sq
       bf16_split(-2.f * ux, 3, sx);
       bf16_split(-2.f * uy, 3, sy);
       bf16_split(-2.f * uz, 3, sz);
+      // both squared norms as explicit fused multiply-adds in the query side's order, so that their
+      // rounding does not depend on where the compiler contracts
       uint16_t sc[3], sr[3];
-      bf16_split(ux * ux + uy * uy + uz * uz, 3, sc);
+      bf16_split(fmaf(uz, uz, fmaf(uy, uy, ux * ux)), 3, sc);
       const float hx = bf16_to_f(bf16_rne(ux)), hy = bf16_to_f(bf16_rne(uy)), hz = bf16_to_f(bf16_rne(uz));
-      bf16_split(hx * hx + hy * hy + hz * hz, 3, sr);
+      bf16_split(fmaf(hz, hz, fmaf(hy, hy, hx * hx)), 3, sr);
       const uint16_t one = 0x3f80;
       put_b16_row(B16, slot, sl,
                   (b16row8){sx[0], sy[0], sz[0], sx[0], sy[0], sz[0], sx[1], sy[1]},   // k0-7

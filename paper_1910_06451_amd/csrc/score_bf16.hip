@@ -44,23 +44,34 @@ __device__ __forceinline__ Split3 split3(float v) {
   return s;
 }
 
-// Query-side value of k slot `k` (layout mirrors the prepared support operand).
-__device__ __forceinline__ unsigned short query_slot(int k, int variant, const Split3& x, const Split3& y,
-                                                     const Split3& z, const Split3& cq) {
-  const int grp = k / 3, comp = k % 3;
+// Query-side value of k slot K (layout mirrors the prepared support operand);
+// K is a compile-time constant, so only the variant (uniform) is decided at
+// run time.
+template <int K>
+__device__ __forceinline__ unsigned short query_slot(int variant, const Split3& x, const Split3& y, const Split3& z,
+                                                     const Split3& cq) {
+  constexpr int grp = K / 3, comp = K % 3;
   const Split3& v = comp == 0 ? x : (comp == 1 ? y : z);
-  switch (grp) {
-    case 0: return v.h;                          // against hi(p')
-    case 1: return variant >= 1 ? v.m : 0;       // against hi(p')
-    case 2: return variant >= 1 ? v.h : 0;       // against mid(p')
-    case 3: return variant >= 2 ? v.l : 0;       // against hi(p')
-    case 4: return variant >= 2 ? v.h : 0;       // against lo(p')
-    case 5: return variant >= 2 ? v.m : 0;       // against mid(p')
-    case 6: return comp == 0 ? cq.h : (comp == 1 ? cq.m : cq.l);  // against 1
-    case 7: return variant >= 1 ? 0x3f80 : 0;   // 1 against the three bf16 parts of ||u'||^2
-    case 8: return variant == 0 ? 0x3f80 : 0;   // 1 against those of ||hi(u')||^2
-    default: return 0;
-  }
+  if constexpr (grp == 0) return v.h;                        // against hi(u')
+  else if constexpr (grp == 1) return variant >= 1 ? v.m : 0;  // against hi(u')
+  else if constexpr (grp == 2) return variant >= 1 ? v.h : 0;  // against mid(u')
+  else if constexpr (grp == 3) return variant >= 2 ? v.l : 0;  // against hi(u')
+  else if constexpr (grp == 4) return variant >= 2 ? v.h : 0;  // against lo(u')
+  else if constexpr (grp == 5) return variant >= 2 ? v.m : 0;  // against mid(u')
+  else if constexpr (grp == 6) return comp == 0 ? cq.h : (comp == 1 ? cq.m : cq.l);  // against 1
+  else if constexpr (grp == 7) return variant >= 1 ? 0x3f80 : 0;  // 1 against the parts of ||u'||^2
+  else if constexpr (grp == 8) return variant == 0 ? 0x3f80 : 0;  // 1 against those of ||hi(u')||^2
+  else return 0;
+}
+
+// The 8 slots 8 G .. 8 G + 7 that lane group G contributes to the operand.
+template <int G>
+__device__ __forceinline__ u16x8 query_group(int variant, const Split3& x, const Split3& y, const Split3& z,
+                                             const Split3& cq) {
+  return (u16x8){query_slot<8 * G + 0>(variant, x, y, z, cq), query_slot<8 * G + 1>(variant, x, y, z, cq),
+                 query_slot<8 * G + 2>(variant, x, y, z, cq), query_slot<8 * G + 3>(variant, x, y, z, cq),
+                 query_slot<8 * G + 4>(variant, x, y, z, cq), query_slot<8 * G + 5>(variant, x, y, z, cq),
+                 query_slot<8 * G + 6>(variant, x, y, z, cq), query_slot<8 * G + 7>(variant, x, y, z, cq)};
 }
 
 // One wave stages 64 queries and scores them in 4 / QB passes of QB query
@@ -96,17 +107,20 @@ __global__ void __launch_bounds__(256) k_score_bf16(ChainArgs c, const float* __
         const f4 p = lds[wave][16 * (h + b) + col][m];
         const float ux = sg * p[0], uy = sg * p[1], uz = sg * p[2];
         const Split3 sx = split3(ux), sy = split3(uy), sz = split3(uz);
+        // the squared norm as explicit fused multiply-adds (the prepare kernel's order)
         float nq;
         if (variant == 0) {
           const float hx = bf16_f(sx.h), hy = bf16_f(sy.h), hz = bf16_f(sz.h);
-          nq = hx * hx + hy * hy + hz * hz;
+          nq = fmaf(hz, hz, fmaf(hy, hy, hx * hx));
         } else {
-          nq = ux * ux + uy * uy + uz * uz;
+          nq = fmaf(uz, uz, fmaf(uy, uy, ux * ux));
         }
         const Split3 sc = split3(1.f + nq);
-        u16x8 u;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) u[e] = query_slot(8 * g + e, variant, sx, sy, sz, sc);
+        // every group's slots are built with constant slot indices; each lane keeps its own group's
+        const u16x8 u = g == 0 ? query_group<0>(variant, sx, sy, sz, sc)
+                      : g == 1 ? query_group<1>(variant, sx, sy, sz, sc)
+                      : g == 2 ? query_group<2>(variant, sx, sy, sz, sc)
+                               : query_group<3>(variant, sx, sy, sz, sc);
         B[b][m] = __builtin_bit_cast(bf8, u);
       }
     float fpart[QB];
