@@ -436,6 +436,10 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *                       record exchange, 0..64, or -1 (default): adapted by
  *                       each workgroup to how often its first poll came too
  *                       early. Timing only; results do not depend on it.
+ *   "train.single_group" 1 (default): a training set of at most 1,024 points
+ *                       runs in one workgroup of 16 waves, which needs no
+ *                       record exchange; 0: the grid rule above alone.
+ *                       Results do not depend on it.
  *   "train.blocks"      workgroups of the slice kernel, 0 = automatic
  *   "train.threads"     threads per slice-kernel workgroup: 256, 512 or 1024
  *   "score.rational"    1 (default): the scoring kernels (FP32 MFMA and

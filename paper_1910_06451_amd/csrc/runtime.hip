@@ -25,6 +25,7 @@ std::unordered_map<std::string, Knob>& table() {
       {"train.wave_groups", {64, 1, 512, false}},   // grid cap of the wave form
       {"train.waves", {8, 1, 16, true}},            // waves per workgroup of the wave form
       {"train.poll_delay", {-1, -1, 64, false}},    // sleeps before an exchange's first poll, -1 = adaptive
+      {"train.single_group", {1, 0, 1, false}},     // 1: a set that fits one workgroup runs in one
       {"score.rational", {1, 0, 1, false}},        // 1 = running-fraction sum where the reach bound allows it
       {"score.bf16_blocks", {2, 2, 4, true}},      // query blocks resident per pass of the BF16 score kernel
       {"batch.shape_cache", {1, 0, 1, false}},     // 1 = batch autotune reuses a shape tuned for the same kind

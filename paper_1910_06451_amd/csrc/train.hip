@@ -865,58 +865,62 @@ __global__ void __launch_bounds__(MULTI ? 1024 / PT : 64) k_train_wave(TrainStat
       } else if constexpr (MULTI) {
         mine = wave_allreduce<16>(lane < nw ? sh[lane] : rec_empty<T>());
       }
-      const unsigned long long tag = rec_tag(it);
-      unsigned long long* slot = words + (size_t)(it & 1) * G * K;
-      if (lane < K)
-        __hip_atomic_store(slot + (size_t)me * K + lane, tag | RecWords<T>::get(mine, lane), __ATOMIC_RELAXED,
-                           __HIP_MEMORY_SCOPE_AGENT);
-      unsigned long long pay[CH][K];
-      bool ready[CH];
-#pragma unroll
-      for (int c = 0; c < CH; ++c) ready[c] = c * 64 + lane >= (int)G;
-      bool ok = true;
-      for (int q = 0; q < delay; ++q) __builtin_amdgcn_s_sleep(1);
-      int polls = 0;
-      const long long t0 = wall_clock64();
-      while (true) {
-        ++polls;
-        bool all = true;
-#pragma unroll
-        for (int c = 0; c < CH; ++c) {
-          if (!ready[c]) {
-            const unsigned long long* rw = slot + (size_t)(c * 64 + lane) * K;
-            bool rd = true;
-#pragma unroll
-            for (int k = 0; k < K; ++k) {
-              pay[c][k] = __hip_atomic_load(rw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-              rd = rd && rec_tagged(pay[c][k], tag);
-            }
-            ready[c] = rd;
-          }
-          all = all && ready[c];
-        }
-        if (__all(all)) break;
-        __builtin_amdgcn_s_sleep(1);
-        if (wall_clock64() - t0 > st.timeout) {
-          ok = false;
-          break;
-        }
-      }
-      if (st.poll_delay < 0) {
-        if (polls > 1) {
-          delay = delay + 2 < kMaxPollDelay ? delay + 2 : kMaxPollDelay;
-          early_ok = 0;
-        } else if (++early_ok == 4) {
-          delay = delay > 0 ? delay - 1 : 0;
-          early_ok = 0;
-        }
-      }
       Rec<T> gr = rec_empty<T>();
-      if (ok) {
+      bool ok = true;
+      if (G == 1) {
+        gr = mine;  // the set's only workgroup: its record is the set's, nothing to exchange
+      } else {
+        const unsigned long long tag = rec_tag(it);
+        unsigned long long* slot = words + (size_t)(it & 1) * G * K;
+        if (lane < K)
+          __hip_atomic_store(slot + (size_t)me * K + lane, tag | RecWords<T>::get(mine, lane), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+        unsigned long long pay[CH][K];
+        bool ready[CH];
 #pragma unroll
-        for (int c = 0; c < CH; ++c)
-          if (c * 64 < (int)G && c * 64 + lane < (int)G) rec_merge(gr, RecWords<T>::make(pay[c]));
-        gr = wave_allreduce(gr);
+        for (int c = 0; c < CH; ++c) ready[c] = c * 64 + lane >= (int)G;
+        for (int q = 0; q < delay; ++q) __builtin_amdgcn_s_sleep(1);
+        int polls = 0;
+        const long long t0 = wall_clock64();
+        while (true) {
+          ++polls;
+          bool all = true;
+#pragma unroll
+          for (int c = 0; c < CH; ++c) {
+            if (!ready[c]) {
+              const unsigned long long* rw = slot + (size_t)(c * 64 + lane) * K;
+              bool rd = true;
+#pragma unroll
+              for (int k = 0; k < K; ++k) {
+                pay[c][k] = __hip_atomic_load(rw + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                rd = rd && rec_tagged(pay[c][k], tag);
+              }
+              ready[c] = rd;
+            }
+            all = all && ready[c];
+          }
+          if (__all(all)) break;
+          __builtin_amdgcn_s_sleep(1);
+          if (wall_clock64() - t0 > st.timeout) {
+            ok = false;
+            break;
+          }
+        }
+        if (st.poll_delay < 0) {
+          if (polls > 1) {
+            delay = delay + 2 < kMaxPollDelay ? delay + 2 : kMaxPollDelay;
+            early_ok = 0;
+          } else if (++early_ok == 4) {
+            delay = delay > 0 ? delay - 1 : 0;
+            early_ok = 0;
+          }
+        }
+        if (ok) {
+#pragma unroll
+          for (int c = 0; c < CH; ++c)
+            if (c * 64 < (int)G && c * 64 + lane < (int)G) rec_merge(gr, RecWords<T>::make(pay[c]));
+          gr = wave_allreduce(gr);
+        }
       }
       d.action = 0;
       d.i = -1;
@@ -1080,7 +1084,11 @@ static bool wave_shape(int64_t N, int M, int D, int nw, int64_t cap, int ncu, co
   const bool multi = nw > 1;
   auto groups = [&](int w, int pt) { return (N + 64ll * w * pt - 1) / (64ll * w * pt); };
   int PT = 1, waves = multi ? nw : 1;
-  if (multi) {
+  // a set that fits one workgroup of 16 waves (one point per lane) runs in one: the kernel then skips the
+  // record exchange
+  if (multi && groups(waves, 1) > 1 && groups(16, 1) == 1 && tune_get("train.single_group") == 1) {
+    waves = 16;
+  } else if (multi) {
     while (waves < 16 && groups(waves, PT) > cap) waves *= 2;
   } else {
     while (PT < 16 && groups(waves, PT) > cap) PT *= 2;

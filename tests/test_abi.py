@@ -71,6 +71,11 @@ def test_host_only_entry_points(lib):
     assert lib.fastron_tune_set(b"train.poll_delay", 65) == nat.FASTRON_EINVAL
     assert lib.fastron_tune_set(b"train.poll_delay", 12) == nat.FASTRON_OK
     assert lib.fastron_tune_set(b"train.poll_delay", -1) == nat.FASTRON_OK
+    # one workgroup for a set that fits 16 waves (1) or the grid rule alone (0)
+    assert lib.fastron_tune_get(b"train.single_group") == 1
+    assert lib.fastron_tune_set(b"train.single_group", 2) == nat.FASTRON_EINVAL
+    assert lib.fastron_tune_set(b"train.single_group", 0) == nat.FASTRON_OK
+    assert lib.fastron_tune_set(b"train.single_group", 1) == nat.FASTRON_OK
     assert lib.fastron_model_bytes(-1, 8) == -1
     assert lib.fastron_model_bytes(4000, 17) == -1
     assert lib.fastron_model_bytes(4000, 8) > 4000 * 8 * 4

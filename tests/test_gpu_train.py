@@ -49,7 +49,7 @@ def test_gram_update_parity(oracle_mod, dev):
     np.testing.assert_allclose(F.cpu().numpy(), F0 - 0.75 * ref, atol=2e-6)
 
 
-TRAIN_KEYS = ("train.kernel", "train.waves", "train.wave_groups", "train.poll_delay")
+TRAIN_KEYS = ("train.kernel", "train.waves", "train.wave_groups", "train.poll_delay", "train.single_group")
 
 
 class launch_shape:
@@ -92,6 +92,29 @@ def test_train_fp64_step_exact(oracle_mod, dev, beta, shape):
     np.testing.assert_array_equal(out["alpha"].cpu().numpy(), ref["alpha"])
     np.testing.assert_array_equal(out["F"].cpu().numpy(), ref["F"])
     np.testing.assert_array_equal(out["support"].cpu().numpy(), ref["support"])
+
+
+def test_train_single_workgroup(oracle_mod, dev):
+    """A training set that fits one workgroup of 16 waves (here 900 points) runs in one and skips the record
+    exchange: the FP64 trajectory equals the oracle's with and without that rule (two workgroups of 8 waves),
+    and the FP32 weights and scores are bit-identical between the two shapes."""
+    arm = wl.arm_7dof()
+    q, P32, y = labelled_set(oracle_mod, arm, "train7one", 900, 20, 0.1, 0.25)
+    ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 30.0, trace=True)
+    P, yd = torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev)
+    fp32 = {}
+    for single in (1, 0):
+        announce(f"train 7dof N=900 single_group={single}")
+        with launch_shape(train_single_group=single):
+            out = api.train_points(P, yd, 30.0, fp64=True, trace_cap=ref["updates"] + 10)
+            fp32[single] = api.train_points(P, yd, 30.0)
+        assert out["updates"] == ref["updates"] and out["converged"] == ref["converged"]
+        np.testing.assert_array_equal(out["trace_action"].cpu().numpy(), ref["trace_action"])
+        np.testing.assert_array_equal(out["trace_index"].cpu().numpy(), ref["trace_index"])
+        np.testing.assert_array_equal(out["alpha"].cpu().numpy(), ref["alpha"])
+        np.testing.assert_array_equal(out["F"].cpu().numpy(), ref["F"])
+    assert fp32[1]["updates"] == fp32[0]["updates"]
+    assert torch.equal(fp32[1]["alpha"], fp32[0]["alpha"]) and torch.equal(fp32[1]["F"], fp32[0]["F"])
 
 
 @pytest.mark.parametrize("shape", [(8, 64), (1, 256), (4, 2)], ids=lambda s: f"waves{s[0]}-cap{s[1]}")
