@@ -96,7 +96,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=10)  # the clocks ramp over the first ~30 ms of work
     ap.add_argument("--S", type=int, default=4000)
     ap.add_argument("--N", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
