@@ -1050,8 +1050,11 @@ static const void* wave_kernel_mm(int PT) {
       case 1: return reinterpret_cast<const void*>(k_train_wave<T, 1, MM, false>);
       case 2: return reinterpret_cast<const void*>(k_train_wave<T, 2, MM, false>);
       case 4: return reinterpret_cast<const void*>(k_train_wave<T, 4, MM, false>);
-      case 8: return reinterpret_cast<const void*>(k_train_wave<T, 8, MM, false>);
-      default: return reinterpret_cast<const void*>(k_train_wave<T, 16, MM, false>);
+      default:
+        // coordinates stay in registers only up to 4 points per lane (the launch shapes never ask for more)
+        if constexpr (MM > 0) return nullptr;
+        else return PT == 8 ? reinterpret_cast<const void*>(k_train_wave<T, 8, 0, false>)
+                            : reinterpret_cast<const void*>(k_train_wave<T, 16, 0, false>);
     }
   }
 }
@@ -1099,6 +1102,7 @@ static bool wave_shape(int64_t N, int M, int D, int nw, int64_t cap, int ncu, co
   if (*G > (int64_t)(multi ? kMultiChunks<T> : kWaveChunks) * 64) return false;
   const int mm = (D == 3 && PT <= 4 && (M == 4 || M == 8)) ? M : 0;
   *kfn = wave_kernel<T>(PT, mm, multi);
+  if (*kfn == nullptr) return false;
   *lds_bytes = mm ? 0 : (size_t)*chunk * M * D * sizeof(float);
   if (*lds_bytes > 48 * 1024) *lds_bytes = 0;
   *threads = nt;
@@ -1297,6 +1301,7 @@ static fastron_status train_batch_impl(const float* P, const int8_t* y, int32_t 
       if (largest > (int64_t)(multi ? kMultiChunks<float> : kWaveChunks) * 64) continue;
       const int mm = (PT <= 4 && (M == 4 || M == 8)) ? M : 0;
       const void* fn = wave_kernel<float>(PT, mm, multi == 1);
+      if (fn == nullptr) continue;
       size_t lds = mm ? 0 : (size_t)chunk_try * 3 * M * sizeof(float);
       if (lds > 48 * 1024) lds = 0;
       int per_cu = 0;
