@@ -35,8 +35,11 @@ namespace fastron {
 constexpr int kScoreBlocks = 2;
 constexpr int kScoreQueriesPerBlock = kWavesPerBlock * 16 * kScoreBlocks;
 
+// 5 waves per SIMD (96 VGPRs) up to 8 moving points; with the FP32 chain (fewer than 7 joints) 8 points need
+// more registers, so 4 there
 template <int MM, typename R, bool RAT>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MM <= 8 ? 5 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MM < 8 || sizeof(R) == 8 ? (MM <= 8 ? 5 : 1)
+                                                                                                     : (MM <= 8 ? 4 : 1))))
 k_score_mfma(ChainArgs c, const float* __restrict__ q, int64_t N, const char* __restrict__ blob, int64_t ntiles,
              int Mp, float gamma, float* __restrict__ f, int8_t* __restrict__ label) {
   static_assert(kScoreQueriesPerBlock % 64 == 0, "whole waves stage the workgroup's queries");
