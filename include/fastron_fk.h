@@ -425,7 +425,8 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *                       (also used when the wave form's grid would exceed
  *                       its limits)
  *   "train.waves"       waves per workgroup the wave form starts from: 1, 2,
- *                       4, 8 (default) or 16; 1 keeps single-wave workgroups
+ *                       4, 8 (default) or 16 (FP64 workgroups stop at 8);
+ *                       1 keeps single-wave workgroups
  *                       (which also take over when the multi-wave grid would
  *                       exceed 256 workgroups, 128 in FP64)
  *   "train.wave_groups" grid cap of the wave form, 1..512 (64): the waves per
@@ -437,8 +438,9 @@ fastron_status fastron_label_capsule_box(const fastron_chain* chain, const float
  *                       each workgroup to how often its first poll came too
  *                       early. Timing only; results do not depend on it.
  *   "train.single_group" 1 (default): a training set of at most 1,024 points
- *                       runs in one workgroup of 16 waves, which needs no
- *                       record exchange; 0: the grid rule above alone.
+ *                       (512 in FP64) runs in one workgroup of 16 waves (8),
+ *                       which needs no record exchange; 0: the grid rule
+ *                       above alone.
  *                       Results do not depend on it.
  *   "train.blocks"      workgroups of the slice kernel, 0 = automatic
  *   "train.threads"     threads per slice-kernel workgroup: 256, 512 or 1024

@@ -733,7 +733,7 @@ constexpr int kMultiMaxPT = 4;  // points per lane of multi-wave workgroups in m
 // points' coordinates in registers for the whole run; MM = 0: any M, the
 // coordinates come from LDS (or global memory) in each column pass.
 template <typename T, int PT, int MM, bool MULTI>
-__global__ void __launch_bounds__(MULTI ? 1024 / PT : 64) k_train_wave(TrainState<T> st) {
+__global__ void __launch_bounds__(MULTI ? (sizeof(T) == 8 ? 512 : 1024 / PT) : 64) k_train_wave(TrainState<T> st) {
   constexpr int K = RecWords<T>::K;
   constexpr int CH = MULTI ? kMultiChunks<T> : kWaveChunks;
   // FP32 with several waves: the waves' records meet as LDS keys and per-lane
@@ -1087,12 +1087,15 @@ static bool wave_shape(int64_t N, int M, int D, int nw, int64_t cap, int ncu, co
   const bool multi = nw > 1;
   auto groups = [&](int w, int pt) { return (N + 64ll * w * pt - 1) / (64ll * w * pt); };
   int PT = 1, waves = multi ? nw : 1;
-  // a set that fits one workgroup of 16 waves (one point per lane) runs in one: the kernel then skips the
-  // record exchange
-  if (multi && groups(waves, 1) > 1 && groups(16, 1) == 1 && tune_get("train.single_group") == 1) {
-    waves = 16;
+  // FP64 workgroups stop at 8 waves (512 threads leave its register-held coordinates room without spills)
+  const int max_waves = sizeof(T) == 8 ? 8 : 16;
+  if (multi && waves > max_waves) waves = max_waves;
+  // a set that fits one workgroup of the largest size (one point per lane) runs in one: the kernel then
+  // skips the record exchange
+  if (multi && groups(waves, 1) > 1 && groups(max_waves, 1) == 1 && tune_get("train.single_group") == 1) {
+    waves = max_waves;
   } else if (multi) {
-    while (waves < 16 && groups(waves, PT) > cap) waves *= 2;
+    while (waves < max_waves && groups(waves, PT) > cap) waves *= 2;
   } else {
     while (PT < 16 && groups(waves, PT) > cap) PT *= 2;
   }

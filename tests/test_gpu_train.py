@@ -68,9 +68,9 @@ class launch_shape:
             api.tune_set(k, v)
 
 
-# (waves per workgroup, workgroup cap): the default multi-wave shape (8 waves), single-wave workgroups with 1
-# and with 16 points per lane (the latter with the coordinates outside registers), and 16 waves
-SHAPES = [(8, 64), (1, 256), (1, 2), (16, 1)]
+# (waves per workgroup, workgroup cap): the default multi-wave shape (8 waves, the FP64 limit), single-wave
+# workgroups with 1 and with 16 points per lane (the latter with the coordinates outside registers), and 4 waves
+SHAPES = [(8, 64), (1, 256), (1, 2), (4, 256)]
 
 
 @pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"waves{s[0]}-cap{s[1]}")
@@ -95,33 +95,37 @@ def test_train_fp64_step_exact(oracle_mod, dev, beta, shape):
 
 
 def test_train_single_workgroup(oracle_mod, dev):
-    """A training set that fits one workgroup of 16 waves (here 900 points) runs in one and skips the record
-    exchange: the FP64 trajectory equals the oracle's with and without that rule (two workgroups of 8 waves),
-    and the FP32 weights and scores are bit-identical between the two shapes."""
+    """A training set that fits one workgroup (FP32: 16 waves, here 900 points) runs in one, and a set with one
+    workgroup skips the record exchange: the FP32 weights and scores are bit-identical with and without that
+    rule (one workgroup against two of 8 waves), and the FP64 trajectory equals the oracle's with one workgroup
+    (the first 480 points: FP64 workgroups stop at 8 waves) and with two (all 900)."""
     arm = wl.arm_7dof()
     q, P32, y = labelled_set(oracle_mod, arm, "train7one", 900, 20, 0.1, 0.25)
-    ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 30.0, trace=True)
     P, yd = torch.from_numpy(P32).to(dev), torch.from_numpy(y).to(dev)
     fp32 = {}
     for single in (1, 0):
-        announce(f"train 7dof N=900 single_group={single}")
+        announce(f"train fp32 7dof N=900 single_group={single}")
         with launch_shape(train_single_group=single):
-            out = api.train_points(P, yd, 30.0, fp64=True, trace_cap=ref["updates"] + 10)
             fp32[single] = api.train_points(P, yd, 30.0)
+    assert fp32[1]["updates"] == fp32[0]["updates"]
+    assert torch.equal(fp32[1]["alpha"], fp32[0]["alpha"]) and torch.equal(fp32[1]["F"], fp32[0]["F"])
+    for n in (480, 900):
+        ref = oracle_mod.fastron_update(P32[:n].astype(np.float64), y[:n], 30.0, trace=True)
+        announce(f"train fp64 7dof N={n}")
+        out = api.train_points(P[:n].contiguous(), yd[:n].contiguous(), 30.0, fp64=True,
+                               trace_cap=ref["updates"] + 10)
         assert out["updates"] == ref["updates"] and out["converged"] == ref["converged"]
         np.testing.assert_array_equal(out["trace_action"].cpu().numpy(), ref["trace_action"])
         np.testing.assert_array_equal(out["trace_index"].cpu().numpy(), ref["trace_index"])
         np.testing.assert_array_equal(out["alpha"].cpu().numpy(), ref["alpha"])
         np.testing.assert_array_equal(out["F"].cpu().numpy(), ref["F"])
-    assert fp32[1]["updates"] == fp32[0]["updates"]
-    assert torch.equal(fp32[1]["alpha"], fp32[0]["alpha"]) and torch.equal(fp32[1]["F"], fp32[0]["F"])
 
 
 @pytest.mark.parametrize("shape", [(8, 64), (1, 256), (4, 2)], ids=lambda s: f"waves{s[0]}-cap{s[1]}")
 def test_train_fp64_step_exact_7dof(oracle_mod, dev, shape):
     """7-DOF arm (8 control points, kept in registers by the kernel), 2,500 labelled configurations, 20 cubes,
     gamma = 30: the FP64 device trajectory equals the oracle's in the default multi-wave shape, with
-    single-wave workgroups, and with waves grown from 4 to 16 by a small grid cap."""
+    single-wave workgroups, and with waves grown from 4 to 8 (the FP64 limit) by a small grid cap."""
     arm = wl.arm_7dof()
     q, P32, y = labelled_set(oracle_mod, arm, "train7x", 2500, 20, 0.1, 0.25)
     ref = oracle_mod.fastron_update(P32.astype(np.float64), y, 30.0, trace=True)
