@@ -616,7 +616,7 @@ __global__ void __launch_bounds__(kInfTile) k_mlp_screen_fused(InferArgs a) {
 //                  rows contiguous) for the weight gradients, and
 //                  per-workgroup sums over its rows for the bias and head
 //                  gradients and the loss. Splitting the units fills the
-//                  part with a batch of 8,192 rows: 256 workgroups of 8 waves
+//                  device with a batch of 8,192 rows: 256 workgroups of 8 waves
 //                  (two 16-row blocks), all sharing one staged copy of the
 //                  W2 operands, instead of one wave per 16 rows.
 //   k_train_wgrad  gW2 = H1^T dZ2 and gW1 = X^T dZ1, contracting over the

@@ -1072,8 +1072,10 @@ static const void* wave_kernel(int PT, int mm, bool multi) {
 }
 
 // Launch shape of the wave form for one training set of N points. Several
-// waves per workgroup (nw > 1): one point per lane, the waves doubling from nw
-// up to 16 while the grid exceeds `cap` workgroups (more waves spread a
+// waves per workgroup (nw > 1): one point per lane; a set that fits one
+// workgroup of the largest size runs in one (no record exchange), else the
+// waves double from nw up to 16 (8 in FP64) while the grid exceeds `cap`
+// workgroups (more waves spread a
 // workgroup's column over its CU's SIMDs; a workgroup holds at most 1,024
 // points in this form whatever the split between waves and points per lane,
 // so more points per lane would only lengthen every wave's column). Single-wave
