@@ -293,35 +293,41 @@ def test_bf16_resident_blocks_setting(dev):
     assert torch.equal(out[2][0], out[4][0]) and torch.equal(out[2][1], out[4][1])
 
 
-def test_score_edge_cases(oracle_mod, dev):
+@pytest.mark.parametrize("flags", [api.SCORE_FP32, api.SCORE_VALU, api.SCORE_BF16 | api.BF16_PLAIN,
+                                   api.SCORE_BF16 | api.BF16_SPLIT3], ids=["fp32", "valu", "bf16plain", "bf16split3"])
+def test_score_edge_cases(oracle_mod, dev, flags):
+    """Empty model, empty query batch, every control point fixed to the base, a single moving point; in every
+    form of the score (the BF16 forms against their own bounds)."""
     arm = wl.arm_7dof()
     gamma = 10.0
     q = torch.from_numpy(wl.configs("edge/q", 100, 7)).to(dev)
-    announce("edge: empty model")
-    f, lab = api.fk_score(arm, torch.zeros((0, 7), device=dev), torch.zeros(0, device=dev), gamma, q)
+    announce(f"edge: empty model flags={flags}")
+    f, lab = api.fk_score(arm, torch.zeros((0, 7), device=dev), torch.zeros(0, device=dev), gamma, q, flags=flags)
     assert torch.all(f == 0) and torch.all(lab == 1)
-    announce("edge: empty query batch")
-    f, lab = api.fk_score(arm, torch.zeros((3, 7), device=dev), torch.ones(3, device=dev), gamma, q[:0])
+    announce(f"edge: empty query batch flags={flags}")
+    f, lab = api.fk_score(arm, torch.zeros((3, 7), device=dev), torch.ones(3, device=dev), gamma, q[:0], flags=flags)
     assert f.shape == (0,)
     # every control point fixed to the base: K_FK = 1 for every pair, f = sum(alpha)
     fixed = wl.arm_7dof()
     fixed.frames = np.zeros(3, dtype=np.int32)
     al = torch.tensor([0.5, -2.0, 0.25], device=dev)
-    announce("edge: all points fixed")
-    f, _ = api.fk_score(fixed, torch.zeros((3, 7), device=dev), al, gamma, q)
+    announce(f"edge: all points fixed flags={flags}")
+    f, _ = api.fk_score(fixed, torch.zeros((3, 7), device=dev), al, gamma, q, flags=flags)
     torch.testing.assert_close(f, torch.full_like(f, -1.25))
     # a single moving point (M = 1)
     one = wl.arm_7dof()
     one.frames = np.array([7], dtype=np.int32)
     sq, alp = wl.model("edge/one", 50, 7)
-    announce("edge: M = 1")
-    f, lab = api.fk_score(one, torch.from_numpy(sq).to(dev), torch.from_numpy(alp).to(dev), gamma, q)
+    announce(f"edge: M = 1 flags={flags}")
+    f, lab = api.fk_score(one, torch.from_numpy(sq).to(dev), torch.from_numpy(alp).to(dev), gamma, q, flags=flags)
     dh = oracle_dh(oracle_mod, one)
     ref = oracle_mod.score(dh, one.frames, sq.astype(np.float64), alp.astype(np.float64), gamma,
                            q.cpu().numpy().astype(np.float64))
     Ps = oracle_mod.control_points(dh, one.frames, sq.astype(np.float64))
     Pq = oracle_mod.control_points(dh, one.frames, q.cpu().numpy().astype(np.float64))
-    check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, error_bound(Ps, alp, gamma, Pq), min_agree=0.99)
+    tol = (bf16_error_bound(Ps, alp, gamma, Pq, api.BF16_PLAIN) if flags == (api.SCORE_BF16 | api.BF16_PLAIN)
+           else error_bound(Ps, alp, gamma, Pq))
+    check_scores(f.cpu().numpy(), lab.cpu().numpy(), ref, tol, min_agree=0.8 if flags & api.SCORE_BF16 else 0.99)
 
 
 def _random_chain(name, n, frames, offsets=False, prismatic=()):
