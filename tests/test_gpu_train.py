@@ -49,6 +49,25 @@ def test_gram_update_parity(oracle_mod, dev):
     np.testing.assert_allclose(F.cpu().numpy(), F0 - 0.75 * ref, atol=2e-6)
 
 
+@pytest.mark.parametrize("N,i", [(1, 0), (257, 0), (257, 256)])
+def test_gram_update_edges(oracle_mod, dev, N, i):
+    """Gram column at the degenerate sizes: one point (K(x, x) = 1), a set one past a block of 256, the chosen
+    point first and last; F updated alone (no column requested) and the column alone (no F)."""
+    arm = wl.arm_7dof()
+    dh = oracle_dh(oracle_mod, arm)
+    q = wl.configs(f"gram_edge{N}", N, 7)
+    P32 = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
+    P = torch.from_numpy(P32).to(dev)
+    ref = np.array([oracle_mod.k_fk(P32[j].astype(np.float64), P32[i].astype(np.float64), 10.0) for j in range(N)])
+    announce(f"gram_update edges N={N} i={i}")
+    F0 = wl.rng(f"gram_edge{N}/F").standard_normal(N).astype(np.float32)
+    F = torch.from_numpy(F0).to(dev)
+    assert api.gram_update_points(P, 10.0, i, 0.5, F=F, want_kcol=False) is None
+    np.testing.assert_allclose(F.cpu().numpy(), F0 + 0.5 * ref, atol=2e-6)
+    kcol = api.gram_update_points(P, 10.0, i, 0.0).cpu().numpy()
+    assert np.abs(kcol - ref).max() <= 1e-6 and kcol[i] == 1.0
+
+
 TRAIN_KEYS = ("train.kernel", "train.waves", "train.wave_groups", "train.poll_delay", "train.single_group")
 
 
