@@ -13,19 +13,29 @@ from conftest import announce, oracle_dh
 pytestmark = pytest.mark.gpu
 
 
-def _data(oracle_mod, N, name, n_cubes=20):
-    arm = wl.arm_7dof()
+def _arm9():
+    """A 9-joint chain with a point on every frame: 10 points, 30 input features (the widest the three-kernel
+    training step takes is 32)."""
+    g = wl.rng("mlp_arm9")
+    n = 9
+    return wl.Arm(a=g.uniform(0.1, 0.25, size=n), alpha=g.choice(np.array([0.0, np.pi / 2, -np.pi / 2]), size=n),
+                  d=np.zeros(n), theta=np.zeros(n), joint_type=np.zeros(n, dtype=np.int32),
+                  frames=np.arange(n + 1, dtype=np.int32))
+
+
+def _data(oracle_mod, N, name, n_cubes=20, arm=None):
+    arm = arm if arm is not None else wl.arm_7dof()
     dh = oracle_dh(oracle_mod, arm)
-    q = wl.configs(name, N, 7)
+    q = wl.configs(name, N, arm.n)
     lo, hi = wl.cubes("bench7/cubes", n_cubes, 0.1, 0.25)
     y, _ = oracle_mod.capsule_box_labels(dh, q.astype(np.float64), arm.radius, lo, hi)
     P = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).astype(np.float32)
     return arm, q, P, y.astype(np.int8)
 
 
-def _grad_setup(oracle_mod, dev, N, name, max_rows, H=256):
-    arm, q, P, y = _data(oracle_mod, N, name)
-    d_in = 24
+def _grad_setup(oracle_mod, dev, N, name, max_rows, H=256, arm=None):
+    arm, q, P, y = _data(oracle_mod, N, name, arm=arm)
+    d_in = 3 * arm.M
     params = wl.mlp_init(d_in, H, name=f"{name}_init")
     g = wl.rng(f"{name}/biases")
     params[d_in * H:d_in * H + H] = g.normal(0, 0.1, H)                   # b1
@@ -62,25 +72,19 @@ def ADAM_F32(lr):
     return dict(lr=f(lr), beta1=f(0.9), beta2=f(0.999), eps=f(1e-8))
 
 
-@pytest.mark.parametrize("H", [256, 128])
-def test_forward_and_gradients_match_oracle(oracle_mod, dev, H):
-    """Forward logits, loss and all six gradients of one batch against the oracle, element by element: the
-    oracle's BF16 forms round to bfloat16 where the device does, and every difference must lie within the bound
-    propagated from the device's FP32 arithmetic, the bfloat16 roundings that this arithmetic can tip and the
-    ReLU decisions it can flip (tests/mlp_bounds.py). Nonzero biases, so that every bias path carries weight.
-    Also reported: the relative L2 distance to the unrounded FP64 network. Hidden width 256 runs the
-    three-kernel training step, 128 the staged GEMM path."""
-    net, P, X, y, params, ps, mu, sd = _grad_setup(oracle_mod, dev, 700, "mlp_grad", 1024, H)
+def _forward_and_gradients(oracle_mod, dev, H, name, arm=None):
+    net, P, X, y, params, ps, mu, sd = _grad_setup(oracle_mod, dev, 700, name, 1024, H, arm=arm)
+    d_in = X.shape[1]
     P_d = torch.from_numpy(P).to(dev)
-    announce("mlp forward")
+    announce(f"mlp forward d_in={d_in} H={H}")
     z = net.forward(P_d).cpu().numpy().astype(np.float64)
-    announce("mlp gradients")
+    announce(f"mlp gradients d_in={d_in} H={H}")
     loss = net.gradients(P_d, torch.from_numpy(y).to(dev))
     _, g, _, _ = net.get_params(dev)
     g = g.cpu().numpy().astype(np.float64)
     z_ref, g_ref, fb, Eg, info = _oracle_grads(ps, X, y, mu, sd)
     Ez = 1.25 * fb["E_z"]
-    report = dict(info, z_ratio=float(np.max(np.abs(z - z_ref) / Ez)))
+    report = dict(info, d_in=d_in, z_ratio=float(np.max(np.abs(z - z_ref) / Ez)))
     assert np.all(np.abs(z - z_ref) <= Ez), np.max(np.abs(z - z_ref) / Ez)
     loss_ref = mo.bce_loss(z_ref, y)
     # BCE is 1-Lipschitz in z; the loss is summed in FP32 over 256-row blocks, then in FP64 on the host
@@ -88,7 +92,7 @@ def test_forward_and_gradients_match_oracle(oracle_mod, dev, H):
     z64, c64 = mo.forward(ps, X, mu, sd)
     g64 = mo.backward(ps, c64, z64, y)
     report["logits_rel_l2_vs_fp64"] = float(np.linalg.norm(z - z64) / np.linalg.norm(z64))
-    gs = wl.split_mlp_params(g, 24, H)
+    gs = wl.split_mlp_params(g, d_in, H)
     for k, (a, b, e) in enumerate(zip(gs, g_ref, Eg)):
         err = np.abs(np.ravel(a) - np.ravel(b))
         e = np.ravel(e)
@@ -100,6 +104,26 @@ def test_forward_and_gradients_match_oracle(oracle_mod, dev, H):
         assert np.all(err <= e), (NAMES[k], float(np.max(ratio)))
     print(report)
     net.close()
+
+
+@pytest.mark.parametrize("H", [256, 128])
+def test_forward_and_gradients_match_oracle(oracle_mod, dev, H):
+    """Forward logits, loss and all six gradients of one batch against the oracle, element by element: the
+    oracle's BF16 forms round to bfloat16 where the device does, and every difference must lie within the bound
+    propagated from the device's FP32 arithmetic, the bfloat16 roundings that this arithmetic can tip and the
+    ReLU decisions it can flip (tests/mlp_bounds.py). Nonzero biases, so that every bias path carries weight.
+    Also reported: the relative L2 distance to the unrounded FP64 network. Hidden width 256 runs the
+    three-kernel training step, 128 the staged GEMM path."""
+    _forward_and_gradients(oracle_mod, dev, H, "mlp_grad")
+
+
+@pytest.mark.parametrize("which", ["3dof", "9joint"])
+def test_forward_and_gradients_other_input_widths(oracle_mod, dev, which):
+    """The same element-by-element check at the other input widths of the three-kernel training step: 12
+    features (the 3-DOF arm's 4 points) and 30 (a 9-joint chain's 10 points), where the zero padding of the
+    32-wide layer-1 operand and the standardisation's feature bound matter."""
+    arm = wl.arm_3dof() if which == "3dof" else _arm9()
+    _forward_and_gradients(oracle_mod, dev, 256, f"mlp_grad_{which}", arm=arm)
 
 
 @pytest.mark.parametrize("H", [256, 128])
