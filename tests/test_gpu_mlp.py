@@ -243,37 +243,40 @@ def test_training_learns(oracle_mod, dev):
     net.close()
 
 
-@pytest.mark.parametrize("N", [1, 63, 3001])
-def test_fused_screen_logits(oracle_mod, dev, N):
+@pytest.mark.parametrize("which,N", [("7dof", 1), ("7dof", 63), ("7dof", 3001), ("3dof", 3001)],
+                         ids=["7dof-1", "7dof-63", "7dof-3001", "3dof-3001"])
+def test_fused_screen_logits(oracle_mod, dev, which, N):
     """The fused screening pass (FK + both layers + head in one persistent kernel) against the staged GEMM
     forward on the same control points, and against the FP64 oracle; ragged sizes (one query, less than a
-    wave, several tiles plus a partial one)."""
-    arm = wl.arm_7dof()
+    wave, several tiles plus a partial one), 24 input features (7-DOF arm) and 12 (3-DOF arm, FP32 chain)."""
+    arm = wl.arm_7dof() if which == "7dof" else wl.arm_3dof()
+    d_in = 3 * arm.M
     dh = oracle_dh(oracle_mod, arm)
-    q = wl.configs(f"fused_screen/{N}", N, 7)
+    q = wl.configs(f"fused_screen/{which}/{N}", N, arm.n)
     q_d = torch.from_numpy(q).to(dev)
     P_d = api.fk_points(arm, q_d)
-    params = wl.mlp_init(24, 256, name="fused_screen_init")
-    params[24 * 256:24 * 256 + 256] = wl.rng("fused_screen/b1").normal(0, 0.1, 256)  # nonzero biases
-    params[-257:-1] = wl.rng("fused_screen/w3").normal(0, 0.2, 256)
-    P_stats = api.fk_points(arm, torch.from_numpy(wl.configs("fused_screen/stats", 4096, 7)).to(dev))
-    net = api.MLP(24, 256, max_rows=4096)
+    params = wl.mlp_init(d_in, 256, name=f"fused_screen_init_{which}")
+    params[d_in * 256:d_in * 256 + 256] = wl.rng(f"fused_screen/b1/{which}").normal(0, 0.1, 256)  # nonzero biases
+    params[-257:-1] = wl.rng(f"fused_screen/w3/{which}").normal(0, 0.2, 256)
+    P_stats = api.fk_points(arm, torch.from_numpy(wl.configs(f"fused_screen/stats/{which}", 4096, arm.n)).to(dev))
+    net = api.MLP(d_in, 256, max_rows=4096)
     net.set_params(torch.from_numpy(params).to(dev))
     net.fit_standardisation(P_stats)
-    sq, al = wl.model("fused_screen_model", 64, 7)
+    sq, al = wl.model(f"fused_screen_model_{which}", 64, arm.n)
     model = api.support_prep(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), 10.0)
-    announce(f"fused screen N={N}")
+    announce(f"fused screen {which} N={N}")
     lab, z, fb, nf = net.screen(arm, model, q_d, 0.0)
-    announce(f"staged forward N={N}")
+    announce(f"staged forward {which} N={N}")
     z_st = net.forward(P_d)
     z, z_st = z.cpu().numpy().astype(np.float64), z_st.cpu().numpy().astype(np.float64)
     diff = np.linalg.norm(z - z_st) / max(np.linalg.norm(z_st), 1e-30)
     _, _, mu, sd = net.get_params(dev)
-    ps = [p_.astype(np.float64) for p_ in wl.split_mlp_params(params, 24)]
-    X = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).reshape(N, 24)
+    ps = [p_.astype(np.float64) for p_ in wl.split_mlp_params(params, d_in)]
+    X = oracle_mod.control_points(dh, arm.frames, q.astype(np.float64)).reshape(N, d_in)
     z_ref, _ = mo.forward(ps, X, mu.cpu().numpy().astype(np.float64), sd.cpu().numpy().astype(np.float64))
     rel = np.linalg.norm(z - z_ref) / max(np.linalg.norm(z_ref), 1e-30)
-    print(dict(N=N, rel_vs_staged=float(diff), rel_vs_oracle=float(rel), max_abs_vs_staged=float(np.abs(z - z_st).max())))
+    print(dict(which=which, N=N, rel_vs_staged=float(diff), rel_vs_oracle=float(rel),
+               max_abs_vs_staged=float(np.abs(z - z_st).max())))
     assert diff < 1e-3, diff
     assert rel < 2e-2, rel
     assert nf == 0
