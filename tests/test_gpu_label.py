@@ -41,3 +41,41 @@ def test_labels_match_oracle(oracle_mod, dev, arm_name, N, n_cubes):
         print(dict(collision_rate=float(np.mean(ref == 1)), near_boundary=int(near.sum())))
     else:
         assert np.all(lab == -1)
+
+
+def _prismatic_chain():
+    g = wl.rng("label_chain6")
+    n = 6
+    jt = np.zeros(n, dtype=np.int32)
+    jt[[1, 4]] = 1
+    return wl.Arm(a=g.uniform(0.1, 0.25, n), alpha=g.choice(np.array([0.0, np.pi / 2, -np.pi / 2]), size=n),
+                  d=g.uniform(-0.1, 0.1, n), theta=g.uniform(-0.5, 0.5, n), joint_type=jt,
+                  frames=np.arange(n + 1, dtype=np.int32))
+
+
+@pytest.mark.parametrize("case", ["cubes_and_point_box", "enclosing_box"])
+def test_labels_general_chain(oracle_mod, dev, case):
+    """A 6-joint chain with two prismatic joints (joint values as lengths), a ragged batch; random cubes plus a
+    degenerate box (lo = hi, a single point), or one box enclosing the whole reach (every configuration
+    collides, every clearance negative)."""
+    arm = _prismatic_chain()
+    q = wl.configs(f"label_chain6/{case}", 1001, arm.n, lo=-1.0, hi=1.0)
+    if case == "cubes_and_point_box":
+        lo, hi = wl.cubes("label_chain6/cubes", 8, 0.1, 0.25)
+        p = np.array([[0.15, 0.05, 0.1]])
+        lo, hi = np.concatenate([lo, p]), np.concatenate([hi, p])
+    else:
+        lo, hi = np.full((1, 3), -10.0), np.full((1, 3), 10.0)
+    announce(f"label prismatic chain {case}")
+    lab, clr = api.label_capsule_box(arm, torch.from_numpy(q).to(dev), arm.radius, lo, hi)
+    lab, clr = lab.cpu().numpy(), clr.cpu().numpy()
+    lab_only, _ = api.label_capsule_box(arm, torch.from_numpy(q).to(dev), arm.radius, lo, hi, want_clearance=False)
+    np.testing.assert_array_equal(lab_only.cpu().numpy(), lab)
+    ref, ref_clr = oracle_mod.capsule_box_labels(oracle_dh(oracle_mod, arm), q.astype(np.float64), arm.radius, lo,
+                                                 hi)
+    near = np.abs(ref_clr) < 1e-9
+    np.testing.assert_array_equal(lab[~near], ref[~near])
+    assert np.abs(clr - ref_clr).max() <= 1e-6
+    if case == "enclosing_box":
+        assert np.all(lab == 1) and np.all(clr < 0)
+    print(dict(case=case, collision_rate=float(np.mean(ref == 1)), near_boundary=int(near.sum())))
