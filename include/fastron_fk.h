@@ -27,7 +27,12 @@
  *     negative fastron_status; fastron_last_error() then returns a message
  *     (thread-local, valid until the next call on the same thread). Nothing
  *     aborts or throws across the ABI.
- *   - Limits: 1 <= n <= 16 joints, 1 <= M <= 16 control points.
+ *   - Limits: 1 <= n <= 16 joints, 1 <= M <= 16 control points. One call
+ *     takes at most 2^32 - 256 configurations or rows (2^31 - 128 queries
+ *     for the FK-kernel score entry points), since a launch spans at most
+ *     2^32 - 1 work-items per grid dimension; more go in several calls
+ *     (FASTRON_EINVAL otherwise). Offsets into every array are 64-bit, so
+ *     arrays past 2^31 elements are addressed correctly.
  */
 #ifndef FASTRON_FK_H
 #define FASTRON_FK_H

@@ -58,7 +58,7 @@ extern "C" fastron_status fastron_active_samples(const float* support_q, const f
   if (rows == 0) return FASTRON_OK;
   FASTRON_CHECK(X_out != nullptr, "X_out is NULL");
   const int64_t blocks = (rows + 255) / 256;
-  FASTRON_CHECK(blocks <= INT32_MAX, "too many rows");
+  FASTRON_CHECK(grid_fits(blocks, 256), "%lld rows above one launch's 2^32 - 256", (long long)rows);
   hipLaunchKernelGGL(k_active_samples, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), support_q, alpha, S,
                      (int)n, noise, (int)k, explore, E, X_out, alpha_out);
   FASTRON_HIP(hipGetLastError());
@@ -71,7 +71,7 @@ extern "C" fastron_status fastron_active_relabel(const int8_t* y, int64_t S, flo
   if (S == 0) return FASTRON_OK;
   FASTRON_CHECK(y && alpha, "y and alpha must be non-NULL");
   const int64_t blocks = (S + 255) / 256;
-  FASTRON_CHECK(blocks <= INT32_MAX, "S too large");
+  FASTRON_CHECK(grid_fits(blocks, 256), "S = %lld above one launch's 2^32 - 256", (long long)S);
   hipLaunchKernelGGL(k_active_relabel, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), y, S, alpha);
   FASTRON_HIP(hipGetLastError());
   return FASTRON_OK;

@@ -83,6 +83,11 @@ inline hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s);
 // Device pointer sanity (host check only: non-null and aligned).
 inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
+// A dispatch spans at most 2^32 - 1 work-items per grid dimension (the
+// dispatch packet holds the grid size in 32 bits): `blocks` workgroups of
+// `threads` work-items fit if their product does.
+inline bool grid_fits(int64_t blocks, int threads) { return blocks >= 0 && blocks <= (int64_t)UINT32_MAX / threads; }
+
 // ---------------------------------------------------------------------------
 // Device-side forward kinematics (Section II-A, Eq. 1 and Eq. 2).
 //

@@ -559,7 +559,7 @@ fastron_status fastron_fk_points(const fastron_chain* chain, const fastron_cpoin
   FASTRON_CHECK(q && P, "q and P must be non-NULL");
   FASTRON_CHECK(aligned(q, 4) && aligned(P, 4), "q and P must be 4-byte aligned");
   const int64_t blocks = (N + 255) / 256;
-  FASTRON_CHECK(blocks <= INT32_MAX, "N too large");
+  FASTRON_CHECK(grid_fits(blocks, 256), "N = %lld above one launch's 2^32 - 256 configurations", (long long)N);
   const size_t lds = (size_t)256 * (c.n + 3 * c.M) * sizeof(float);
   const dim3 grid((unsigned)blocks);
   hipStream_t s = as_stream(stream);

@@ -139,7 +139,7 @@ extern "C" fastron_status fastron_label_capsule_box(const fastron_chain* chain, 
   FASTRON_CHECK(q && label, "q and label must be non-NULL");
   FASTRON_CHECK(nbox == 0 || boxes != nullptr, "boxes is NULL");
   const int64_t blocks = (N + 255) / 256;
-  FASTRON_CHECK(blocks <= INT32_MAX, "N too large");
+  FASTRON_CHECK(grid_fits(blocks, 256), "N = %lld above one launch's 2^32 - 256 configurations", (long long)N);
   hipLaunchKernelGGL(k_label, dim3((unsigned)blocks), dim3(256), 0, as_stream(stream), c, q, N, radius, boxes, nbox,
                      label, clearance);
   FASTRON_HIP(hipGetLastError());

@@ -172,7 +172,7 @@ fastron_status fastron_rbf_score(const float* support_x, const float* alpha, int
   if (N == 0) return FASTRON_OK;
   hipStream_t s = as_stream(stream);
   const int64_t qblocks = (N + 255) / 256;
-  FASTRON_CHECK(qblocks <= INT32_MAX, "N too large");
+  FASTRON_CHECK(grid_fits(qblocks, 256), "N = %lld above one launch's 2^32 - 256 queries", (long long)N);
   if (S == 0) {
     hipLaunchKernelGGL(k_rbf_empty, dim3((unsigned)qblocks), dim3(256), 0, s, N, f, label);
     FASTRON_HIP(hipGetLastError());

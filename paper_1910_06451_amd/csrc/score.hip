@@ -156,7 +156,9 @@ fastron_status score_launch(const ChainArgs& c, const fastron_model* model, cons
   const int64_t nt = ntiles_of(model->S);
   const int Mp = mp_of(c.M);
   const int64_t blocks = (N + 64 * kWavesPerBlock - 1) / (64 * kWavesPerBlock);
-  FASTRON_CHECK((N + kScoreQueriesPerBlock - 1) / kScoreQueriesPerBlock <= INT32_MAX, "N too large");
+  // the MFMA form's grid is the largest: two work-items per query
+  FASTRON_CHECK(grid_fits((N + kScoreQueriesPerBlock - 1) / kScoreQueriesPerBlock, 256),
+                "N = %lld above one launch's 2^31 - 128 queries", (long long)N);
   const char* blob = static_cast<const char*>(model->data);
   if (c.Mm == 0) {
     hipLaunchKernelGGL(k_score_const, dim3((unsigned)((N + 255) / 256)), dim3(256), 0, s, blob, N, f, label);
@@ -188,6 +190,8 @@ static fastron_status check_score_args(const ChainArgs& c, const fastron_model* 
   FASTRON_CHECK(std::isfinite(model->gamma) && model->gamma > 0.f, "model->gamma must be finite and > 0");
   FASTRON_CHECK(N >= 0, "N = %lld < 0", (long long)N);
   FASTRON_CHECK(N == 0 || q != nullptr, "q is NULL");
+  FASTRON_CHECK(fastron::grid_fits((N + fastron::kScoreQueriesPerBlock - 1) / fastron::kScoreQueriesPerBlock, 256),
+                "N = %lld above one launch's 2^31 - 128 queries", (long long)N);
   FASTRON_CHECK(N == 0 || f != nullptr || label != nullptr, "f and label are both NULL");
   FASTRON_CHECK((flags & ~0x33u) == 0 && (flags & 3u) != 3u, "unknown flags 0x%x", flags);
   FASTRON_CHECK(((flags >> 4) & 3u) <= 2u, "unknown BF16 variant");

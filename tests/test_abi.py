@@ -157,6 +157,19 @@ def test_validation_before_device_work(lib):
     assert lib.fastron_active_samples(fake, fake, 10, 7, fake, 2, None, 5, fake, None, None) == nat.FASTRON_EINVAL
     assert lib.fastron_active_samples(fake, fake, 10, 7, fake, 2, fake, 5, None, None, None) == nat.FASTRON_EINVAL
     assert lib.fastron_active_samples(fake, fake, -1, 7, fake, 2, fake, 5, fake, None, None) == nat.FASTRON_EINVAL
+    # one launch spans at most 2^32 - 1 work-items per grid dimension: 2^32 - 256 configurations (256 per
+    # workgroup of 256), 2^31 - 128 queries for the FK-kernel score (128 per workgroup of 256)
+    big = 2 ** 32 - 255
+    assert lib.fastron_fk_points(ch, cp, fake, big, fake, None) == nat.FASTRON_EINVAL
+    assert "2^32 - 256" in nat.last_error()
+    assert lib.fastron_label_capsule_box(ch, fake, big, 0.04, fake, 1, fake, None, None) == nat.FASTRON_EINVAL
+    assert lib.fastron_rbf_score(fake, fake, 10, 7, 1.0, fake, big, fake, None, None) == nat.FASTRON_EINVAL
+    model = nat.Model(100, hc.cpoints.M, 10.0, fake, lib.fastron_model_bytes(100, hc.cpoints.M))
+    assert lib.fastron_fk_score_prepared(ch, cp, ctypes.byref(model), fake, 2 ** 31 - 127, fake, None, 0,
+                                         None) == nat.FASTRON_EINVAL
+    assert "2^31 - 128" in nat.last_error()
+    assert lib.fastron_fk_score(ch, cp, fake, fake, 100, 10.0, fake, 2 ** 31 - 127, fake, None, 0,
+                                None) == nat.FASTRON_EINVAL
 
 
 def _frames_lib(lib, a, d, types, include_base):
