@@ -310,3 +310,49 @@ def test_label_binding_rejects_inverted_boxes():
     # well-formed boxes pass the check and reach the device-tensor check
     with pytest.raises(ValueError, match="device tensor"):
         api.label_capsule_box(arm, q, arm.radius, lo[:1], hi[:1])
+
+
+def test_product_path_is_independent_of_the_oracle():
+    """The package neither imports the oracle nor includes its sources; with the HIP library missing the binding
+    raises, and the entry points refuse host tensors: nothing is computed on the host."""
+    import ast
+    import pathlib
+    import subprocess
+    import sys
+    pkg = pathlib.Path(nat.__file__).resolve().parent
+    for py in pkg.rglob("*.py"):
+        for node in ast.walk(ast.parse(py.read_text())):
+            names = [a.name for a in node.names] if isinstance(node, ast.Import) else \
+                [node.module or ""] if isinstance(node, ast.ImportFrom) else []
+            assert not any(n.split(".")[0] == "oracle" for n in names), py
+    for src in list(pkg.rglob("*.hip")) + list(pkg.rglob("*.h")):
+        for line in src.read_text().splitlines():
+            assert not (line.lstrip().startswith("#include") and "oracle" in line), (src, line)
+    code = (
+        "import torch\n"
+        "from paper_1910_06451_amd import _native as nat, api, workloads as wl\n"
+        "nat.LIB_PATH = '/nonexistent/libfastron_fk.so'\n"
+        "arm = wl.arm_3dof()\n"
+        "q = torch.zeros(4, arm.n)\n"
+        "calls = [lambda: api.fk_points(arm, q), lambda: api.fk_score(arm, q, torch.ones(4), 10.0, q),\n"
+        "         lambda: api.label_capsule_box(arm, q, 0.04, [[0, 0, 0]], [[1, 1, 1]])]\n"
+        "try:\n"
+        "    nat.lib()\n"
+        "    raise SystemExit('the binding loaded a library that is not there')\n"
+        "except nat.FastronLibraryMissing:\n"
+        "    pass\n"
+        "for c in calls:\n"
+        "    try:\n"
+        "        c()\n"
+        "    except nat.FastronLibraryMissing:\n"
+        "        continue\n"
+        "    except ValueError as e:\n"
+        "        if 'device tensor' in str(e):  # host tensors are refused before the library is looked up\n"
+        "            continue\n"
+        "        raise SystemExit(f'unexpected ValueError: {e}')\n"
+        "    raise SystemExit('an entry point ran without the HIP library')\n"
+        "import sys\n"
+        "assert 'oracle' not in sys.modules\n"
+        "print('ok')\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=pkg.parent, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
