@@ -73,28 +73,34 @@ def test_fk_points_and_gram_column_past_2g(oracle_mod, dev):
 
 def test_score_past_2g(oracle_mod, dev):
     """310,000,000 queries of the 7-DOF arm in one launch: 2.17e9 joint values, query 306,783,379 onwards past
-    2^31; S = 64 supports (four tiles), gamma = 10."""
+    2^31; S = 64 supports (four tiles), gamma = 10; the FP32 form and the BF16 SPLIT3 form (FP32 bound)."""
     arm = wl.arm_7dof()
     N, S, gamma = 310_000_000, 64, 10.0
     sq, al = wl.model("large/score", S, arm.n)
     base, q = _repeated("large/score/q", N, arm.n, dev)
     first_past = -(-(2 ** 31) // arm.n)
     assert N * arm.n > 2 ** 31 - 1 and first_past < N
-    announce(f"fk_score 7dof S={S} N={N}")
-    f, lab = api.fk_score(arm, torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev), gamma, q)
-    torch.cuda.synchronize()
-    del q
+    sq_d, al_d = torch.from_numpy(sq).to(dev), torch.from_numpy(al).to(dev)
     idx = _sample("large/score", N, first_past)
     ti, to = torch.from_numpy(idx).to(dev), torch.from_numpy(idx % R).to(dev)
-    fg, lg = f[ti].cpu().numpy(), lab[ti].cpu().numpy()
-    np.testing.assert_array_equal(fg, f[to].cpu().numpy())
-    np.testing.assert_array_equal(lg, lab[to].cpu().numpy())
     dh = oracle_dh(oracle_mod, arm)
     qs = base[idx % R].astype(np.float64)
     ref = oracle_mod.score(dh, arm.frames, sq.astype(np.float64), al.astype(np.float64), gamma, qs)
-    Ps = oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64))
-    Pq = oracle_mod.control_points(dh, arm.frames, qs)
-    stats = check_scores(fg, lg, ref, error_bound(Ps, al, gamma, Pq), min_agree=0.99)
-    print(stats)
-    del f, lab
+    tol = error_bound(oracle_mod.control_points(dh, arm.frames, sq.astype(np.float64)), al, gamma,
+                      oracle_mod.control_points(dh, arm.frames, qs))
+    for name in ("fp32", "bf16 split3"):
+        announce(f"fk_score 7dof {name} S={S} N={N}")
+        if name == "fp32":
+            f, lab = api.fk_score(arm, sq_d, al_d, gamma, q)
+        else:
+            model = api.support_prep(arm, sq_d, al_d, gamma)
+            f, lab = api.fk_score_prepared(arm, model, q, flags=api.SCORE_BF16 | api.BF16_SPLIT3)
+        torch.cuda.synchronize()
+        fg, lg = f[ti].cpu().numpy(), lab[ti].cpu().numpy()
+        np.testing.assert_array_equal(fg, f[to].cpu().numpy())
+        np.testing.assert_array_equal(lg, lab[to].cpu().numpy())
+        stats = check_scores(fg, lg, ref, tol, min_agree=0.99)
+        print(name, stats)
+        del f, lab
+    del q
     torch.cuda.empty_cache()
