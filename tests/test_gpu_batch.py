@@ -103,6 +103,25 @@ def test_batch_autotune_and_graph_replay(dev):
         side.synchronize()
         assert torch.equal(f_g, expect_f), rep
         assert torch.equal(l_g, expect_l), rep
+    # a new launch shape rebuilds the work items and drops the captured graph (which holds the old kernel and
+    # item count): replay refuses until the caller captures again, and the new capture replays exactly
+    cur = b.shape["queries_per_item"]
+    b.set_shape(*((16, 4, 0, 100) if cur != 16 else (32, 8, 0, 75)))
+    assert b.shape["queries_per_item"] != cur
+    with pytest.raises(api.nat.FastronError, match="no captured graph"):
+        b.replay()
+    announce("batch graph recapture after a new shape")
+    with torch.cuda.stream(side):
+        b.capture(q_g, (f_g, l_g))
+    torch.cuda.synchronize()
+    q_g.copy_(q2)
+    expect_f, expect_l = b.score(q2)
+    expect_f, expect_l = expect_f.clone(), expect_l.clone()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        b.replay()
+    side.synchronize()
+    assert torch.equal(f_g, expect_f) and torch.equal(l_g, expect_l)
     b.close()
 
 
